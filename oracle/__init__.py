@@ -1,0 +1,155 @@
+"""ctypes binding of the FP64 CPU oracle (``lagp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use it; the GPU library never does.  It shares no code with the GPU
+path.  See ``lagp_oracle.c`` for the method and the readings of the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "lagp_oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+STATUS = {0: "ok", 1: "init not PD", 2: "step failure", 3: "non-finite", 4: "bad forced", 5: "bad args"}
+
+CFLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def compile_c(src: str, out: str) -> str:
+    subprocess.run(["gcc", *CFLAGS, src, "-o", out + ".tmp", "-lm"], check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        compile_c(SRC, LIB)
+    return LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Oracle:
+    """One loaded copy of the oracle library."""
+
+    def __init__(self, path: str):
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.orc_nn_pool.argtypes = [P, i64, i32, P, i64, i32, P, i32]
+        L.orc_nn_pool.restype = i32
+        L.orc_gp_predict.argtypes = [P, P, i32, i32, P, f64, f64, P]
+        L.orc_gp_predict.restype = i32
+        L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, f64,
+                              P, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_alc.restype = i32
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = i32
+        self.L = L
+
+    def nn_pool(self, X, XX, Np: int, threads: int = 0) -> np.ndarray:
+        """M x Np int32: the Np nearest design rows of each location, sorted by (sq. distance, index)."""
+        X, XX = _f64(X), _f64(np.atleast_2d(XX))
+        M = XX.shape[0]
+        pool = np.empty((M, Np), dtype=np.int32)
+        rc = self.L.orc_nn_pool(_p(X), X.shape[0], X.shape[1], _p(XX), M, Np, _p(pool), threads)
+        if rc:
+            raise ValueError(f"orc_nn_pool: {STATUS.get(rc, rc)}")
+        return pool
+
+    def gp_predict(self, D, Yd, x, d: float, g: float) -> dict:
+        """Textbook GP prediction on a fixed design (eqs. predgp, preds2)."""
+        D, Yd, x = _f64(np.atleast_2d(D)), _f64(Yd), _f64(x)
+        out = np.empty(5)
+        rc = self.L.orc_gp_predict(_p(D), _p(Yd), D.shape[0], D.shape[1], _p(x), d, g, _p(out))
+        return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
+
+    def alc(self, X, Y, XX, pool, n0: int, n: int, d: float, g: float, *, Np: int | None = None,
+            n_per=None, Np_per=None, forced=None, mode_b: bool = False, threads: int = 0) -> dict:
+        """Greedy ALC local designs and local predictions for every location.
+
+        Returns arrays: sel, dsel, dmax, amax, dsecond, nu (M x nmax), vtraj
+        (M x (nmax + 1)), mean, s2, var, v, psi (M), status (M).
+        """
+        X, Y, XX = _f64(X), _f64(Y), _f64(np.atleast_2d(XX))
+        pool = _i32(np.atleast_2d(pool))
+        M, Np_stride = pool.shape
+        Np = Np_stride if Np is None else Np
+        n_per, Np_per = _i32(n_per), _i32(Np_per)
+        nmax = int(n_per.max()) if n_per is not None and len(n_per) else n
+        forced = None if forced is None else _i32(np.atleast_2d(forced))
+        if forced is not None:
+            nmax = max(nmax, forced.shape[1])
+            assert forced.shape == (M, nmax)
+        sel = np.full((M, nmax), -1, np.int32)
+        amax = np.full((M, nmax), -1, np.int32)
+        dsel, dmax, dsecond, nu = (np.full((M, nmax), np.nan) for _ in range(4))
+        vtraj = np.full((M, nmax + 1), np.nan)
+        pred = np.full((M, 5), np.nan)
+        status = np.zeros(M, np.int32)
+        rc = self.L.orc_alc(_p(X), _p(Y), X.shape[0], X.shape[1], _p(XX), M, _p(pool), Np_stride,
+                            _p(Np_per), Np, _p(n_per), n, nmax, n0, d, g, _p(forced), int(mode_b),
+                            threads, _p(sel), _p(dsel), _p(dmax), _p(amax), _p(dsecond), _p(nu),
+                            _p(vtraj), _p(pred), _p(status))
+        if rc:
+            raise ValueError(f"orc_alc: {STATUS.get(rc, rc)}")
+        return dict(sel=sel, dsel=dsel, dmax=dmax, amax=amax, dsecond=dsecond, nu=nu,
+                    vtraj=vtraj, mean=pred[:, 0], s2=pred[:, 1], var=pred[:, 2], v=pred[:, 3],
+                    psi=pred[:, 4], status=status)
+
+    def lagp(self, X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, **kw) -> dict:
+        """Nearest-neighbour pool, greedy ALC design and prediction for every location."""
+        pool = self.nn_pool(X, XX, Np, threads=kw.get("threads", 0))
+        out = self.alc(X, Y, XX, pool, n0, n, d, g, **kw)
+        out["pool"] = pool
+        return out
+
+    def max_threads(self) -> int:
+        return self.L.orc_max_threads()
+
+
+_default: Oracle | None = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(build())
+    return _default
+
+
+def nn_pool(*a, **k):
+    return default().nn_pool(*a, **k)
+
+
+def gp_predict(*a, **k):
+    return default().gp_predict(*a, **k)
+
+
+def alc(*a, **k):
+    return default().alc(*a, **k)
+
+
+def lagp(*a, **k):
+    return default().lagp(*a, **k)
+
+
+def max_threads() -> int:
+    return default().max_threads()

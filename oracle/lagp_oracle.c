@@ -1,0 +1,522 @@
+/*
+ * Plain FP64 CPU oracle for local approximate GP regression with greedy
+ * ALC (active learning Cohn) local designs.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path calls, links or
+ * loads this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code with the GPU library.
+ *
+ * Method (Gramacy, Niemi & Weiss, "Massively parallel approximate Gaussian
+ * process regression", arXiv:1310.5182):
+ *   - Sec. 2.1: isotropic Gaussian correlation K(x,x') = exp(-||x-x'||^2/d),
+ *     nugget g on the diagonal of the design covariance only; predictive
+ *     mean (eq. predgp) mu = k^T K^{-1} Y, scale (eq. preds2)
+ *     s2 = psi [K(x,x) - k^T K^{-1} k] / n with psi = Y^T K^{-1} Y,
+ *     variance V = s2 n / (n - 2).
+ *   - Sec. 2.2 / Fig. 1: local design for each predictive location x:
+ *     nearest-neighbour start X_{n0}(x), then for j = n0..n-1 add the
+ *     candidate that maximises the reduction in predictive variance
+ *     v_j(x) - v_{j+1}(x) (eqs. newv and dxy).
+ *   - Sec. 3.1: candidates restricted to the N' nearest neighbours of x.
+ *
+ * Mode A (the plain definition) recomputes a Cholesky factor L_j of K_j at
+ * every step.  For a candidate c with k_c = K(X_j, c), z_c = L_j^{-1} k_c and
+ * z_h = L_j^{-1} K(X_j, x), the conditional (given D_j) variance of c is
+ * s_c = kappa - z_c.z_c and its conditional covariance with x is
+ * cov_c = K(c, x) - z_c.z_h; adding c reduces the variance at x by exactly
+ * cov_c^2 / s_c (the textbook rank-one conditioning identity), which is the
+ * quantity v_j(x) - v_{j+1}(x) of eq. dxy.
+ *
+ * Mode B (optional, for route noise) is the paper's own route: K_j^{-1}
+ * carried by the partitioned-inverse update (eq. piedef) and the score
+ * evaluated term by term as printed in eq. dxy.
+ *
+ * Readings of the paper taken here:
+ *   - kappa = K(x',x') = 1 + g for candidates and for the predictive location
+ *     (Fig. 3 step 5 uses 1 + eta); cross-covariances carry no nugget.
+ *   - the score is the unnormalised reduction (Sec. 3.1, last paragraph:
+ *     normalisation does not change the argmax).
+ *   - candidates at step j are the pool minus X_j; X_{n0} is the first n0
+ *     pool entries, the pool sorted by (squared distance, design index).
+ *   - exact ties in the score go to the smallest design index.
+ *   - a candidate whose computed conditional variance s_c is not positive is
+ *     numerically a duplicate of the design and is never selected.
+ *
+ * Squared distances are summed left to right over coordinates; the file is
+ * compiled with -ffp-contract=off so no multiply-add is fused.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_INIT_NOT_PD = 1,   /* K_{n0} not positive definite                 */
+    ORC_STEP_FAIL = 2,     /* K_j not positive definite / no valid choice  */
+    ORC_NONFINITE = 3,     /* non-finite input                             */
+    ORC_BAD_FORCED = 4,    /* forced sequence not a valid pool sequence    */
+    ORC_BAD_ARGS = 5,
+};
+
+/* ||a - b||^2, summed left to right (no contraction). */
+static double sqdist(const double *a, const double *b, int p)
+{
+    double s = 0.0;
+    for (int k = 0; k < p; k++) {
+        double t = a[k] - b[k];
+        s = s + t * t;
+    }
+    return s;
+}
+
+/* Isotropic Gaussian correlation, Sec. 2.1. */
+static double kern(const double *a, const double *b, int p, double d)
+{
+    return exp(-sqdist(a, b, p) / d);
+}
+
+/* ------------------------------------------------------------------ */
+/* Nearest-neighbour pool (Sec. 2.2 NN sub-design; Sec. 3.1 N' NNs).    */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double key;
+    int32_t idx;
+} keyed;
+
+static int cmp_keyed(const void *pa, const void *pb)
+{
+    const keyed *a = (const keyed *)pa, *b = (const keyed *)pb;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+/* Pool of the Np nearest rows of X (N x p) to each row of XX (M x p),
+ * sorted by (squared distance, index).  pool is M x Np. */
+int orc_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M,
+                int Np, int32_t *pool, int nthreads)
+{
+    if (Np < 1 || Np > N || p < 1) return ORC_BAD_ARGS;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int bad = 0;
+#pragma omp parallel
+    {
+        keyed *buf = (keyed *)malloc(sizeof(keyed) * (size_t)N);
+        if (!buf) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t m = 0; m < M; m++) {
+                const double *x = XX + m * p;
+                for (int64_t i = 0; i < N; i++) {
+                    buf[i].key = sqdist(X + i * p, x, p);
+                    buf[i].idx = (int32_t)i;
+                }
+                qsort(buf, (size_t)N, sizeof(keyed), cmp_keyed);
+                for (int r = 0; r < Np; r++) pool[m * Np + r] = buf[r].idx;
+            }
+            free(buf);
+        }
+    }
+    return bad ? ORC_BAD_ARGS : ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dense linear algebra (plain, unblocked).                             */
+/* ------------------------------------------------------------------ */
+
+/* Lower Cholesky factor of the j x j SPD matrix A (row-major) into L.
+ * Returns 0 on success, 1 if a pivot is not positive. */
+static int cholesky(const double *A, double *L, int j)
+{
+    memset(L, 0, sizeof(double) * (size_t)j * j);
+    for (int r = 0; r < j; r++) {
+        for (int c = 0; c <= r; c++) {
+            double s = A[r * j + c];
+            for (int k = 0; k < c; k++) s -= L[r * j + k] * L[c * j + k];
+            if (r == c) {
+                if (!(s > 0.0)) return 1;
+                L[r * j + r] = sqrt(s);
+            } else {
+                L[r * j + c] = s / L[c * j + c];
+            }
+        }
+    }
+    return 0;
+}
+
+/* Solve L z = b (L lower triangular, j x j). */
+static void forward_solve(const double *L, const double *b, double *z, int j)
+{
+    for (int r = 0; r < j; r++) {
+        double s = b[r];
+        for (int k = 0; k < r; k++) s -= L[r * j + k] * z[k];
+        z[r] = s / L[r * j + r];
+    }
+}
+
+/* Solve L^T z = b. */
+static void backward_solve_t(const double *L, const double *b, double *z, int j)
+{
+    for (int r = j - 1; r >= 0; r--) {
+        double s = b[r];
+        for (int k = r + 1; k < j; k++) s -= L[k * j + r] * z[k];
+        z[r] = s / L[r * j + r];
+    }
+}
+
+static double dot(const double *a, const double *b, int j)
+{
+    double s = 0.0;
+    for (int k = 0; k < j; k++) s += a[k] * b[k];
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* GP prediction from a fixed design (eqs. predgp and preds2).          */
+/* ------------------------------------------------------------------ */
+
+/* Design rows D (n x p, row-major), responses Yd (n), location x.
+ * out[0] = mean, out[1] = s2 (Student-t scale, df n), out[2] = V = s2 n/(n-2)
+ * (NaN if n <= 2), out[3] = v = kappa - k^T K^{-1} k, out[4] = psi.
+ * Returns 0, or 1 if K is not positive definite. */
+int orc_gp_predict(const double *D, const double *Yd, int n, int p, const double *x,
+                   double d, double g, double *out)
+{
+    double kappa = 1.0 + g;
+    double *K = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *L = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *h = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *alpha = (double *)malloc(sizeof(double) * (size_t)n);
+    double *zh = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 0;
+    for (int a = 0; a < n; a++) {
+        for (int b = 0; b < n; b++) K[a * n + b] = kern(D + a * p, D + b * p, p, d);
+        K[a * n + a] += g;
+        h[a] = kern(D + a * p, x, p, d);
+    }
+    if (cholesky(K, L, n)) {
+        rc = 1;
+        for (int q = 0; q < 5; q++) out[q] = NAN;
+    } else {
+        forward_solve(L, Yd, w, n);
+        backward_solve_t(L, w, alpha, n);
+        forward_solve(L, h, zh, n);
+        double mu = dot(h, alpha, n);
+        double psi = dot(Yd, alpha, n);
+        double v = kappa - dot(zh, zh, n);
+        double s2 = psi * v / n;
+        out[0] = mu;
+        out[1] = s2;
+        out[2] = n > 2 ? s2 * n / (n - 2) : NAN;
+        out[3] = v;
+        out[4] = psi;
+    }
+    free(K); free(L); free(h); free(w); free(alpha); free(zh);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Greedy ALC local design for one location (Fig. 1 steps 2a, 2b, 5).   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    /* per step j = 0..n-1 (entries j < n0 describe the NN start) */
+    int32_t *sel;     /* design index added at step j                        */
+    double *dsel;     /* mode-A score of that choice (NaN for j < n0)        */
+    double *dmax;     /* best mode-A score at step j (NaN for j < n0)        */
+    int32_t *amax;    /* its design index (-1 for j < n0)                    */
+    double *dsecond;  /* runner-up score (NaN if none)                       */
+    double *nu;       /* route noise max|dA - dB| / dmax (NaN if mode B off) */
+    double *vtraj;    /* v_j(x) before step j, and v_n at index n (n + 1)   */
+    double pred[5];   /* mean, s2, V, v, psi on the final design             */
+} orc_trace;
+
+typedef struct {
+    double *K, *L, *h, *zh, *kc, *zc, *Kinv, *Kinv2, *u, *gv, *Dn, *Yn;
+    uint8_t *chosen;
+} orc_work;
+
+static int work_alloc(orc_work *w, int n, int Np, int p)
+{
+    size_t nn = (size_t)n * n;
+    w->K = (double *)malloc(sizeof(double) * nn);
+    w->L = (double *)malloc(sizeof(double) * nn);
+    w->Kinv = (double *)malloc(sizeof(double) * nn);
+    w->Kinv2 = (double *)malloc(sizeof(double) * nn);
+    w->h = (double *)malloc(sizeof(double) * n);
+    w->zh = (double *)malloc(sizeof(double) * n);
+    w->kc = (double *)malloc(sizeof(double) * n);
+    w->zc = (double *)malloc(sizeof(double) * n);
+    w->u = (double *)malloc(sizeof(double) * n);
+    w->gv = (double *)malloc(sizeof(double) * n);
+    w->Dn = (double *)malloc(sizeof(double) * (size_t)n * p);
+    w->Yn = (double *)malloc(sizeof(double) * n);
+    w->chosen = (uint8_t *)malloc((size_t)Np);
+    return w->K && w->L && w->Kinv && w->Kinv2 && w->h && w->zh && w->kc && w->zc && w->u &&
+           w->gv && w->Dn && w->Yn && w->chosen;
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->K); free(w->L); free(w->Kinv); free(w->Kinv2); free(w->h); free(w->zh);
+    free(w->kc); free(w->zc); free(w->u); free(w->gv); free(w->Dn); free(w->Yn);
+    free(w->chosen);
+}
+
+/* Mode B: grow K^{-1} (j x j, row-major, stride j) to (j+1) x (j+1) with the
+ * partitioned inverse (eq. piedef): for the new point with k' = K(X_j, x')
+ * and kappa, u = K^{-1} k', m^{-1} = kappa - k'.u, g = -m u and
+ * K_{j+1}^{-1} = [[K^{-1} + g g^T m^{-1}, g], [g^T, m]]. */
+static int piedef_grow(const double *Kinv, double *Kout, const double *kp, double kappa,
+                       double *u, double *gv, int j)
+{
+    for (int a = 0; a < j; a++) u[a] = dot(Kinv + a * j, kp, j);
+    double minv = kappa - dot(kp, u, j);
+    if (!(minv > 0.0)) return 1;
+    double m = 1.0 / minv;
+    for (int a = 0; a < j; a++) gv[a] = -m * u[a];
+    int J = j + 1;
+    for (int a = 0; a < j; a++) {
+        for (int b = 0; b < j; b++) Kout[a * J + b] = Kinv[a * j + b] + gv[a] * gv[b] * minv;
+        Kout[a * J + j] = gv[a];
+        Kout[j * J + a] = gv[a];
+    }
+    Kout[j * J + j] = m;
+    return 0;
+}
+
+/* Mode B score, eq. dxy term by term:
+ *   h^T G m^{-1} h + 2 h^T g K(x',x) + K(x',x)^2 m,  G = g g^T. */
+static double dxy_score(const double *Kinv, const double *kc, const double *h, double kcx,
+                        double kappa, double *u, double *gv, int j)
+{
+    for (int a = 0; a < j; a++) u[a] = dot(Kinv + a * j, kc, j);
+    double minv = kappa - dot(kc, u, j);
+    if (!(minv > 0.0)) return -INFINITY;
+    double m = 1.0 / minv;
+    for (int a = 0; a < j; a++) gv[a] = -m * u[a];
+    double hg = dot(h, gv, j);
+    return hg * hg * minv + 2.0 * hg * kcx + kcx * kcx * m;
+}
+
+/*
+ * One location.  X (N x p), Y (N); x (p); pool (Np sorted design indices).
+ * forced: NULL for the oracle's own greedy choices, else n design indices to
+ * add in that order (the scores of every candidate are still evaluated).
+ * Returns a status code; the trace is filled as far as it got.
+ */
+static int alc_one(const double *X, const double *Y, int p, const double *x,
+                   const int32_t *pool, int Np, int n0, int n, double d, double g,
+                   const int32_t *forced, int mode_b, orc_trace *tr, orc_work *w)
+{
+    const double kappa = 1.0 + g;
+    for (int k = 0; k < p; k++)
+        if (!isfinite(x[k])) return ORC_NONFINITE;
+    memset(w->chosen, 0, (size_t)Np);
+    for (int q = 0; q < 5; q++) tr->pred[q] = NAN;
+    int32_t *slot_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)n); /* pool slot of X_j rows */
+    int rc = ORC_OK;
+
+    for (int j = 0; j < n; j++) {
+        tr->dsel[j] = tr->dmax[j] = tr->dsecond[j] = tr->nu[j] = tr->vtraj[j] = NAN;
+        tr->amax[j] = -1;
+        tr->sel[j] = -1;
+    }
+    tr->vtraj[n] = NAN;
+
+    /* mode B state */
+    double *Kinv = w->Kinv, *Kinv2 = w->Kinv2;
+
+    for (int j = 0; j < n; j++) {
+        /* Design covariance K_j and its Cholesky factor (mode A). */
+        if (j > 0) {
+            for (int a = 0; a < j; a++) {
+                const double *xa = X + (int64_t)pool[slot_of[a]] * p;
+                for (int b = 0; b < j; b++)
+                    w->K[a * j + b] = kern(xa, X + (int64_t)pool[slot_of[b]] * p, p, d);
+                w->K[a * j + a] += g;
+                w->h[a] = kern(xa, x, p, d);
+            }
+            if (cholesky(w->K, w->L, j)) { rc = j <= n0 ? ORC_INIT_NOT_PD : ORC_STEP_FAIL; break; }
+            forward_solve(w->L, w->h, w->zh, j);
+        }
+        double vj = kappa - (j > 0 ? dot(w->zh, w->zh, j) : 0.0);
+        tr->vtraj[j] = vj;
+
+        int take_slot = -1;
+        if (j < n0) {
+            /* NN start X_{n0}: pool entries in order (Fig. 1 step 2a). */
+            if (forced) {
+                for (int s = 0; s < Np; s++)
+                    if (pool[s] == forced[j]) { take_slot = s; break; }
+                if (take_slot < 0 || w->chosen[take_slot]) { rc = ORC_BAD_FORCED; break; }
+            } else {
+                take_slot = j;
+            }
+        } else {
+            /* Score every remaining candidate (Fig. 1 step 2b). */
+            double best = -INFINITY, second = -INFINITY, maxdiff = 0.0;
+            int best_slot = -1;
+            double forced_score = NAN;
+            int forced_slot = -1;
+            for (int s = 0; s < Np; s++) {
+                if (w->chosen[s]) continue;
+                const double *xc = X + (int64_t)pool[s] * p;
+                for (int a = 0; a < j; a++)
+                    w->kc[a] = kern(X + (int64_t)pool[slot_of[a]] * p, xc, p, d);
+                forward_solve(w->L, w->kc, w->zc, j);
+                double sc = kappa - dot(w->zc, w->zc, j);
+                double kcx = kern(xc, x, p, d);
+                double cov = kcx - dot(w->zc, w->zh, j);
+                double delta = sc > 0.0 ? cov * cov / sc : -INFINITY;
+                if (mode_b) {
+                    double db = dxy_score(Kinv, w->kc, w->h, kcx, kappa, w->u, w->gv, j);
+                    if (isfinite(delta) && isfinite(db)) {
+                        double df = fabs(delta - db);
+                        if (df > maxdiff) maxdiff = df;
+                    }
+                }
+                if (forced && pool[s] == forced[j]) { forced_score = delta; forced_slot = s; }
+                int better = delta > best ||
+                             (delta == best && best_slot >= 0 && pool[s] < pool[best_slot]);
+                if (better) {
+                    if (best_slot >= 0 && best > second) second = best;
+                    best = delta;
+                    best_slot = s;
+                } else if (delta > second) {
+                    second = delta;
+                }
+            }
+            if (best_slot < 0 || !(best > -INFINITY)) { rc = ORC_STEP_FAIL; break; }
+            tr->dmax[j] = best;
+            tr->amax[j] = pool[best_slot];
+            tr->dsecond[j] = second > -INFINITY ? second : NAN;
+            tr->nu[j] = mode_b ? maxdiff / best : NAN;
+            if (forced) {
+                if (forced_slot < 0) { rc = ORC_BAD_FORCED; break; }
+                take_slot = forced_slot;
+                tr->dsel[j] = forced_score;
+            } else {
+                take_slot = best_slot;
+                tr->dsel[j] = best;
+            }
+        }
+
+        /* Mode B bookkeeping: grow K^{-1} by the partitioned inverse. */
+        if (mode_b) {
+            const double *xn = X + (int64_t)pool[take_slot] * p;
+            for (int a = 0; a < j; a++) w->kc[a] = kern(X + (int64_t)pool[slot_of[a]] * p, xn, p, d);
+            if (piedef_grow(Kinv, Kinv2, w->kc, kappa, w->u, w->gv, j)) mode_b = 0;
+            double *t = Kinv; Kinv = Kinv2; Kinv2 = t;
+        }
+
+        /* D_{j+1} = D_j U (x_{j+1}, y_{j+1}). */
+        w->chosen[take_slot] = 1;
+        slot_of[j] = take_slot;
+        tr->sel[j] = pool[take_slot];
+    }
+
+    if (rc == ORC_OK) {
+        /* Local prediction on the final design (Fig. 1 step 5). */
+        for (int a = 0; a < n; a++) {
+            memcpy(w->Dn + (size_t)a * p, X + (int64_t)tr->sel[a] * p, sizeof(double) * p);
+            w->Yn[a] = Y[tr->sel[a]];
+        }
+        if (orc_gp_predict(w->Dn, w->Yn, n, p, x, d, g, tr->pred)) rc = ORC_STEP_FAIL;
+        else tr->vtraj[n] = tr->pred[3];
+    }
+    free(slot_of);
+    return rc;
+}
+
+/*
+ * Batched driver over M locations (OpenMP over locations, Sec. 2.2 last
+ * paragraph: every location is independent).
+ *
+ * pool: M x Np_stride design indices (row m holds Np_m valid entries).
+ * n_per / Np_per: per-location sizes or NULL for the uniform n / Np.
+ * forced: NULL, or M x n_stride sequences to evaluate instead of choosing.
+ * Per-step outputs are M x n_stride (row m holds n_m entries); vtraj is
+ * M x (n_stride + 1); pred is M x 5.  Any per-step output may be NULL.
+ */
+int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX, int64_t M,
+            const int32_t *pool, int Np_stride, const int32_t *Np_per, int Np,
+            const int32_t *n_per, int n, int n_stride, int n0, double d, double g,
+            const int32_t *forced, int mode_b, int nthreads,
+            int32_t *sel, double *dsel, double *dmax, int32_t *amax, double *dsecond,
+            double *nu, double *vtraj, double *pred, int32_t *status)
+{
+    if (!(d > 0.0) || !(g > 0.0) || !isfinite(d) || !isfinite(g) || p < 1 || n0 < 1)
+        return ORC_BAD_ARGS;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        orc_work w;
+        int ok = work_alloc(&w, n_stride, Np_stride, p);
+        int32_t *t_sel = (int32_t *)malloc(sizeof(int32_t) * n_stride);
+        int32_t *t_amax = (int32_t *)malloc(sizeof(int32_t) * n_stride);
+        double *t_d = (double *)malloc(sizeof(double) * n_stride * 4);
+        double *t_v = (double *)malloc(sizeof(double) * (n_stride + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t m = 0; m < M; m++) {
+            int nm = n_per ? n_per[m] : n;
+            int Npm = Np_per ? Np_per[m] : Np;
+            orc_trace tr = {t_sel, t_d, t_d + n_stride, t_amax, t_d + 2 * n_stride,
+                            t_d + 3 * n_stride, t_v, {0}};
+            int rc;
+            if (!ok || nm > n_stride || Npm > Np_stride || nm > Npm || n0 > nm || Npm > N)
+                rc = ORC_BAD_ARGS;
+            else
+                rc = alc_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np_stride, Npm, n0, nm, d, g,
+                             forced ? forced + m * (int64_t)n_stride : NULL, mode_b, &tr, &w);
+            if (rc == ORC_BAD_ARGS) {
+                for (int j = 0; j < n_stride; j++) { t_sel[j] = -1; t_amax[j] = -1; }
+                for (int j = 0; j < 4 * n_stride; j++) t_d[j] = NAN;
+                for (int j = 0; j <= n_stride; j++) t_v[j] = NAN;
+                for (int q = 0; q < 5; q++) tr.pred[q] = NAN;
+                nm = n_stride;
+            }
+            if (rc != ORC_OK)
+                for (int q = 0; q < 5; q++) tr.pred[q] = NAN;
+            int64_t o = m * (int64_t)n_stride;
+            for (int j = 0; j < nm; j++) {
+                if (sel) sel[o + j] = t_sel[j];
+                if (dsel) dsel[o + j] = t_d[j];
+                if (dmax) dmax[o + j] = t_d[n_stride + j];
+                if (amax) amax[o + j] = t_amax[j];
+                if (dsecond) dsecond[o + j] = t_d[2 * n_stride + j];
+                if (nu) nu[o + j] = t_d[3 * n_stride + j];
+            }
+            if (vtraj)
+                for (int j = 0; j <= nm; j++) vtraj[m * (int64_t)(n_stride + 1) + j] = t_v[j];
+            if (pred)
+                for (int q = 0; q < 5; q++) pred[m * 5 + q] = tr.pred[q];
+            if (status) status[m] = rc;
+        }
+        if (ok) work_free(&w);
+        free(t_sel); free(t_amax); free(t_d); free(t_v);
+    }
+    return ORC_OK;
+}
+
+/* Threads OpenMP would use (for reporting). */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,74 @@
+"""NumPy brute force for tiny inputs: every quantity from its definition with
+fresh dense solves, no partitioned inverses, no Cholesky updates.
+
+Test infrastructure.  Used to pin the oracle (and nothing else).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def sqdist_rows(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Squared distances of the rows of A to b, summed left to right."""
+    s = np.zeros(A.shape[0])
+    for k in range(A.shape[1]):
+        t = A[:, k] - b[k]
+        s = s + t * t
+    return s
+
+
+def corr(A: np.ndarray, B: np.ndarray, d: float) -> np.ndarray:
+    """exp(-||a - b||^2 / d) for all row pairs (Sec. 2.1)."""
+    out = np.empty((A.shape[0], B.shape[0]))
+    for j in range(B.shape[0]):
+        out[:, j] = np.exp(-sqdist_rows(A, B[j]) / d)
+    return out
+
+
+def pool(X: np.ndarray, x: np.ndarray, Np: int) -> np.ndarray:
+    dist = sqdist_rows(X, x)
+    order = np.lexsort((np.arange(X.shape[0]), dist))
+    return order[:Np].astype(np.int32)
+
+
+def v_of(D: np.ndarray, x: np.ndarray, d: float, g: float) -> float:
+    """v(x) = K(x,x) - k^T K^{-1} k with K(x,x) = 1 + g (eq. newv)."""
+    if D.shape[0] == 0:
+        return 1.0 + g
+    K = corr(D, D, d) + g * np.eye(D.shape[0])
+    k = corr(D, x[None, :], d)[:, 0]
+    return 1.0 + g - k @ np.linalg.solve(K, k)
+
+
+def delta(D: np.ndarray, c: np.ndarray, x: np.ndarray, d: float, g: float) -> float:
+    """v_j(x) - v_{j+1}(x) with c appended, from two fresh solves (eq. dxy, left side)."""
+    return v_of(D, x, d, g) - v_of(np.vstack([D, c[None, :]]), x, d, g)
+
+
+def predict(D: np.ndarray, Yd: np.ndarray, x: np.ndarray, d: float, g: float) -> dict:
+    """Eqs. predgp and preds2 with N -> n, via numpy.linalg.solve."""
+    n = D.shape[0]
+    K = corr(D, D, d) + g * np.eye(n)
+    k = corr(D, x[None, :], d)[:, 0]
+    a = np.linalg.solve(K, Yd)
+    psi = Yd @ a
+    v = 1.0 + g - k @ np.linalg.solve(K, k)
+    s2 = psi * v / n
+    return dict(mean=k @ a, s2=s2, var=s2 * n / (n - 2) if n > 2 else np.nan, v=v, psi=psi)
+
+
+def greedy(X: np.ndarray, x: np.ndarray, P: np.ndarray, n0: int, n: int, d: float, g: float):
+    """Fig. 1 steps 2a-2b by brute force: returns (sel, best score per step)."""
+    sel = list(P[:n0])
+    best = []
+    for _ in range(n0, n):
+        D = X[sel]
+        scores = []
+        for c in P:
+            if c in sel:
+                continue
+            scores.append((delta(D, X[c], x, d, g), -c, c))
+        s, _, c = max(scores)
+        sel.append(c)
+        best.append(s)
+    return np.array(sel, dtype=np.int32), np.array(best)

@@ -1,0 +1,221 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each pin takes an ``oracle.Oracle`` and raises AssertionError on a mismatch.
+They are run on the real oracle (test_oracle_pins.py) and on copies with a
+planted mistake (test_oracle_mutants.py), which each must trip at least one.
+
+What pins what:
+  pool_exact        - NN pool = lexsort by (squared distance, index), with ties
+  greedy_brute      - scores and sequence = brute force v_j - v_{j+1} (eq. dxy)
+                      from fresh dense solves (Sec. 2.2, Fig. 1)
+  hand_j1           - closed form of the score with a one-point design
+  tie_rule          - exact score ties go to the smallest design index
+  invariants        - score >= 0, v_j non-increasing, telescoping sum
+  y_independence    - selected sequence independent of Y (Sec. 2.1: the
+                      variance does not depend on Y); mean linear in Y
+  scale_invariance  - X -> 2X, d -> 4d leaves every kernel value bit-identical
+  special_cases     - n0 = n (NN GP), N' = n (whole pool), n0 = n = N' = N
+                      (full GP) reduce to the textbook GP (eqs. predgp, preds2)
+  design_point      - at a design point v = 2g - g^2 (K^{-1})_ii -> 0 with g
+  predict_textbook  - local prediction = eqs. predgp/preds2 via numpy.solve
+  route_b           - the paper's partitioned-inverse route (eq. piedef) and the
+                      literal three-term eq. dxy agree with mode A
+  forced            - evaluating a given sequence reproduces the free run
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import brute
+import workloads
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+
+
+def pool_exact(orc):
+    r = np.random.default_rng(7)
+    base = r.random((150, 3))
+    lattice = np.array([[i / 4, j / 4, k / 4] for i in range(5) for j in range(5) for k in range(3)])
+    X = np.vstack([base, base[:40], lattice, base[10:20]])  # duplicates -> exact distance ties
+    XX = np.vstack([r.random((6, 3)), lattice[[3, 17, 40]], base[[5, 11]]])
+    for Np in (1, 37, 90, X.shape[0]):
+        P = orc.nn_pool(X, XX, Np)
+        for m in range(XX.shape[0]):
+            want = brute.pool(X, XX[m], Np)
+            assert np.array_equal(P[m], want), (Np, m)
+
+
+def greedy_brute(orc):
+    X, Y, XX = workloads.uniform(3, 70, 2, 4)
+    d, g, n0, n, Np = 0.15, 1e-3, 3, 11, 30
+    out = orc.lagp(X, Y, XX, n0, n, Np, d, g)
+    assert np.all(out["status"] == 0)
+    for m in range(XX.shape[0]):
+        P = brute.pool(X, XX[m], Np)
+        sel, best = brute.greedy(X, XX[m], P, n0, n, d, g)
+        assert np.array_equal(out["sel"][m], sel), m
+        assert _rel(out["dsel"][m, n0:], best) < 1e-8, m
+
+
+def hand_j1(orc):
+    X, Y, XX = workloads.uniform(4, 50, 2, 3)
+    d, g, Np = 0.2, 1e-2, 20
+    out = orc.lagp(X, Y, XX, 1, 2, Np, d, g)
+    kappa = 1.0 + g
+
+    def K(a, b):
+        return math.exp(-sum((a[k] - b[k]) ** 2 for k in range(len(a))) / d)
+
+    for m in range(XX.shape[0]):
+        P = brute.pool(X, XX[m], Np)
+        a = X[P[0]]
+        x = XX[m]
+        best, arg = -1.0, -1
+        for c in P[1:]:
+            s = kappa - K(X[c], a) ** 2 / kappa
+            cov = K(X[c], x) - K(X[c], a) * K(a, x) / kappa
+            sc = cov * cov / s
+            if sc > best or (sc == best and c < arg):
+                best, arg = sc, c
+        assert out["amax"][m, 1] == arg
+        assert abs(out["dmax"][m, 1] - best) <= 1e-12 * best
+
+
+def tie_rule(orc):
+    r = np.random.default_rng(11)
+    A = r.random((60, 2))
+    X = np.vstack([A, A])  # every point twice: rows i and i + 60
+    Y = np.sin(4 * X[:, 0]) + X[:, 1]
+    XX = r.random((3, 2))
+    n0, n, Np = 2, 9, 40
+    out = orc.lagp(X, Y, XX, n0, n, Np, 0.2, 1e-3)
+    for m in range(XX.shape[0]):
+        P = out["pool"][m]
+        # twins are adjacent in the pool, smaller index first
+        for s in range(0, Np - 1, 2):
+            assert P[s] + 60 == P[s + 1] or P[s] == P[s + 1] - 60
+        chosen = out["sel"][m, n0:]
+        # the first greedy pick is the smaller twin of a tied pair
+        assert chosen[0] < 60
+
+
+def invariants(orc):
+    W = workloads.make(2, N=3000, M=6)
+    out = orc.lagp(W.X, W.Y, W.XX, W.n0, 30, 300, W.d, W.g)
+    assert np.all(out["status"] == 0)
+    ds = out["dsel"][:, W.n0:]
+    assert np.all(ds >= 0)
+    v = out["vtraj"][:, W.n0:]
+    assert np.all(np.diff(v, axis=1) <= 1e-14 * v[:, :-1])
+    tele = out["vtraj"][:, W.n0] - ds.sum(axis=1)
+    assert _rel(out["vtraj"][:, 30], tele) < 1e-9
+
+
+def y_independence(orc):
+    W = workloads.make(2, N=2000, M=5)
+    a = orc.lagp(W.X, W.Y, W.XX, 6, 20, 200, W.d, W.g)
+    noise = np.random.default_rng(5).normal(size=W.N)
+    b = orc.lagp(W.X, 3.0 * W.Y + noise, W.XX, 6, 20, 200, W.d, W.g)
+    assert np.array_equal(a["sel"], b["sel"])
+    c = orc.lagp(W.X, -2.5 * W.Y, W.XX, 6, 20, 200, W.d, W.g)
+    assert _rel(c["mean"], -2.5 * a["mean"]) < 1e-12
+    assert _rel(c["s2"], 6.25 * a["s2"]) < 1e-12
+
+
+def scale_invariance(orc):
+    W = workloads.make(1, N=1500, M=5)
+    a = orc.lagp(W.X, W.Y, W.XX, 6, 16, 150, W.d, 1e-4)
+    b = orc.lagp(2 * W.X, W.Y, 2 * W.XX, 6, 16, 150, 4 * W.d, 1e-4)
+    for k in ("pool", "sel", "mean", "s2", "var"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def special_cases(orc):
+    W = workloads.make(4, N=800, M=4)
+    d, g = W.d, W.g
+    n = 12
+    # n0 = n: the NN GP on the first n pool points
+    a = orc.lagp(W.X, W.Y, W.XX, n, n, 40, d, g)
+    for m in range(W.M):
+        P = brute.pool(W.X, W.XX[m], n)
+        ref = brute.predict(W.X[P], W.Y[P], W.XX[m], d, g)
+        assert np.array_equal(a["sel"][m], P)
+        for k in ("mean", "s2", "var"):
+            assert _rel(a[k][m], ref[k]) < 1e-9, k
+    # N' = n: the final design is the whole pool
+    b = orc.lagp(W.X, W.Y, W.XX, 4, n, n, d, g)
+    for m in range(W.M):
+        P = brute.pool(W.X, W.XX[m], n)
+        assert sorted(b["sel"][m]) == sorted(P)
+        ref = brute.predict(W.X[P], W.Y[P], W.XX[m], d, g)
+        for k in ("mean", "s2"):
+            assert _rel(b[k][m], ref[k]) < 1e-9, k
+    # n0 = n = N' = N: the full GP
+    Xs, Ys = W.X[:25], W.Y[:25]
+    c = orc.lagp(Xs, Ys, W.XX, 25, 25, 25, d, g)
+    for m in range(W.M):
+        ref = brute.predict(Xs, Ys, W.XX[m], d, g)
+        for k in ("mean", "s2", "var"):
+            assert _rel(c[k][m], ref[k]) < 1e-9, k
+
+
+def design_point(orc):
+    X, Y, _ = workloads.uniform(6, 400, 2, 1)
+    XX = X[[17, 123, 250]]
+    vs = []
+    for g in (1e-2, 1e-4, 1e-6):
+        out = orc.lagp(X, Y, XX, 6, 14, 60, 0.5, g)
+        for m, i in enumerate((17, 123, 250)):
+            sel = out["sel"][m]
+            assert sel[0] == i  # distance 0 comes first in the pool
+            D = X[sel]
+            K = brute.corr(D, D, 0.5) + g * np.eye(len(sel))
+            Kinv = np.linalg.inv(K)
+            want = 2 * g - g * g * Kinv[0, 0]
+            assert abs(out["v"][m] - want) <= 1e-6 * want + 1e-15, (g, m)
+            vs.append(out["v"][m] / g)
+    assert max(vs) <= 2.0 + 1e-6
+
+
+def predict_textbook(orc):
+    r = np.random.default_rng(9)
+    for n, p, d, g in ((5, 1, 0.3, 1e-3), (17, 3, 0.7, 1e-4), (40, 4, 0.25, 1e-5)):
+        D = r.random((n, p))
+        Yd = np.cos(3 * D).sum(axis=1) + r.normal(0, 0.1, n)
+        x = r.random(p)
+        got = orc.gp_predict(D, Yd, x, d, g)
+        ref = brute.predict(D, Yd, x, d, g)
+        for k in ("mean", "s2", "v", "psi"):
+            assert _rel(got[k], ref[k]) < 1e-8, (n, k)
+        assert _rel(got["var"], got["s2"] * n / (n - 2)) < 1e-15
+
+
+def route_b(orc):
+    W = workloads.make(2, N=5000, M=4)
+    out = orc.lagp(W.X, W.Y, W.XX, 6, 30, 300, W.d, W.g, mode_b=True)
+    nu = out["nu"][:, 6:]
+    assert np.all(np.isfinite(nu))
+    assert np.max(nu) < 1e-9, np.max(nu)
+
+
+def forced(orc):
+    W = workloads.make(2, N=3000, M=4)
+    a = orc.lagp(W.X, W.Y, W.XX, 6, 20, 200, W.d, W.g)
+    b = orc.alc(W.X, W.Y, W.XX, a["pool"], 6, 20, W.d, W.g, forced=a["sel"])
+    for k in ("sel", "dsel", "dmax", "amax", "mean", "s2"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    nn = np.ascontiguousarray(a["pool"][:, :20])
+    c = orc.alc(W.X, W.Y, W.XX, a["pool"], 6, 20, W.d, W.g, forced=nn)
+    assert np.all(c["dsel"][:, 6:] <= c["dmax"][:, 6:])
+    for m in range(W.M):
+        ref = brute.predict(W.X[nn[m]], W.Y[nn[m]], W.XX[m], W.d, W.g)
+        assert _rel(c["mean"][m], ref["mean"]) < 1e-9
+
+
+ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
+       special_cases, design_point, predict_textbook, route_b, forced]

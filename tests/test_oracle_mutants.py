@@ -1,0 +1,60 @@
+"""Plausible mistakes planted in copies of the oracle must each trip a pin.
+
+Every mutant is a textual edit of ``oracle/lagp_oracle.c`` compiled into a
+temporary directory; the real oracle is never modified.
+"""
+import pytest
+
+import oracle
+import oracle_pins
+
+MUTANTS = {
+    # the sign slip of Fig. 3 step 5 taken literally: (c + u.h)^2 / s
+    "cov_sign": ("double cov = kcx - dot(w->zc, w->zh, j);", "double cov = kcx + dot(w->zc, w->zh, j);"),
+    # nugget dropped from the candidate self-covariance
+    "kappa_no_nugget": ("    const double kappa = 1.0 + g;\n    for (int k = 0; k < p; k++)",
+                        "    const double kappa = 1.0;\n    for (int k = 0; k < p; k++)"),
+    # nugget wrongly added to the cross-covariance with x
+    "nugget_on_h": ("w->h[a] = kern(xa, x, p, d);", "w->h[a] = kern(xa, x, p, d) + g;"),
+    # transposed operand in the triangular solve
+    "solve_transposed": ("for (int k = 0; k < r; k++) s -= L[r * j + k] * z[k];",
+                         "for (int k = 0; k < r; k++) s -= L[k * j + r] * z[k];"),
+    # score ties go to the largest index
+    "tie_reversed": ("(delta == best && best_slot >= 0 && pool[s] < pool[best_slot])",
+                     "(delta == best && best_slot >= 0 && pool[s] > pool[best_slot])"),
+    # pool ties broken by descending index
+    "pool_tie_reversed": ("return (a->idx > b->idx) - (a->idx < b->idx);",
+                          "return (a->idx < b->idx) - (a->idx > b->idx);"),
+    # Student-t scale divided by n - 1
+    "s2_divisor": ("double s2 = psi * v / n;", "double s2 = psi * v / (n - 1);"),
+    # psi = Y^T Y instead of Y^T K^{-1} Y
+    "psi_wrong": ("double psi = dot(Yd, alpha, n);", "double psi = dot(Yd, Yd, n);"),
+    # NN start skips the nearest point
+    "init_off_by_one": ("                take_slot = j;\n", "                take_slot = j + 1;\n"),
+    # last coordinate dropped from the distance
+    "dist_drops_coord": ("    for (int k = 0; k < p; k++) {\n        double t = a[k] - b[k];",
+                         "    for (int k = 0; k + 1 < p; k++) {\n        double t = a[k] - b[k];"),
+    # partitioned inverse with the sign of g flipped (mode B)
+    "piedef_sign": ("for (int a = 0; a < j; a++) gv[a] = -m * u[a];\n    int J",
+                    "for (int a = 0; a < j; a++) gv[a] = m * u[a];\n    int J"),
+    # Cholesky diagonal without the square root
+    "chol_no_sqrt": ("L[r * j + r] = sqrt(s);", "L[r * j + r] = s;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.compile_c(str(path), str(tmp_path / f"lib{name}.so"))
+    orc = oracle.Oracle(lib)
+    tripped = []
+    for pin in oracle_pins.ALL:
+        try:
+            pin(orc)
+        except Exception:  # any failure, including garbage indices, counts
+            tripped.append(pin.__name__)
+    assert tripped, f"mutant {name} passed every pin"
