@@ -1,0 +1,140 @@
+/*
+ * lagp_alc.h -- C ABI of the MI355X (gfx950) library for local approximate
+ * Gaussian-process regression with greedy ALC local designs.
+ *
+ * Method: Gramacy, Niemi & Weiss, "Massively parallel approximate Gaussian
+ * process regression" (arXiv:1310.5182).  For every predictive location x:
+ *   1. the pool of the N' design points nearest to x (Sec. 2.2 NN sub-design,
+ *      Sec. 3.1 search over N' nearest neighbours);
+ *   2. a local design grown from the n0 nearest to n points, each step adding
+ *      the candidate with the largest reduction in predictive variance at x,
+ *      v_j(x) - v_{j+1}(x) (eq. dxy, Fig. 1 step 2), folded in with the
+ *      partitioned-inverse update (eq. piedef);
+ *   3. the local predictive mean, scale and variance (eqs. predgp, preds2,
+ *      Student-t with n degrees of freedom, Sec. 2.1).
+ * Correlation: K(x, x') = exp(-||x - x'||^2 / d) (Sec. 2.1); the nugget g is
+ * added to the diagonal of the design covariance only, and K(x', x') = 1 + g
+ * for candidates and for x (Fig. 3 step 5).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers on the current HIP device,
+ *     caller-owned, row-major, float64 unless stated, int32 indices (0-based).
+ *     The library never allocates or frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     and the call returns; the caller synchronises.
+ *   - Arguments are validated on the host before any HIP call; on failure
+ *     nothing is enqueued or written and LAGP_EINVAL is returned.  HIP
+ *     launch failures return LAGP_EHIP.  lagp_last_error() gives a
+ *     human-readable message for the calling thread's last failure.
+ *   - Per-location numerical failures do not fail the call: they are
+ *     reported in status[m] and that location's outputs are NaN.
+ *   - Calls that overlap on one device must not share output buffers.
+ */
+#ifndef LAGP_ALC_H
+#define LAGP_ALC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lagp_status;
+#define LAGP_OK 0
+#define LAGP_EINVAL (-1)        /* invalid argument                        */
+#define LAGP_EWORKSPACE (-2)    /* workspace too small                     */
+#define LAGP_EHIP (-3)          /* HIP runtime or launch error             */
+#define LAGP_EUNSUPPORTED (-4)  /* sizes outside the compiled schedules    */
+
+/* Arithmetic of the candidate scoring (Fig. 1 step 2b). */
+#define LAGP_FP64 0   /* everything in float64                                 */
+#define LAGP_MIXED 1  /* candidate kernel vectors and scores in float32 with   */
+                      /* float32 accumulation; the inverse-factor update, the  */
+                      /* Schur complement of the chosen point, a re-score of   */
+                      /* the near-best candidates and the prediction in       */
+                      /* float64                                               */
+
+/* Per-location status codes written to status[m]. */
+#define LAGP_LOC_OK 0
+#define LAGP_LOC_INIT_NOT_PD 1  /* K_{n0} not numerically positive definite    */
+#define LAGP_LOC_STEP_FAIL 2    /* Schur complement of a chosen point <= 0, or */
+                                /* no candidate with a positive one             */
+#define LAGP_LOC_NONFINITE 3    /* x not finite                                 */
+#define LAGP_LOC_BAD_POOL 4     /* a pool entry outside [0, N): the location is */
+                                /* skipped, no design row is read               */
+
+/*
+ * lagp_nn_pool -- nearest-neighbour candidate pools (Sec. 2.2, Sec. 3.1).
+ *
+ *   X    [N x p]  design            XX  [M x p]  predictive locations
+ *   pool [M x Np] out: for location m, the Np design indices with the
+ *                 smallest squared distance sum_k (X[i,k] - XX[m,k])^2,
+ *                 evaluated in float64 left to right with no fused
+ *                 multiply-add, sorted ascending by (distance, index).
+ * Requires 1 <= Np <= N, N < 2^31, p >= 1.  M = 0 is a no-op.
+ */
+lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
+                         int32_t Np, int32_t *pool, void *stream);
+
+/*
+ * lagp_alc_from_pool -- greedy ALC local designs and local predictions
+ * (Fig. 1 steps 2a, 2b and 5) from given candidate pools.
+ *
+ *   X [N x p], Y [N]        design and responses (Y used raw: zero-mean GP)
+ *   XX [M x p]              predictive locations
+ *   pool [M x Np]           candidate pools as written by lagp_nn_pool; the
+ *                           local design starts from pool[m][0 .. n0-1]
+ *   n0, n                   start and final local design sizes
+ *                           (1 <= n0 <= n <= Np)
+ *   d, g                    lengthscale and nugget (finite, > 0)
+ *   precision               LAGP_FP64 or LAGP_MIXED
+ * Outputs (any may be NULL except sel):
+ *   mean [M]                local predictive mean k^T K_n^{-1} Y_n (eq. predgp)
+ *   s2   [M]                Student-t scale psi (1 + g - k^T K_n^{-1} k) / n
+ *                           (eq. preds2 with N -> n)
+ *   var  [M]                predictive variance s2 n / (n - 2); NaN if n <= 2
+ *   sel  [M x n]            design indices of the local design in the order
+ *                           added; row m starts with pool[m][0 .. n0-1]
+ *   alc  [M x n]            float64 score v_j(x) - v_{j+1}(x) of the point
+ *                           added at step j (unnormalised, eq. dxy); NaN for
+ *                           j < n0
+ *   status [M]              LAGP_LOC_* code
+ *   guard  [M]              LAGP_MIXED: number of steps whose float32 scores
+ *                           were not trusted and were redone in float64; 0 for
+ *                           LAGP_FP64
+ * Exact score ties go to the smallest design index.
+ * Supported sizes: p <= 8, Np <= 1024, n <= 52 for LAGP_FP64 and n <= 64
+ * for LAGP_MIXED.  Others return LAGP_EUNSUPPORTED.
+ */
+lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
+                               const double *XX, int64_t M, const int32_t *pool, int32_t Np,
+                               int32_t n0, int32_t n, double d, double g, int32_t precision,
+                               double *mean, double *s2, double *var, int32_t *sel, double *alc,
+                               int32_t *status, int32_t *guard, void *stream);
+
+/*
+ * lagp_alc_predict -- the whole hot path: lagp_nn_pool into `pool`
+ * (caller-allocated M x Np int32, left holding the pools), then
+ * lagp_alc_from_pool.  Arguments as above.
+ */
+lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_t p,
+                             const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
+                             double d, double g, int32_t precision, int32_t *pool,
+                             double *mean, double *s2, double *var, int32_t *sel, double *alc,
+                             int32_t *status, int32_t *guard, void *stream);
+
+/* Name of a status code. */
+const char *lagp_status_string(lagp_status s);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *lagp_last_error(void);
+
+/* Library version string. */
+const char *lagp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGP_ALC_H */

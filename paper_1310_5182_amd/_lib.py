@@ -1,0 +1,74 @@
+"""ctypes loader of liblagp_alc.so (the gfx950 library).  No fallback: if the
+library is missing or fails to load, every call raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblagp_alc.so")
+
+LAGP_OK = 0
+LAGP_EINVAL = -1
+LAGP_EWORKSPACE = -2
+LAGP_EHIP = -3
+LAGP_EUNSUPPORTED = -4
+
+LAGP_FP64 = 0
+LAGP_MIXED = 1
+
+# Every symbol declared in include/lagp_alc.h.
+EXPORTS = (
+    "lagp_nn_pool",
+    "lagp_alc_from_pool",
+    "lagp_alc_predict",
+    "lagp_status_string",
+    "lagp_last_error",
+    "lagp_version",
+)
+
+_lib = None
+
+
+class LagpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(msg)
+        self.code = code
+
+
+def load():
+    """Load the library (once).  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} not found: build it with `python -m paper_1310_5182_amd.build` "
+            "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.lagp_nn_pool.argtypes = [P, i64, i32, P, i64, i32, P, P]
+    L.lagp_nn_pool.restype = i32
+    L.lagp_alc_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, i32,
+                                     P, P, P, P, P, P, P, P]
+    L.lagp_alc_from_pool.restype = i32
+    L.lagp_alc_predict.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, f64, f64, i32, P,
+                                   P, P, P, P, P, P, P, P]
+    L.lagp_alc_predict.restype = i32
+    L.lagp_status_string.argtypes = [i32]
+    L.lagp_status_string.restype = ctypes.c_char_p
+    L.lagp_last_error.argtypes = []
+    L.lagp_last_error.restype = ctypes.c_char_p
+    L.lagp_version.argtypes = []
+    L.lagp_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(code: int) -> None:
+    if code == LAGP_OK:
+        return
+    L = load()
+    msg = f"{L.lagp_status_string(code).decode()}: {L.lagp_last_error().decode()}"
+    if code == LAGP_EINVAL:
+        raise ValueError(msg)
+    raise LagpError(code, msg)

@@ -1,0 +1,478 @@
+// Greedy ALC local designs on gfx950 (Fig. 1 steps 2a, 2b and 5).
+//
+// One workgroup per predictive location x.  With R_j = L_j^{-1} the inverse
+// of the lower Cholesky factor of K_j (so K_j^{-1} = R_j^T R_j), the score of
+// candidate c (eq. dxy) is
+//     Delta_c = (K(c,x) - z_c . z_h)^2 / (kappa - z_c . z_c),
+//     z_c = R_j K(X_j, c),  z_h = R_j K(X_j, x),
+// i.e. conditional covariance squared over conditional variance.  Adding the
+// chosen point x* with l = R_j K(X_j, x*) and s* = kappa - l.l (the Schur
+// complement m^{-1} of eq. piedef) borders the factor:
+//     R_{j+1} = [[R_j, 0], [-l^T R_j / sqrt(s*), 1 / sqrt(s*)]],
+// whose new last row is sqrt(s*) times the last row [g^T, m] of the
+// partitioned inverse K_{j+1}^{-1} of eq. piedef.
+//
+// Work split.  Each wave owns CBW blocks of 16 candidates.  The candidate
+// kernel matrix Q = K(candidates, X_j) stays in registers for the whole
+// design, laid out as the B operand of the 16x16x4 MFMA (lane l of block cb
+// holds Q[16 cb + l % 16][4 kg + l / 16] in register kg); every step appends
+// one column.  R_j sits in LDS in A-operand fragment order, so Z^T = R_j Q^T
+// is a chain of MFMAs over the non-zero (lower-triangular) tiles of R_j, and
+// the epilogue folds z.z and z.z_h straight out of the accumulators.
+//
+// Precision.  LAGP_FP64 runs the MFMA in float64.  LAGP_MIXED keeps Q and a
+// float32 copy of R_j for float32 MFMA scoring; the float64 master R_j, the
+// re-score of every candidate within kBandTau of the float32 best, the Schur
+// complement of the chosen point, the update and the prediction stay in
+// float64.  A step whose float32 scores look untrustworthy (band overflow,
+// re-score disagreement above kTrustErr, a tiny float32 conditional variance)
+// is re-scored entirely in float64 and counted in guard[m].
+#include "lagp_device.hpp"
+#include "lagp_internal.hpp"
+
+#include <math.h>
+
+namespace lagp {
+
+template <typename T>
+struct Mma;
+// Accumulator element r of lane l holds row row(l, r), column l % 16, of the
+// 16x16 result; the float32 and float64 16x16x4 instructions differ here.
+template <>
+struct Mma<float> {
+    typedef v4f acc;
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static __device__ __forceinline__ acc run(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mma<double> {
+    typedef v4d acc;
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    static __device__ __forceinline__ acc run(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kBandCap = 32;
+constexpr float kBandTau = 1.0f / 64;
+constexpr double kTrustErr = 1.0 / 256;
+constexpr float kSmallS = 1.0f / 131072;
+constexpr int kPmax = 8;
+
+constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4;
+
+// Element (i, l) of an R-sized matrix stored in 16x4 A-fragment tiles.
+template <int KG>
+__device__ __forceinline__ int ridx(int i, int l)
+{
+    return ((i >> 4) * KG + (l >> 2)) * 64 + (i & 15) + 16 * (l & 3);
+}
+
+// Float64 score of candidate `slot` by one wave (lane i computes z_i):
+// returns Delta (or -1 if the conditional variance is not positive) and the
+// conditional variance in s_out; writes z to zout[lane] when zout != nullptr.
+template <int SLOTS, int KG>
+__device__ __forceinline__ double wave_score64(const double *cx, const int32_t *selslot,
+                                               const double *RM, const double *zh,
+                                               const double *cxv, int slot, int j, int p,
+                                               double d, double kappa, int lane, double *zout,
+                                               double &s_out)
+{
+    double kl = 0.0;
+    if (lane < j) kl = corr64(sqdist_strict(cx + selslot[lane], SLOTS, cx + slot, SLOTS, p), d);
+    double z = 0.0;
+    for (int l = 0; l < j; l++) z = fma(RM[ridx<KG>(lane, l)], readlane(kl, l), z);
+    if (zout) zout[lane] = z;
+    const double ss = wave_sum(z * z);
+    const double zz = wave_sum(z * zh[lane]);
+    const double s = kappa - ss;
+    const double cov = cxv[slot] - zz;
+    s_out = s;
+    return s > 0.0 ? cov * cov / s : -1.0;
+}
+
+template <typename T, int NW, int CBW, int KG, int G>
+__global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
+{
+    using Acc = typename Mma<T>::acc;
+    constexpr int kThreads = NW * kWave;
+    constexpr int SLOTS = NW * CBW * 16;
+    constexpr int NMAX = 4 * KG;
+    constexpr int NIB = (NMAX + 15) / 16;
+    constexpr int ROWS = NIB * 16;
+    constexpr int RT = NIB * KG * 64;
+    constexpr bool MIXED = sizeof(T) == 4;
+    static_assert(ROWS == 64, "one lane per row of R in the wave-level float64 routines");
+    static_assert(CBW % G == 0, "column blocks come in groups of G");
+
+    __shared__ double RM[RT];                  // float64 R_j, A-fragment tiles
+    __shared__ float RA32[MIXED ? RT : 1];     // float32 copy of R_j (mixed)
+    __shared__ double cx[kPmax * SLOTS];       // candidate coordinates, [k][slot]
+    __shared__ double cxv[SLOTS];              // K(candidate, x)
+    __shared__ int32_t cid[SLOTS];             // design index of each slot
+    __shared__ uint8_t cflag[SLOTS];           // 0 candidate, 1 in design, 2 empty
+    __shared__ float sc32[MIXED ? SLOTS : 1];  // float32 scores (mixed)
+    __shared__ double zh[ROWS], tY[ROWS], ell[ROWS];
+    __shared__ float zh32[MIXED ? ROWS : 1];
+    __shared__ double xs[kPmax];
+    __shared__ int32_t selslot[NMAX];
+    __shared__ T red_s[NW];
+    __shared__ double red64[NW];
+    __shared__ int32_t red_i[NW], red_k[NW];
+    __shared__ int32_t band_slot[kBandCap];
+    __shared__ double band_val[kBandCap];
+    __shared__ int band_cnt, ctl_status, ctl_susp;
+    __shared__ double ctl_sstar, ctl_alc;
+
+    const T *RA;
+    const T *zhT;
+    if constexpr (MIXED) {
+        RA = RA32;
+        zhT = zh32;
+    } else {
+        RA = RM;
+        zhT = zh;
+    }
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int64_t m = blockIdx.x;
+    const int p = a.p, Np = a.Np, n = a.n, n0 = a.n0;
+    const double d = a.d, kappa = 1.0 + a.g;
+    const int wbase = w * CBW * 16;
+
+    // ---- stage the location, its pool and zeroed factors in LDS
+    if (tid == 0) {
+        ctl_status = kLocOk;
+        band_cnt = 0;
+        ctl_susp = 0;
+    }
+    if (tid < p) xs[tid] = a.XX[m * p + tid];
+    __syncthreads();
+    for (int s = tid; s < SLOTS; s += kThreads) {
+        bool valid = s < Np;
+        int32_t di = valid ? a.pool[m * Np + s] : INT32_MAX;
+        if (valid && (di < 0 || di >= a.N)) {  // never read outside X
+            ctl_status = kLocBadPool;
+            valid = false;
+            di = INT32_MAX;
+        }
+        cid[s] = di;
+        cflag[s] = valid ? 0 : 2;
+        for (int k = 0; k < p; k++) cx[k * SLOTS + s] = valid ? a.X[(int64_t)di * p + k] : 0.0;
+    }
+    for (int i = tid; i < RT; i += kThreads) {
+        RM[i] = 0.0;
+        if constexpr (MIXED) RA32[i] = 0.0f;
+    }
+    for (int i = tid; i < ROWS; i += kThreads) {
+        zh[i] = 0.0;
+        tY[i] = 0.0;
+        ell[i] = 0.0;
+        if constexpr (MIXED) zh32[i] = 0.0f;
+    }
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 0; k < p; k++)
+            if (!isfinite(xs[k]) && ctl_status == kLocOk) ctl_status = kLocNonfinite;
+    for (int s = tid; s < SLOTS; s += kThreads)
+        cxv[s] = s < Np ? corr64(sqdist_strict(cx + s, SLOTS, xs, 1, p), d) : 0.0;
+    __syncthreads();
+
+    int status = ctl_status;
+    int guard_steps = 0;
+    int j = 0;
+
+    T Q[CBW][KG];
+#pragma unroll
+    for (int cb = 0; cb < CBW; cb++)
+#pragma unroll
+        for (int kg = 0; kg < KG; kg++) Q[cb][kg] = (T)0;
+
+    for (; status == kLocOk && j < n; j++) {
+        int win = j;  // X_{n0}: the nearest n0 pool entries, in pool order
+        if (j >= n0) {
+            // ===== score every candidate: Z^T = R_j Q^T on the matrix cores
+            T best_s = (T)-1;
+            int32_t best_i = INT32_MAX, best_k = -1;
+            bool susp = false;
+#pragma unroll
+            for (int cg = 0; cg < CBW; cg += G) {
+                T sp[G], cp[G];
+#pragma unroll
+                for (int q = 0; q < G; q++) sp[q] = cp[q] = (T)0;
+                const int nib = (j + 15) >> 4;
+#pragma unroll 1
+                for (int ib = 0; ib < nib; ib++) {
+                    {
+                        Acc acc[G];
+#pragma unroll
+                        for (int q = 0; q < G; q++) acc[q] = Acc{0, 0, 0, 0};
+#pragma unroll
+                        for (int kg = 0; kg < KG; kg++) {
+                            if (kg * 4 < j && kg <= ib * 4 + 3) {
+                                const T av = RA[(ib * KG + kg) * 64 + lane];
+#pragma unroll
+                                for (int q = 0; q < G; q++) acc[q] = Mma<T>::run(av, Q[cg + q][kg], acc[q]);
+                            }
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const T zr = zhT[ib * 16 + Mma<T>::row(lane, r)];
+#pragma unroll
+                            for (int q = 0; q < G; q++) {
+                                const T z = acc[q][r];
+                                sp[q] += z * z;
+                                cp[q] += z * zr;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < G; q++) {
+                    T s_ = sp[q];
+                    s_ += __shfl_xor(s_, 16, kWave);
+                    s_ += __shfl_xor(s_, 32, kWave);
+                    T c_ = cp[q];
+                    c_ += __shfl_xor(c_, 16, kWave);
+                    c_ += __shfl_xor(c_, 32, kWave);
+                    const int slot = wbase + (cg + q) * 16 + (lane & 15);
+                    const bool live = cflag[slot] == 0;
+                    const T sv = (T)kappa - s_;
+                    const T cv = (T)cxv[slot] - c_;
+                    const T score = (live && sv > (T)0) ? cv * cv / sv : (T)-1;
+                    if constexpr (MIXED) {
+                        if (live && !(sv > kSmallS * (float)kappa)) susp = true;
+                        if (lane < 16) sc32[slot] = score;
+                    }
+                    const int32_t di = score >= (T)0 ? cid[slot] : INT32_MAX;
+                    if (beats(score, di, best_s, best_i)) {
+                        best_s = score;
+                        best_i = di;
+                        best_k = slot;
+                    }
+                }
+            }
+            wave_argmax(best_s, best_i, best_k);
+            if (lane == 0) {
+                red_s[w] = best_s;
+                red_i[w] = best_i;
+                red_k[w] = best_k;
+            }
+            if constexpr (MIXED)
+                if (susp) ctl_susp = 1;
+            __syncthreads();
+            T bs = red_s[0];
+            int32_t bi = red_i[0];
+            win = red_k[0];
+            for (int q = 1; q < NW; q++)
+                if (beats(red_s[q], red_i[q], bs, bi)) {
+                    bs = red_s[q];
+                    bi = red_i[q];
+                    win = red_k[q];
+                }
+            if (bs < (T)0) win = -1;
+
+            if constexpr (MIXED) {
+                // ===== float64 re-score of the near-best float32 band
+                bool fallback = ctl_susp != 0 || !(bs > 0.0f);
+                win = -1;
+                if (!fallback) {
+                    const float thr = bs * (1.0f - kBandTau);
+                    for (int s = tid; s < SLOTS; s += kThreads)
+                        if (sc32[s] >= thr) {
+                            const int pos = atomicAdd(&band_cnt, 1);
+                            if (pos < kBandCap) band_slot[pos] = s;
+                        }
+                    __syncthreads();
+                    const int cnt = band_cnt;
+                    if (cnt <= kBandCap) {
+                        for (int b = w; b < cnt; b += NW) {
+                            double sdummy;
+                            const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, band_slot[b], j, p, d,
+                                                                     kappa, lane, nullptr, sdummy);
+                            if (lane == 0) band_val[b] = v;
+                        }
+                        __syncthreads();
+                        double b64 = -1.0, err = 0.0;
+                        int32_t bi64 = INT32_MAX;
+                        int bk64 = -1;
+                        for (int b = 0; b < cnt; b++) {
+                            const int s = band_slot[b];
+                            const double v = band_val[b];
+                            if (beats(v, cid[s], b64, bi64)) {
+                                b64 = v;
+                                bi64 = cid[s];
+                                bk64 = s;
+                            }
+                            err = v > 0.0 ? fmax(err, fabs((double)sc32[s] - v) / v) : INFINITY;
+                        }
+                        if (b64 > 0.0 && err <= kTrustErr)
+                            win = bk64;
+                        else
+                            fallback = true;
+                    } else {
+                        fallback = true;
+                    }
+                }
+                if (fallback) {
+                    // ===== the whole step in float64, one candidate per wave at a time
+                    double fb = -1.0;
+                    int32_t fi = INT32_MAX;
+                    int fk = -1;
+                    for (int s = w; s < SLOTS; s += NW) {
+                        if (cflag[s] != 0) continue;
+                        double sdummy;
+                        const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, s, j, p, d, kappa, lane,
+                                                                 nullptr, sdummy);
+                        if (beats(v, v >= 0.0 ? cid[s] : INT32_MAX, fb, fi)) {
+                            fb = v;
+                            fi = cid[s];
+                            fk = s;
+                        }
+                    }
+                    __syncthreads();
+                    if (lane == 0) {
+                        red64[w] = fb;
+                        red_i[w] = fi;
+                        red_k[w] = fk;
+                    }
+                    __syncthreads();
+                    fb = red64[0];
+                    fi = red_i[0];
+                    win = red_k[0];
+                    for (int q = 1; q < NW; q++)
+                        if (beats(red64[q], red_i[q], fb, fi)) {
+                            fb = red64[q];
+                            fi = red_i[q];
+                            win = red_k[q];
+                        }
+                    if (fb < 0.0) win = -1;
+                    guard_steps++;
+                }
+            }
+            if (win < 0) {  // no candidate with a positive conditional variance
+                status = kLocStepFail;
+                break;
+            }
+        }
+
+        // ===== float64 update: l = R_j k*, s*, border R, z_h and R Y
+        if (w == 0) {
+            double sstar;
+            const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, win, j, p, d, kappa, lane, ell, sstar);
+            const double zt = wave_sum(ell[lane] * tY[lane]);
+            const double zz = wave_sum(ell[lane] * zh[lane]);
+            if (lane == 0) {
+                ctl_sstar = sstar;
+                ctl_alc = j >= n0 ? v : NAN;
+                if (!(sstar > 0.0) || !isfinite(sstar)) {
+                    ctl_status = j < n0 ? kLocInitNotPd : kLocStepFail;
+                } else {
+                    const double lam = sqrt(sstar);
+                    zh[j] = (cxv[win] - zz) / lam;
+                    tY[j] = (a.Y[cid[win]] - zt) / lam;
+                    if constexpr (MIXED) zh32[j] = (float)zh[j];
+                }
+                band_cnt = 0;
+                ctl_susp = 0;
+            }
+        }
+        __syncthreads();
+        status = ctl_status;
+        if (status != kLocOk) break;
+
+        const double lam = sqrt(ctl_sstar);
+        for (int l = w; l <= j; l += NW) {
+            const double prod = lane < j ? ell[lane] * RM[ridx<KG>(lane, l)] : 0.0;
+            const double sum = wave_sum(prod);
+            if (lane == 0) {
+                const double r = l < j ? -sum / lam : 1.0 / lam;
+                RM[ridx<KG>(j, l)] = r;
+                if constexpr (MIXED) RA32[ridx<KG>(j, l)] = (float)r;
+            }
+        }
+        if (tid == 0) {
+            cflag[win] = 1;
+            selslot[j] = win;
+            a.sel[m * n + j] = cid[win];
+            if (a.alc) a.alc[m * n + j] = ctl_alc;
+        }
+        // new column j of Q: K(candidate, x*)
+        {
+            const int kgj = j >> 2;
+            if ((lane >> 4) == (j & 3)) {
+#pragma unroll
+                for (int cb = 0; cb < CBW; cb++) {
+                    const int slot = wbase + cb * 16 + (lane & 15);
+                    double v = 0.0;
+                    if (slot < Np) v = corr64(sqdist_strict(cx + slot, SLOTS, cx + win, SLOTS, p), d);
+#pragma unroll
+                    for (int q = 0; q < KG; q++)
+                        if (q == kgj) Q[cb][q] = (T)v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+
+    // ===== local prediction (eqs. predgp, preds2): mu = z_h.(R Y), psi = |R Y|^2
+    if (w == 0) {
+        const double zi = (status == kLocOk && lane < n) ? zh[lane] : 0.0;
+        const double ti = (status == kLocOk && lane < n) ? tY[lane] : 0.0;
+        const double mu = wave_sum(zi * ti);
+        const double psi = wave_sum(ti * ti);
+        const double zz = wave_sum(zi * zi);
+        if (lane == 0) {
+            const bool ok = status == kLocOk;
+            const double v = kappa - zz;
+            const double s2 = psi * v / n;
+            if (a.mean) a.mean[m] = ok ? mu : NAN;
+            if (a.s2) a.s2[m] = ok ? s2 : NAN;
+            if (a.var) a.var[m] = (ok && n > 2) ? s2 * n / (n - 2) : NAN;
+            if (a.status) a.status[m] = status;
+            if (a.guard) a.guard[m] = guard_steps;
+        }
+        if (status != kLocOk)
+            for (int jj = j + lane; jj < n; jj += kWave) {
+                a.sel[m * n + jj] = -1;
+                if (a.alc) a.alc[m * n + jj] = NAN;
+            }
+    }
+}
+
+struct Sched {
+    int slots;
+    int nmax;
+};
+
+template <typename T, int NW, int CBW, int KG, int G>
+static hipError_t launch_t(const AlcArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((alc_kernel<T, NW, CBW, KG, G>), dim3((unsigned)a.M), dim3(NW * kWave), 0, st, a);
+    return hipGetLastError();
+}
+
+bool alc_supported(int precision, int p, int Np, int n)
+{
+    if (p > kPmax || Np > 1024) return false;
+    return precision == 0 ? n <= 52 : n <= 64;
+}
+
+hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st)
+{
+    if (a.M == 0) return hipSuccess;
+    if (!alc_supported(precision, a.p, a.Np, a.n)) return hipErrorNotSupported;
+    if (precision == 0) {
+        if (a.Np <= 512) return launch_t<double, 4, 8, 13, 1>(a, st);
+        return launch_t<double, 8, 8, 13, 1>(a, st);
+    }
+    if (a.Np <= 512) return launch_t<float, 8, 4, 16, 4>(a, st);
+    return launch_t<float, 16, 4, 16, 4>(a, st);
+}
+
+}  // namespace lagp

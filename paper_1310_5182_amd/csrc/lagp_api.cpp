@@ -1,0 +1,146 @@
+// C ABI of the local approximate GP library (declarations in lagp_alc.h).
+// Host side only: argument validation, dispatch to the kernel launchers.
+#include "lagp_alc.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "lagp_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lagp_status fail(lagp_status code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+lagp_status ok()
+{
+    g_err[0] = '\0';
+    return LAGP_OK;
+}
+
+lagp_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(LAGP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+lagp_status check_common(const double *X, int64_t N, int32_t p, const double *XX, int64_t M, int32_t Np)
+{
+    if (M < 0) return fail(LAGP_EINVAL, "M = %lld < 0", (long long)M);
+    if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
+    if (p > lagp::kMaxP) return fail(LAGP_EUNSUPPORTED, "p = %d > %d", p, lagp::kMaxP);
+    if (N < 1 || N >= (int64_t)1 << 31) return fail(LAGP_EINVAL, "N = %lld outside [1, 2^31)", (long long)N);
+    if (Np < 1 || Np > N) return fail(LAGP_EINVAL, "Np = %d outside [1, N = %lld]", Np, (long long)N);
+    if (M > 0 && (!X || !XX)) return fail(LAGP_EINVAL, "X and XX must be non-NULL");
+    if (M > (int64_t)0x7fffffff) return fail(LAGP_EUNSUPPORTED, "M = %lld exceeds one launch", (long long)M);
+    return LAGP_OK;
+}
+
+lagp_status check_alc(const double *Y, int32_t Np, int32_t n0, int32_t n, double d, double g,
+                      int32_t precision, const int32_t *sel, int64_t M)
+{
+    if (precision != LAGP_FP64 && precision != LAGP_MIXED)
+        return fail(LAGP_EINVAL, "precision = %d is neither LAGP_FP64 nor LAGP_MIXED", precision);
+    if (!(n0 >= 1 && n0 <= n && n <= Np))
+        return fail(LAGP_EINVAL, "need 1 <= n0 <= n <= Np (n0 = %d, n = %d, Np = %d)", n0, n, Np);
+    if (!(d > 0.0) || !isfinite(d)) return fail(LAGP_EINVAL, "lengthscale d must be finite and > 0");
+    if (!(g > 0.0) || !isfinite(g)) return fail(LAGP_EINVAL, "nugget g must be finite and > 0");
+    if (M > 0 && (!Y || !sel)) return fail(LAGP_EINVAL, "Y and sel must be non-NULL");
+    return LAGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
+                         int32_t Np, int32_t *pool, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (lagp::nn_pool_cap(Np) == 0) return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", Np);
+    if (M == 0) return ok();
+    hipError_t e = lagp::launch_nn_pool(X, N, p, XX, M, Np, pool, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
+    return ok();
+}
+
+lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
+                               const double *XX, int64_t M, const int32_t *pool, int32_t Np,
+                               int32_t n0, int32_t n, double d, double g, int32_t precision,
+                               double *mean, double *s2, double *var, int32_t *sel, double *alc,
+                               int32_t *status, int32_t *guard, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    s = check_alc(Y, Np, n0, n, d, g, precision, sel, M);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (!lagp::alc_supported(precision, p, Np, n))
+        return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d, precision = %d", p, Np, n,
+                    precision);
+    if (M == 0) return ok();
+    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np, n0, n, d, g, mean, s2, var, sel, alc, status, guard};
+    hipError_t e = lagp::launch_alc(a, precision, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "alc launch");
+    return ok();
+}
+
+lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_t p,
+                             const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
+                             double d, double g, int32_t precision, int32_t *pool,
+                             double *mean, double *s2, double *var, int32_t *sel, double *alc,
+                             int32_t *status, int32_t *guard, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    s = check_alc(Y, Np, n0, n, d, g, precision, sel, M);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (lagp::nn_pool_cap(Np) == 0 || !lagp::alc_supported(precision, p, Np, n))
+        return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d, precision = %d", p, Np, n,
+                    precision);
+    s = lagp_nn_pool(X, N, p, XX, M, Np, pool, stream);
+    if (s != LAGP_OK) return s;
+    return lagp_alc_from_pool(X, Y, N, p, XX, M, pool, Np, n0, n, d, g, precision, mean, s2, var, sel, alc,
+                              status, guard, stream);
+}
+
+const char *lagp_status_string(lagp_status s)
+{
+    switch (s) {
+    case LAGP_OK:
+        return "LAGP_OK";
+    case LAGP_EINVAL:
+        return "LAGP_EINVAL";
+    case LAGP_EWORKSPACE:
+        return "LAGP_EWORKSPACE";
+    case LAGP_EHIP:
+        return "LAGP_EHIP";
+    case LAGP_EUNSUPPORTED:
+        return "LAGP_EUNSUPPORTED";
+    default:
+        return "unknown lagp_status";
+    }
+}
+
+const char *lagp_last_error(void)
+{
+    return g_err;
+}
+
+const char *lagp_version(void)
+{
+    return "lagp-alc 0.1 (gfx950)";
+}
+
+}  // extern "C"

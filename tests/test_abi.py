@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lagp_alc.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1310_5182_amd import _lib
+
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lagp_\w+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("lagp_nn_pool", "lagp_alc_from_pool", "lagp_alc_predict", "lagp_last_error"):
+        assert s in syms
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_1310_5182_amd import _lib
+
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert sorted(_lib.EXPORTS) == declared_symbols()
+
+
+def test_version_and_strings(L):
+    assert b"gfx950" in L.lagp_version()
+    assert L.lagp_status_string(0) == b"LAGP_OK"
+    assert L.lagp_status_string(-1) == b"LAGP_EINVAL"
+    assert L.lagp_status_string(-4) == b"LAGP_EUNSUPPORTED"
+
+
+FAKE = 0x1000  # never dereferenced: validation fails (or M == 0) before any HIP call
+
+
+def nn(L, N=100, p=2, M=3, Np=10, X=FAKE, XX=FAKE, pool=FAKE):
+    return L.lagp_nn_pool(X, N, p, XX, M, Np, pool, None)
+
+
+def alc(L, N=100, p=2, M=3, Np=10, n0=2, n=5, d=0.5, g=1e-3, prec=0, Y=FAKE, sel=FAKE):
+    return L.lagp_alc_from_pool(FAKE, Y, N, p, FAKE, M, FAKE, Np, n0, n, d, g, prec,
+                                None, None, None, sel, None, None, None, None)
+
+
+def test_nn_pool_validation(L):
+    assert nn(L, Np=0) == -1
+    assert nn(L, Np=101) == -1
+    assert nn(L, p=0) == -1
+    assert nn(L, N=0) == -1
+    assert nn(L, M=-1) == -1
+    assert nn(L, pool=None) == -1
+    assert nn(L, X=None) == -1
+    assert nn(L, p=17) == -4
+    assert nn(L, N=10**6, Np=5000) == -4
+    assert b"Np" in L.lagp_last_error()
+    assert nn(L, M=0) == 0  # no-op, no HIP call
+    assert L.lagp_last_error() == b""
+
+
+def test_alc_validation(L):
+    assert alc(L, n0=0) == -1
+    assert alc(L, n0=6, n=5) == -1
+    assert alc(L, n=11) == -1
+    assert alc(L, d=0.0) == -1
+    assert alc(L, d=float("nan")) == -1
+    assert alc(L, g=0.0) == -1
+    assert alc(L, g=float("inf")) == -1
+    assert alc(L, prec=2) == -1
+    assert alc(L, Y=None) == -1
+    assert alc(L, sel=None) == -1
+    assert alc(L, N=5000, Np=2000, n=50) == -4
+    assert alc(L, n=60, Np=100, prec=0) == -4
+    assert alc(L, p=9) == -4
+    assert alc(L, M=0) == 0
+
+
+def test_predict_validation(L):
+    r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 3, 6, 5, 10, 0.5, 1e-3, 0, FAKE,
+                           None, None, None, FAKE, None, None, None, None)
+    assert r == -1
+    r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 0, 2, 5, 10, 0.5, 1e-3, 1, FAKE,
+                           None, None, None, FAKE, None, None, None, None)
+    assert r == 0
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+
+    import paper_1310_5182_amd as lagp
+
+    with pytest.raises(ValueError):
+        lagp.nn_pool(torch.zeros(10, 2, dtype=torch.float64), torch.zeros(2, 2, dtype=torch.float64), 3)

@@ -1,0 +1,203 @@
+"""GPU path (through the C ABI) against the CPU oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import parity
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _log(name, rec):
+    print(f"[parity] {name}: {json.dumps(rec)}", flush=True)
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_log.jsonl"), "a") as f:
+        f.write(json.dumps(dict(test=name, **rec)) + "\n")
+
+
+@pytest.fixture(scope="module")
+def lagp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1310_5182_amd as lagp
+
+    print(f"[parity] library {lagp.version()} on {torch.cuda.get_device_name(0)}", flush=True)
+    return lagp
+
+
+def dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def run_gpu(lagp, W, n0, n, Np, precision, pool=None):
+    import torch
+
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    if pool is None:
+        o = lagp.alc_predict(X, Y, XX, n0, n, Np, W.d, W.g, precision)
+    else:
+        o = lagp.alc_from_pool(X, Y, XX, dev(pool), n0, n, W.d, W.g, precision)
+        o["pool"] = dev(pool)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}
+
+
+# ---------------------------------------------------------------- NN pools
+
+@pytest.mark.parametrize("case", ["config1", "config2_sub", "ragged_small", "ties"])
+def test_nn_pool_bit_exact(lagp, orc, case):
+    if case == "config1":
+        W, Np = workloads.make(1), 500
+    elif case == "config2_sub":
+        W, Np = workloads.make(2, M=40), 1000
+    elif case == "ragged_small":
+        X, Y, XX = workloads.uniform(21, 1537, 3, 19)
+        W, Np = workloads.Workload("ragged", X, Y, XX, 6, 20, 0, 0.3, 1e-4), None
+    else:
+        r = np.random.default_rng(3)
+        base = r.random((300, 2))
+        lat = np.array([[i / 8, k / 8] for i in range(9) for k in range(9)])
+        X = np.vstack([base, lat, base[:100], lat])
+        XX = np.vstack([lat[[0, 10, 40, 80]], base[[3, 7]], r.random((4, 2))])
+        W, Np = workloads.Workload("ties", X, np.zeros(len(X)), XX, 6, 20, 0, 0.3, 1e-4), None
+    for npl in ([Np] if Np else [1, 37, 500, W.N]):
+        print(f"[parity] nn_pool {case} N={W.N} p={W.p} M={W.M} Np={npl}", flush=True)
+        import torch
+
+        got = lagp.nn_pool(dev(W.X), dev(W.XX), npl)
+        torch.cuda.synchronize()
+        want = orc.nn_pool(W.X, W.XX, npl)
+        assert np.array_equal(got.cpu().numpy(), want), (case, npl)
+
+
+# ---------------------------------------------------------------- ALC designs
+
+def check_alc(orc, W, g, n0, n, Np, precision, tau_out, name, expect_ties_max=None):
+    forced = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n, W.d, W.g, forced=g["sel"], mode_b=True)
+    assert np.all(g["status"] == 0), np.unique(g["status"], return_counts=True)
+    assert np.all(forced["status"] == 0)
+    seq = parity.sequence_check(g["sel"], g["pool"], forced, n0)
+    # alc output = the oracle's score of the same choice on the same prefix, to
+    # within the larger of a fixed floor and 10x the oracle's route noise
+    a_rel = np.abs(g["alc"][:, n0:] - forced["dsel"][:, n0:]) / forced["dmax"][:, n0:]
+    a_tol = np.maximum(1e-9, 10 * forced["nu"][:, n0:])
+    a_excess = float(np.max(a_rel / a_tol)) if a_rel.size else 0.0
+    assert np.all(np.isnan(g["alc"][:, :n0]))
+    mean_floor = 1e-6 * np.sqrt(np.mean(W.Y ** 2))
+    worst, rep = parity.output_check(g, forced, W.X, W.d, W.g, tau_out, mean_floor)
+    free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n, W.d, W.g)
+    same_seq = int(np.sum(np.all(free["sel"] == g["sel"], axis=1)))
+    rec = dict(precision=precision, M=W.M, N=W.N, p=W.p, n=n, Np=Np, ties=seq["ties"],
+               max_tie_r=seq["max_r"], fails=len(seq["fails"]), same_sequence=same_seq,
+               alc_max_rel=float(np.max(a_rel)) if a_rel.size else 0.0, alc_excess=a_excess,
+               outputs=rep, worst_over_tol=worst,
+               guard_steps=int(g["guard"].sum()))
+    _log(name, rec)
+    assert not seq["fails"], seq["fails"][:5]
+    assert worst <= 1.0, rep
+    assert a_excess <= 1.0
+    if expect_ties_max is not None:
+        assert seq["ties"] <= expect_ties_max
+    return rec
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_alc_config2_subset(lagp, orc, precision):
+    W = workloads.make(2, M=64)
+    print(f"[parity] alc config2 M=64 {precision}", flush=True)
+    g = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
+    assert np.array_equal(g["pool"], orc.nn_pool(W.X, W.XX, W.Np))
+    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-10 if precision == "fp64" else 1e-4,
+              f"config2_M64_{precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_alc_config1_full(lagp, orc, precision):
+    W = workloads.make(1)
+    print(f"[parity] alc config1 full {precision}", flush=True)
+    g = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
+    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-10 if precision == "fp64" else 1e-4,
+              f"config1_full_{precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["n0_eq_n", "Np_eq_n", "ragged_Np", "max_Np", "max_n", "p1", "M1"])
+def test_alc_edge_shapes(lagp, orc, precision, shape):
+    base = dict(N=3000, M=24, n0=6, n=20, Np=200)
+    cfg = 2
+    if shape == "n0_eq_n":
+        base.update(n0=12, n=12)
+    elif shape == "Np_eq_n":
+        base.update(n=30, Np=30)
+    elif shape == "ragged_Np":
+        base.update(Np=333, n=37)
+    elif shape == "max_Np":
+        base.update(Np=1024, n=40, N=20000, M=8)
+    elif shape == "max_n":
+        base.update(n=52 if precision == "fp64" else 64, Np=700, N=20000, M=8)
+    elif shape == "M1":
+        base.update(M=1)
+    if shape == "p1":
+        X, Y, XX = workloads.uniform(5, 2000, 1, 16)
+        W = workloads.Workload("p1", X, Y, XX, 6, 20, 200, 0.05, 1e-4)
+    else:
+        W = workloads.make(cfg, N=base["N"], M=base["M"])
+    n0, n, Np = base["n0"], base["n"], base["Np"]
+    print(f"[parity] alc edge {shape} {precision} N={W.N} M={W.M} n0={n0} n={n} Np={Np}", flush=True)
+    g = run_gpu(lagp, W, n0, n, Np, precision)
+    rec = check_alc(orc, W, g, n0, n, Np, precision, 1e-9 if precision == "fp64" else 1e-4,
+                    f"edge_{shape}_{precision}")
+    if shape == "Np_eq_n":
+        for m in range(W.M):
+            assert sorted(g["sel"][m]) == sorted(g["pool"][m])
+    assert rec["fails"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_determinism_and_permutation(lagp, precision):
+    W = workloads.make(2, N=20000, M=40)
+    a = run_gpu(lagp, W, 6, 30, 400, precision)
+    b = run_gpu(lagp, W, 6, 30, 400, precision)
+    perm = np.random.default_rng(2).permutation(W.M)
+    Wp = workloads.Workload("perm", W.X, W.Y, W.XX[perm], 6, 30, 400, W.d, W.g)
+    c = run_gpu(lagp, Wp, 6, 30, 400, precision)
+    for k in ("pool", "sel", "mean", "s2", "var", "alc", "status", "guard"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+        assert np.array_equal(a[k][perm], c[k], equal_nan=True), k
+
+
+def test_predict_equals_pool_then_design(lagp):
+    W = workloads.make(2, N=20000, M=16)
+    a = run_gpu(lagp, W, 6, 30, 400, "fp64")
+    b = run_gpu(lagp, W, 6, 30, 400, "fp64", pool=a["pool"])
+    for k in ("sel", "mean", "s2", "alc"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_bad_pool_and_nonfinite_location(lagp):
+    W = workloads.make(2, N=5000, M=6)
+    XX = W.XX.copy()
+    XX[2, 3] = np.nan
+    Wn = workloads.Workload("nan", W.X, W.Y, XX, 6, 20, 200, W.d, W.g)
+    pool = np.tile(np.arange(200, dtype=np.int32), (6, 1))
+    pool[4, 50] = -7
+    pool[5, 199] = W.N
+    g = run_gpu(lagp, Wn, 6, 20, 200, "fp64", pool=pool)
+    assert list(g["status"]) == [0, 0, 3, 0, 4, 4]
+    for m in (2, 4, 5):
+        assert np.isnan(g["mean"][m]) and np.isnan(g["s2"][m])
+        assert np.all(g["sel"][m] == -1)
+    assert np.all(np.isfinite(g["mean"][[0, 1, 3]]))
