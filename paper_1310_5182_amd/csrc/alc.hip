@@ -20,6 +20,12 @@
 // is a chain of MFMAs over the non-zero (lower-triangular) tiles of R_j, and
 // the epilogue folds z.z and z.z_h straight out of the accumulators.
 //
+// One greedy step: (1) every wave scores its candidates on the matrix cores
+// and reduces its argmax; (2) each wave re-scores in float64 its own members
+// of the near-best band (mixed) or the winner (float64), keeping its best z
+// vector in LDS; (3) all waves border R_j with the winning z and append z_h,
+// R Y and the new Q column.  Three workgroup barriers per step.
+//
 // Precision.  LAGP_FP64 runs the MFMA in float64.  LAGP_MIXED keeps Q and a
 // float32 copy of R_j for float32 MFMA scoring; the float64 master R_j, the
 // re-score of every candidate within kBandTau of the float32 best, the Schur
@@ -57,8 +63,8 @@ struct Mma<double> {
     }
 };
 
-constexpr int kBandCap = 32;
-constexpr float kBandTau = 1.0f / 64;
+constexpr int kWaveBandCap = 6;        // band members a step may re-score before falling back
+constexpr float kBandTau = 1.0f / 64;  // float32 scores within this of the best are re-scored
 constexpr double kTrustErr = 1.0 / 256;
 constexpr float kSmallS = 1.0f / 131072;
 constexpr int kPmax = 8;
@@ -72,27 +78,26 @@ __device__ __forceinline__ int ridx(int i, int l)
     return ((i >> 4) * KG + (l >> 2)) * 64 + (i & 15) + 16 * (l & 3);
 }
 
-// Float64 score of candidate `slot` by one wave (lane i computes z_i):
-// returns Delta (or -1 if the conditional variance is not positive) and the
-// conditional variance in s_out; writes z to zout[lane] when zout != nullptr.
+// Float64 z = R_j K(X_j, c) for candidate `slot` by one wave (lane i owns
+// z_i).  The j-loop is unrolled by four so the LDS loads overlap.
 template <int SLOTS, int KG>
-__device__ __forceinline__ double wave_score64(const double *cx, const int32_t *selslot,
-                                               const double *RM, const double *zh,
-                                               const double *cxv, int slot, int j, int p,
-                                               double d, double kappa, int lane, double *zout,
-                                               double &s_out)
+__device__ __forceinline__ double wave_z64(const double *cx, const int32_t *selslot, const double *RM,
+                                           int slot, int j, int p, double d, int lane)
 {
     double kl = 0.0;
     if (lane < j) kl = corr64(sqdist_strict(cx + selslot[lane], SLOTS, cx + slot, SLOTS, p), d);
-    double z = 0.0;
-    for (int l = 0; l < j; l++) z = fma(RM[ridx<KG>(lane, l)], readlane(kl, l), z);
-    if (zout) zout[lane] = z;
-    const double ss = wave_sum(z * z);
-    const double zz = wave_sum(z * zh[lane]);
-    const double s = kappa - ss;
-    const double cov = cxv[slot] - zz;
-    s_out = s;
-    return s > 0.0 ? cov * cov / s : -1.0;
+    double z0 = 0.0, z1 = 0.0;
+    int l = 0;
+    for (; l + 4 <= j; l += 4) {
+        const double r0 = RM[ridx<KG>(lane, l)], r1 = RM[ridx<KG>(lane, l + 1)];
+        const double r2 = RM[ridx<KG>(lane, l + 2)], r3 = RM[ridx<KG>(lane, l + 3)];
+        z0 = fma(r0, readlane(kl, l), z0);
+        z1 = fma(r1, readlane(kl, l + 1), z1);
+        z0 = fma(r2, readlane(kl, l + 2), z0);
+        z1 = fma(r3, readlane(kl, l + 3), z1);
+    }
+    for (; l < j; l++) z0 = fma(RM[ridx<KG>(lane, l)], readlane(kl, l), z0);
+    return z0 + z1;
 }
 
 template <typename T, int NW, int CBW, int KG, int G>
@@ -101,32 +106,31 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     using Acc = typename Mma<T>::acc;
     constexpr int kThreads = NW * kWave;
     constexpr int SLOTS = NW * CBW * 16;
+    constexpr int WSLOTS = CBW * 16;  // candidates per wave
     constexpr int NMAX = 4 * KG;
     constexpr int NIB = (NMAX + 15) / 16;
     constexpr int ROWS = NIB * 16;
     constexpr int RT = NIB * KG * 64;
     constexpr bool MIXED = sizeof(T) == 4;
     static_assert(ROWS == 64, "one lane per row of R in the wave-level float64 routines");
-    static_assert(CBW % G == 0, "column blocks come in groups of G");
+    static_assert(CBW % G == 0 && WSLOTS % kWave == 0, "candidate blocks tile the wave");
 
-    __shared__ double RM[RT];                  // float64 R_j, A-fragment tiles
-    __shared__ float RA32[MIXED ? RT : 1];     // float32 copy of R_j (mixed)
-    __shared__ double cx[kPmax * SLOTS];       // candidate coordinates, [k][slot]
-    __shared__ double cxv[SLOTS];              // K(candidate, x)
-    __shared__ int32_t cid[SLOTS];             // design index of each slot
-    __shared__ uint8_t cflag[SLOTS];           // 0 candidate, 1 in design, 2 empty
-    __shared__ float sc32[MIXED ? SLOTS : 1];  // float32 scores (mixed)
-    __shared__ double zh[ROWS], tY[ROWS], ell[ROWS];
+    __shared__ double RM[RT];               // float64 R_j, A-fragment tiles
+    __shared__ float RA32[MIXED ? RT : 1];  // float32 copy of R_j (mixed)
+    __shared__ double cx[kPmax * SLOTS];    // candidate coordinates, [k][slot]
+    __shared__ double cxv[SLOTS];           // K(candidate, x)
+    __shared__ int32_t cid[SLOTS];          // design index of each slot
+    __shared__ uint8_t cflag[SLOTS];        // 0 candidate, 1 in design, 2 empty
+    __shared__ double zh[ROWS], tY[ROWS];   // R_j K(X_j, x) and R_j Y_j
     __shared__ float zh32[MIXED ? ROWS : 1];
+    __shared__ double zbest[NW][ROWS];      // each wave's best re-scored z
     __shared__ double xs[kPmax];
     __shared__ int32_t selslot[NMAX];
     __shared__ T red_s[NW];
-    __shared__ double red64[NW];
     __shared__ int32_t red_i[NW], red_k[NW];
-    __shared__ int32_t band_slot[kBandCap];
-    __shared__ double band_val[kBandCap];
-    __shared__ int band_cnt, ctl_status, ctl_susp;
-    __shared__ double ctl_sstar, ctl_alc;
+    __shared__ double rec_v[NW], rec_s[NW], rec_e[NW];
+    __shared__ int32_t rec_i[NW], rec_k[NW], rec_n[NW];
+    __shared__ int ctl_status, ctl_susp;
 
     const T *RA;
     const T *zhT;
@@ -142,12 +146,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     const int64_t m = blockIdx.x;
     const int p = a.p, Np = a.Np, n = a.n, n0 = a.n0;
     const double d = a.d, kappa = 1.0 + a.g;
-    const int wbase = w * CBW * 16;
+    const int wbase = w * WSLOTS;
 
     // ---- stage the location, its pool and zeroed factors in LDS
     if (tid == 0) {
         ctl_status = kLocOk;
-        band_cnt = 0;
         ctl_susp = 0;
     }
     if (tid < p) xs[tid] = a.XX[m * p + tid];
@@ -171,7 +174,6 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     for (int i = tid; i < ROWS; i += kThreads) {
         zh[i] = 0.0;
         tY[i] = 0.0;
-        ell[i] = 0.0;
         if constexpr (MIXED) zh32[i] = 0.0f;
     }
     __syncthreads();
@@ -191,54 +193,50 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     for (int cb = 0; cb < CBW; cb++)
 #pragma unroll
         for (int kg = 0; kg < KG; kg++) Q[cb][kg] = (T)0;
+    T sc[MIXED ? CBW : 1];  // float32 score of candidate lane % 16 of each block (mixed)
 
     for (; status == kLocOk && j < n; j++) {
-        int win = j;  // X_{n0}: the nearest n0 pool entries, in pool order
+        // ===== (1) score every candidate: Z^T = R_j Q^T on the matrix cores
+        T bs = (T)0;
+        int win_hint = j;  // the float64 path's winner; slot j for the NN start
         if (j >= n0) {
-            // ===== score every candidate: Z^T = R_j Q^T on the matrix cores
             T best_s = (T)-1;
             int32_t best_i = INT32_MAX, best_k = -1;
             bool susp = false;
+            const int nib = (j + 15) >> 4;
 #pragma unroll
             for (int cg = 0; cg < CBW; cg += G) {
                 T sp[G], cp[G];
 #pragma unroll
                 for (int q = 0; q < G; q++) sp[q] = cp[q] = (T)0;
-                const int nib = (j + 15) >> 4;
 #pragma unroll 1
                 for (int ib = 0; ib < nib; ib++) {
-                    {
-                        Acc acc[G];
+                    Acc acc[G];
 #pragma unroll
-                        for (int q = 0; q < G; q++) acc[q] = Acc{0, 0, 0, 0};
+                    for (int q = 0; q < G; q++) acc[q] = Acc{0, 0, 0, 0};
 #pragma unroll
-                        for (int kg = 0; kg < KG; kg++) {
-                            if (kg * 4 < j && kg <= ib * 4 + 3) {
-                                const T av = RA[(ib * KG + kg) * 64 + lane];
+                    for (int kg = 0; kg < KG; kg++) {
+                        if (kg * 4 < j && kg <= ib * 4 + 3) {
+                            const T av = RA[(ib * KG + kg) * 64 + lane];
 #pragma unroll
-                                for (int q = 0; q < G; q++) acc[q] = Mma<T>::run(av, Q[cg + q][kg], acc[q]);
-                            }
+                            for (int q = 0; q < G; q++) acc[q] = Mma<T>::run(av, Q[cg + q][kg], acc[q]);
                         }
+                    }
 #pragma unroll
-                        for (int r = 0; r < 4; r++) {
-                            const T zr = zhT[ib * 16 + Mma<T>::row(lane, r)];
+                    for (int r = 0; r < 4; r++) {
+                        const T zr = zhT[ib * 16 + Mma<T>::row(lane, r)];
 #pragma unroll
-                            for (int q = 0; q < G; q++) {
-                                const T z = acc[q][r];
-                                sp[q] += z * z;
-                                cp[q] += z * zr;
-                            }
+                        for (int q = 0; q < G; q++) {
+                            const T z = acc[q][r];
+                            sp[q] += z * z;
+                            cp[q] += z * zr;
                         }
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < G; q++) {
-                    T s_ = sp[q];
-                    s_ += __shfl_xor(s_, 16, kWave);
-                    s_ += __shfl_xor(s_, 32, kWave);
-                    T c_ = cp[q];
-                    c_ += __shfl_xor(c_, 16, kWave);
-                    c_ += __shfl_xor(c_, 32, kWave);
+                    const T s_ = row_sum4(sp[q]);
+                    const T c_ = row_sum4(cp[q]);
                     const int slot = wbase + (cg + q) * 16 + (lane & 15);
                     const bool live = cflag[slot] == 0;
                     const T sv = (T)kappa - s_;
@@ -246,7 +244,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                     const T score = (live && sv > (T)0) ? cv * cv / sv : (T)-1;
                     if constexpr (MIXED) {
                         if (live && !(sv > kSmallS * (float)kappa)) susp = true;
-                        if (lane < 16) sc32[slot] = score;
+                        sc[cg + q] = score;
                     }
                     const int32_t di = score >= (T)0 ? cid[slot] : INT32_MAX;
                     if (beats(score, di, best_s, best_i)) {
@@ -265,154 +263,167 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             if constexpr (MIXED)
                 if (susp) ctl_susp = 1;
             __syncthreads();
-            T bs = red_s[0];
+            bs = red_s[0];
             int32_t bi = red_i[0];
-            win = red_k[0];
+            win_hint = red_k[0];
             for (int q = 1; q < NW; q++)
                 if (beats(red_s[q], red_i[q], bs, bi)) {
                     bs = red_s[q];
                     bi = red_i[q];
-                    win = red_k[q];
+                    win_hint = red_k[q];
                 }
-            if (bs < (T)0) win = -1;
-
-            if constexpr (MIXED) {
-                // ===== float64 re-score of the near-best float32 band
-                bool fallback = ctl_susp != 0 || !(bs > 0.0f);
-                win = -1;
-                if (!fallback) {
-                    const float thr = bs * (1.0f - kBandTau);
-                    for (int s = tid; s < SLOTS; s += kThreads)
-                        if (sc32[s] >= thr) {
-                            const int pos = atomicAdd(&band_cnt, 1);
-                            if (pos < kBandCap) band_slot[pos] = s;
-                        }
-                    __syncthreads();
-                    const int cnt = band_cnt;
-                    if (cnt <= kBandCap) {
-                        for (int b = w; b < cnt; b += NW) {
-                            double sdummy;
-                            const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, band_slot[b], j, p, d,
-                                                                     kappa, lane, nullptr, sdummy);
-                            if (lane == 0) band_val[b] = v;
-                        }
-                        __syncthreads();
-                        double b64 = -1.0, err = 0.0;
-                        int32_t bi64 = INT32_MAX;
-                        int bk64 = -1;
-                        for (int b = 0; b < cnt; b++) {
-                            const int s = band_slot[b];
-                            const double v = band_val[b];
-                            if (beats(v, cid[s], b64, bi64)) {
-                                b64 = v;
-                                bi64 = cid[s];
-                                bk64 = s;
-                            }
-                            err = v > 0.0 ? fmax(err, fabs((double)sc32[s] - v) / v) : INFINITY;
-                        }
-                        if (b64 > 0.0 && err <= kTrustErr)
-                            win = bk64;
-                        else
-                            fallback = true;
-                    } else {
-                        fallback = true;
-                    }
-                }
-                if (fallback) {
-                    // ===== the whole step in float64, one candidate per wave at a time
-                    double fb = -1.0;
-                    int32_t fi = INT32_MAX;
-                    int fk = -1;
-                    for (int s = w; s < SLOTS; s += NW) {
-                        if (cflag[s] != 0) continue;
-                        double sdummy;
-                        const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, s, j, p, d, kappa, lane,
-                                                                 nullptr, sdummy);
-                        if (beats(v, v >= 0.0 ? cid[s] : INT32_MAX, fb, fi)) {
-                            fb = v;
-                            fi = cid[s];
-                            fk = s;
-                        }
-                    }
-                    __syncthreads();
-                    if (lane == 0) {
-                        red64[w] = fb;
-                        red_i[w] = fi;
-                        red_k[w] = fk;
-                    }
-                    __syncthreads();
-                    fb = red64[0];
-                    fi = red_i[0];
-                    win = red_k[0];
-                    for (int q = 1; q < NW; q++)
-                        if (beats(red64[q], red_i[q], fb, fi)) {
-                            fb = red64[q];
-                            fi = red_i[q];
-                            win = red_k[q];
-                        }
-                    if (fb < 0.0) win = -1;
-                    guard_steps++;
-                }
-            }
-            if (win < 0) {  // no candidate with a positive conditional variance
+            if (!(bs >= (T)0)) {  // no candidate with a positive conditional variance
                 status = kLocStepFail;
                 break;
             }
         }
 
-        // ===== float64 update: l = R_j k*, s*, border R, z_h and R Y
-        if (w == 0) {
-            double sstar;
-            const double v = wave_score64<SLOTS, KG>(cx, selslot, RM, zh, cxv, win, j, p, d, kappa, lane, ell, sstar);
-            const double zt = wave_sum(ell[lane] * tY[lane]);
-            const double zz = wave_sum(ell[lane] * zh[lane]);
-            if (lane == 0) {
-                ctl_sstar = sstar;
-                ctl_alc = j >= n0 ? v : NAN;
-                if (!(sstar > 0.0) || !isfinite(sstar)) {
-                    ctl_status = j < n0 ? kLocInitNotPd : kLocStepFail;
-                } else {
-                    const double lam = sqrt(sstar);
-                    zh[j] = (cxv[win] - zz) / lam;
-                    tY[j] = (a.Y[cid[win]] - zt) / lam;
-                    if constexpr (MIXED) zh32[j] = (float)zh[j];
+        // ===== (2) float64 re-score: each wave its own band members
+        bool fallback = false;
+        if constexpr (MIXED) fallback = j >= n0 && ctl_susp != 0;
+        double bv = -1.0, bsv = 0.0, err = 0.0;
+        int32_t bi64 = INT32_MAX;
+        int bk = -1, cnt = 0;
+        auto consider = [&](int slot, double v32) {
+            const double z = wave_z64<SLOTS, KG>(cx, selslot, RM, slot, j, p, d, lane);
+            const double s = kappa - wave_sum(z * z);
+            const double cov = cxv[slot] - wave_sum(z * zh[lane]);
+            const double v = s > 0.0 ? cov * cov / s : -1.0;
+            const int32_t di = v >= 0.0 ? cid[slot] : INT32_MAX;
+            if (v32 >= 0.0) err = v > 0.0 ? fmax(err, fabs(v32 - v) / v) : INFINITY;
+            if (beats(v, di, bv, bi64)) {
+                bv = v;
+                bi64 = di;
+                bk = slot;
+                bsv = s;
+                zbest[w][lane] = z;
+            }
+        };
+        if (j < n0 || !MIXED) {
+            if (win_hint >= wbase && win_hint < wbase + WSLOTS) consider(win_hint, -1.0);
+        } else if (!fallback) {
+            if constexpr (MIXED) {
+                const float thr = (float)bs * (1.0f - kBandTau);
+#pragma unroll
+                for (int cb = 0; cb < CBW; cb++) {
+                    unsigned long long mask = __ballot(lane < 16 && sc[cb] >= thr);
+                    while (mask) {
+                        const int b = __builtin_ctzll(mask);
+                        mask &= mask - 1;
+                        if (++cnt > kWaveBandCap) break;
+                        const float v32 = __builtin_bit_cast(
+                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(unsigned, sc[cb]), b));
+                        consider(wbase + cb * 16 + b, (double)v32);
+                    }
                 }
-                band_cnt = 0;
+            }
+        }
+        if (lane == 0) {
+            rec_v[w] = bv;
+            rec_s[w] = bsv;
+            rec_e[w] = err;
+            rec_i[w] = bi64;
+            rec_k[w] = bk;
+            rec_n[w] = cnt;
+        }
+        __syncthreads();
+        double v = rec_v[0];
+        int32_t vi = rec_i[0];
+        int vw = 0, total = 0;
+        err = 0.0;
+        for (int q = 0; q < NW; q++) {
+            if (q > 0 && beats(rec_v[q], rec_i[q], v, vi)) {
+                v = rec_v[q];
+                vi = rec_i[q];
+                vw = q;
+            }
+            err = fmax(err, rec_e[q]);
+            total += rec_n[q];
+        }
+        if constexpr (MIXED)
+            if (j >= n0 && !fallback && (!(v > 0.0) || err > kTrustErr || total > kWaveBandCap)) fallback = true;
+        if (fallback) {
+            // ===== the whole step in float64: each wave re-scores all its live candidates
+            __syncthreads();
+            bv = -1.0;
+            bi64 = INT32_MAX;
+            bk = -1;
+            for (int s = wbase; s < wbase + WSLOTS; s++)
+                if (cflag[s] == 0) consider(s, -1.0);
+            if (lane == 0) {
+                rec_v[w] = bv;
+                rec_s[w] = bsv;
+                rec_i[w] = bi64;
+                rec_k[w] = bk;
+            }
+            __syncthreads();
+            v = rec_v[0];
+            vi = rec_i[0];
+            vw = 0;
+            for (int q = 1; q < NW; q++)
+                if (beats(rec_v[q], rec_i[q], v, vi)) {
+                    v = rec_v[q];
+                    vi = rec_i[q];
+                    vw = q;
+                }
+            guard_steps++;
+        }
+
+        // ===== (3) float64 update with l = zbest[vw] and s* = rec_s[vw]
+        const int win = rec_k[vw];
+        const double sstar = rec_s[vw];
+        if (win < 0 || !(sstar > 0.0) || !isfinite(sstar)) {
+            status = j < n0 ? kLocInitNotPd : kLocStepFail;
+            break;
+        }
+        const double lam = sqrt(sstar);
+        const double *ell = zbest[vw];
+        // new row of R: r_l = -(sum_{i=l}^{j-1} l_i R(i, l)) / lam, r_j = 1 / lam
+        constexpr int COLS = (ROWS + NW - 1) / NW;
+#pragma unroll
+        for (int c = 0; c < COLS; c++) {
+            const int l = w + c * NW;
+            if (l <= j) {
+                const double prod = lane < j ? ell[lane] * RM[ridx<KG>(lane, l)] : 0.0;
+                const double sum = wave_sum(prod);
+                if (lane == 0) {
+                    const double r = l < j ? -sum / lam : 1.0 / lam;
+                    RM[ridx<KG>(j, l)] = r;
+                    if constexpr (MIXED) RA32[ridx<KG>(j, l)] = (float)r;
+                }
+            }
+        }
+        if (w == 0) {
+            const double zz = wave_sum(ell[lane] * zh[lane]);
+            const double zt = wave_sum(ell[lane] * tY[lane]);
+            if (lane == 0) {
+                zh[j] = (cxv[win] - zz) / lam;
+                tY[j] = (a.Y[cid[win]] - zt) / lam;
+                if constexpr (MIXED) zh32[j] = (float)zh[j];
+                cflag[win] = 1;
+                selslot[j] = win;
+                a.sel[m * n + j] = cid[win];
+                if (a.alc) a.alc[m * n + j] = j >= n0 ? v : NAN;
                 ctl_susp = 0;
             }
         }
-        __syncthreads();
-        status = ctl_status;
-        if (status != kLocOk) break;
-
-        const double lam = sqrt(ctl_sstar);
-        for (int l = w; l <= j; l += NW) {
-            const double prod = lane < j ? ell[lane] * RM[ridx<KG>(lane, l)] : 0.0;
-            const double sum = wave_sum(prod);
-            if (lane == 0) {
-                const double r = l < j ? -sum / lam : 1.0 / lam;
-                RM[ridx<KG>(j, l)] = r;
-                if constexpr (MIXED) RA32[ridx<KG>(j, l)] = (float)r;
-            }
-        }
-        if (tid == 0) {
-            cflag[win] = 1;
-            selslot[j] = win;
-            a.sel[m * n + j] = cid[win];
-            if (a.alc) a.alc[m * n + j] = ctl_alc;
-        }
-        // new column j of Q: K(candidate, x*)
+        // new column j of Q, K(candidate, x*): one candidate per lane, then moved
+        // into its B-operand place (lanes of group j % 4, register j / 4)
         {
             const int kgj = j >> 2;
-            if ((lane >> 4) == (j & 3)) {
+            const bool mine = (lane >> 4) == (j & 3);
 #pragma unroll
-                for (int cb = 0; cb < CBW; cb++) {
-                    const int slot = wbase + cb * 16 + (lane & 15);
-                    double v = 0.0;
-                    if (slot < Np) v = corr64(sqdist_strict(cx + slot, SLOTS, cx + win, SLOTS, p), d);
+            for (int t = 0; t < CBW / 4; t++) {
+                const int slot = wbase + t * kWave + lane;
+                const double v64 =
+                    slot < Np ? corr64(sqdist_strict(cx + slot, SLOTS, cx + win, SLOTS, p), d) : 0.0;
+                const T vt = (T)v64;
+#pragma unroll
+                for (int c4 = 0; c4 < 4; c4++) {
+                    const T moved = __shfl(vt, c4 * 16 + (lane & 15), kWave);
 #pragma unroll
                     for (int q = 0; q < KG; q++)
-                        if (q == kgj) Q[cb][q] = (T)v;
+                        if (q == kgj && mine) Q[t * 4 + c4][q] = moved;
                 }
             }
         }
@@ -429,8 +440,8 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         const double zz = wave_sum(zi * zi);
         if (lane == 0) {
             const bool ok = status == kLocOk;
-            const double v = kappa - zz;
-            const double s2 = psi * v / n;
+            const double vv = kappa - zz;
+            const double s2 = psi * vv / n;
             if (a.mean) a.mean[m] = ok ? mu : NAN;
             if (a.s2) a.s2[m] = ok ? s2 : NAN;
             if (a.var) a.var[m] = (ok && n > 2) ? s2 * n / (n - 2) : NAN;
@@ -444,11 +455,6 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             }
     }
 }
-
-struct Sched {
-    int slots;
-    int nmax;
-};
 
 template <typename T, int NW, int CBW, int KG, int G>
 static hipError_t launch_t(const AlcArgs &a, hipStream_t st)

@@ -32,18 +32,95 @@ __device__ __forceinline__ double corr64(double r2, double d)
     return exp(-r2 / d);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Score candidate ordering: larger score wins, equal scores go to the smaller
+// design index.  Invalid entries carry score -1 and index INT32_MAX.
+template <typename T>
+__device__ __forceinline__ bool beats(T s1, int i1, T s2, int i2)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    return s1 > s2 || (s1 == s2 && i1 < i2);
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// ---- lane exchanges on the VALU (no LDS crossbar), for full-wave reductions.
+// Stage S pairs every lane with one partner; after stages 0..5 every lane has
+// combined all 64 lanes.  xchg<S>(v) returns (a, b): for stages 0-3 (DPP) a is
+// the lane's own word and b its partner's; for stages 4-5 (permlane swaps) a is
+// the even row's (lower half's) word and b the odd row's (upper half's), the
+// same pair in both lanes.  A combine(a, b) that is symmetric in its operands
+// (IEEE addition, a strict-order argmax) therefore gives every lane of a pair
+// the same bits, so results are identical across lanes and runs.
+struct Pair32 {
+    unsigned a, b;
+};
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int S>
+__device__ __forceinline__ Pair32 xchg(unsigned v)
+{
+    if constexpr (S == 0) {
+        return {v, dpp_u32<0xB1>(v)};  // quad_perm [1,0,3,2]: lane ^ 1
+    } else if constexpr (S == 1) {
+        return {v, dpp_u32<0x4E>(v)};  // quad_perm [2,3,0,1]: lane ^ 2
+    } else if constexpr (S == 2) {
+        return {v, dpp_u32<0x141>(v)};  // row_half_mirror: i <-> 7 - i in each 8
+    } else if constexpr (S == 3) {
+        return {v, dpp_u32<0x140>(v)};  // row_mirror: i <-> 15 - i in each 16
+    } else if constexpr (S == 4) {
+        auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // rows 0<->1, 2<->3
+        return {r[0], r[1]};
+    } else {
+        auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);  // halves
+        return {r[0], r[1]};
+    }
+}
+
+struct PairF64 {
+    double a, b;
+};
+
+template <int S>
+__device__ __forceinline__ PairF64 xchg(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const Pair32 lo = xchg<S>((unsigned)u), hi = xchg<S>((unsigned)(u >> 32));
+    return {__builtin_bit_cast(double, ((unsigned long long)hi.a << 32) | lo.a),
+            __builtin_bit_cast(double, ((unsigned long long)hi.b << 32) | lo.b)};
+}
+
+template <int S>
+__device__ __forceinline__ float xsum(float v)
+{
+    const Pair32 p = xchg<S>(__builtin_bit_cast(unsigned, v));
+    return __builtin_bit_cast(float, p.a) + __builtin_bit_cast(float, p.b);
+}
+
+template <int S>
+__device__ __forceinline__ double xsum(double v)
+{
+    const PairF64 p = xchg<S>(v);
+    return p.a + p.b;
+}
+
+// Sum over the four 16-lane rows (lanes l, l^16, l^32, l^48 hold partials).
+template <typename T>
+__device__ __forceinline__ T row_sum4(T v)
+{
+    return xsum<5>(xsum<4>(v));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    v = xsum<0>(v);
+    v = xsum<1>(v);
+    v = xsum<2>(v);
+    v = xsum<3>(v);
+    v = xsum<4>(v);
+    return xsum<5>(v);
 }
 
 // Broadcast lane `l` (wave-uniform) of a double.
@@ -55,29 +132,39 @@ __device__ __forceinline__ double readlane(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Score candidate ordering: larger score wins, equal scores go to the smaller
-// design index.  Invalid entries carry score -1 and index INT32_MAX.
-template <typename T>
-__device__ __forceinline__ bool beats(T s1, int i1, T s2, int i2)
+template <int S>
+__device__ __forceinline__ void argmax_stage(float &s, int &idx, int &slot)
 {
-    return s1 > s2 || (s1 == s2 && i1 < i2);
+    const Pair32 ps = xchg<S>(__builtin_bit_cast(unsigned, s));
+    const Pair32 pi = xchg<S>((unsigned)idx), pk = xchg<S>((unsigned)slot);
+    const float sa = __builtin_bit_cast(float, ps.a), sb = __builtin_bit_cast(float, ps.b);
+    const bool take_b = beats(sb, (int)pi.b, sa, (int)pi.a);
+    s = take_b ? sb : sa;
+    idx = (int)(take_b ? pi.b : pi.a);
+    slot = (int)(take_b ? pk.b : pk.a);
 }
 
-// Wave-wide argmax of (score, design index, slot).
+template <int S>
+__device__ __forceinline__ void argmax_stage(double &s, int &idx, int &slot)
+{
+    const PairF64 ps = xchg<S>(s);
+    const Pair32 pi = xchg<S>((unsigned)idx), pk = xchg<S>((unsigned)slot);
+    const bool take_b = beats(ps.b, (int)pi.b, ps.a, (int)pi.a);
+    s = take_b ? ps.b : ps.a;
+    idx = (int)(take_b ? pi.b : pi.a);
+    slot = (int)(take_b ? pk.b : pk.a);
+}
+
+// Wave-wide argmax of (score, design index, slot); every lane gets the result.
 template <typename T>
 __device__ __forceinline__ void wave_argmax(T &s, int &idx, int &slot)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T s2 = __shfl_xor(s, o, kWave);
-        int i2 = __shfl_xor(idx, o, kWave);
-        int k2 = __shfl_xor(slot, o, kWave);
-        if (beats(s2, i2, s, idx)) {
-            s = s2;
-            idx = i2;
-            slot = k2;
-        }
-    }
+    argmax_stage<0>(s, idx, slot);
+    argmax_stage<1>(s, idx, slot);
+    argmax_stage<2>(s, idx, slot);
+    argmax_stage<3>(s, idx, slot);
+    argmax_stage<4>(s, idx, slot);
+    argmax_stage<5>(s, idx, slot);
 }
 
 }  // namespace lagp

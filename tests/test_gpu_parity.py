@@ -57,12 +57,21 @@ def run_gpu(lagp, W, n0, n, Np, precision, pool=None):
 
 # ---------------------------------------------------------------- NN pools
 
-@pytest.mark.parametrize("case", ["config1", "config2_sub", "ragged_small", "ties"])
+@pytest.mark.parametrize("case", ["config1", "config2_sub", "config3_Np2000", "ragged_small", "ties",
+                                  "identical_rows"])
 def test_nn_pool_bit_exact(lagp, orc, case):
     if case == "config1":
         W, Np = workloads.make(1), 500
     elif case == "config2_sub":
         W, Np = workloads.make(2, M=40), 1000
+    elif case == "config3_Np2000":
+        W, Np = workloads.make(3, N=30000, M=12), 2000
+    elif case == "identical_rows":
+        # thousands of exactly equal distances: the selection falls to the index digits
+        r = np.random.default_rng(4)
+        X = np.vstack([np.tile(r.random((1, 3)), (5000, 1)), r.random((300, 3))])
+        XX = np.vstack([X[:1], X[5000:5002], r.random((3, 3))])
+        W, Np = workloads.Workload("identical", X, np.zeros(len(X)), XX, 6, 20, 0, 0.3, 1e-4), None
     elif case == "ragged_small":
         X, Y, XX = workloads.uniform(21, 1537, 3, 19)
         W, Np = workloads.Workload("ragged", X, Y, XX, 6, 20, 0, 0.3, 1e-4), None
@@ -73,7 +82,8 @@ def test_nn_pool_bit_exact(lagp, orc, case):
         X = np.vstack([base, lat, base[:100], lat])
         XX = np.vstack([lat[[0, 10, 40, 80]], base[[3, 7]], r.random((4, 2))])
         W, Np = workloads.Workload("ties", X, np.zeros(len(X)), XX, 6, 20, 0, 0.3, 1e-4), None
-    for npl in ([Np] if Np else [1, 37, 500, W.N]):
+    sizes = [Np] if Np else [1, 37, 500, 1024, 2000, W.N]
+    for npl in [q for q in sizes if q <= min(W.N, 2048)]:
         print(f"[parity] nn_pool {case} N={W.N} p={W.p} M={W.M} Np={npl}", flush=True)
         import torch
 
