@@ -79,25 +79,30 @@ __device__ __forceinline__ int ridx(int i, int l)
 }
 
 // Float64 z = R_j K(X_j, c) for candidate `slot` by one wave (lane i owns
-// z_i).  The j-loop is unrolled by four so the LDS loads overlap.
+// z_i).  The j-loop is unrolled by eight so the LDS loads overlap.
 template <int SLOTS, int KG>
 __device__ __forceinline__ double wave_z64(const double *cx, const int32_t *selslot, const double *RM,
                                            int slot, int j, int p, double d, int lane)
 {
     double kl = 0.0;
     if (lane < j) kl = corr64(sqdist_strict(cx + selslot[lane], SLOTS, cx + slot, SLOTS, p), d);
-    double z0 = 0.0, z1 = 0.0;
+    double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
     int l = 0;
-    for (; l + 4 <= j; l += 4) {
-        const double r0 = RM[ridx<KG>(lane, l)], r1 = RM[ridx<KG>(lane, l + 1)];
-        const double r2 = RM[ridx<KG>(lane, l + 2)], r3 = RM[ridx<KG>(lane, l + 3)];
-        z0 = fma(r0, readlane(kl, l), z0);
-        z1 = fma(r1, readlane(kl, l + 1), z1);
-        z0 = fma(r2, readlane(kl, l + 2), z0);
-        z1 = fma(r3, readlane(kl, l + 3), z1);
+    for (; l + 8 <= j; l += 8) {
+        double r[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) r[u] = RM[ridx<KG>(lane, l + u)];
+        z0 = fma(r[0], readlane(kl, l), z0);
+        z1 = fma(r[1], readlane(kl, l + 1), z1);
+        z2 = fma(r[2], readlane(kl, l + 2), z2);
+        z3 = fma(r[3], readlane(kl, l + 3), z3);
+        z0 = fma(r[4], readlane(kl, l + 4), z0);
+        z1 = fma(r[5], readlane(kl, l + 5), z1);
+        z2 = fma(r[6], readlane(kl, l + 6), z2);
+        z3 = fma(r[7], readlane(kl, l + 7), z3);
     }
     for (; l < j; l++) z0 = fma(RM[ridx<KG>(lane, l)], readlane(kl, l), z0);
-    return z0 + z1;
+    return (z0 + z1) + (z2 + z3);
 }
 
 template <typename T, int NW, int CBW, int KG, int G>
@@ -119,8 +124,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     __shared__ float RA32[MIXED ? RT : 1];  // float32 copy of R_j (mixed)
     __shared__ double cx[kPmax * SLOTS];    // candidate coordinates, [k][slot]
     __shared__ double cxv[SLOTS];           // K(candidate, x)
+    __shared__ double cY[SLOTS];            // response of each slot
+    __shared__ double alc_out[NMAX];        // score of the point added at each step
     __shared__ int32_t cid[SLOTS];          // design index of each slot
     __shared__ uint8_t cflag[SLOTS];        // 0 candidate, 1 in design, 2 empty
+    __shared__ T fz_s[MIXED ? SLOTS : 1], fz_c[MIXED ? SLOTS : 1];  // z.z, z.z_h over completed row blocks
     __shared__ double zh[ROWS], tY[ROWS];   // R_j K(X_j, x) and R_j Y_j
     __shared__ float zh32[MIXED ? ROWS : 1];
     __shared__ double zbest[NW][ROWS];      // each wave's best re-scored z
@@ -142,10 +150,12 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         zhT = zh;
     }
 
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane0 = tid & 63;
     const int64_t m = blockIdx.x;
     const int p = a.p, Np = a.Np, n = a.n, n0 = a.n0;
     const double d = a.d, kappa = 1.0 + a.g;
+    const float ninv_d32 = (float)(-1.0 / a.d);
     const int wbase = w * WSLOTS;
 
     // ---- stage the location, its pool and zeroed factors in LDS
@@ -165,6 +175,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         }
         cid[s] = di;
         cflag[s] = valid ? 0 : 2;
+        cY[s] = valid ? a.Y[di] : 0.0;
+        if constexpr (MIXED) {
+            fz_s[s] = (T)0;
+            fz_c[s] = (T)0;
+        }
         for (int k = 0; k < p; k++) cx[k * SLOTS + s] = valid ? a.X[(int64_t)di * p + k] : 0.0;
     }
     for (int i = tid; i < RT; i += kThreads) {
@@ -196,6 +211,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     T sc[MIXED ? CBW : 1];  // float32 score of candidate lane % 16 of each block (mixed)
 
     for (; status == kLocOk && j < n; j++) {
+        // Per-lane addresses are cheap to rebuild and costly to keep live across
+        // the whole design (they would be spilled), so the lane id is made opaque
+        // to the optimiser once per step.
+        int lane = lane0;
+        asm volatile("" : "+v"(lane));
         // ===== (1) score every candidate: Z^T = R_j Q^T on the matrix cores
         T bs = (T)0;
         int win_hint = j;  // the float64 path's winner; slot j for the NN start
@@ -203,45 +223,87 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             T best_s = (T)-1;
             int32_t best_i = INT32_MAX, best_k = -1;
             bool susp = false;
-            const int nib = (j + 15) >> 4;
+            // Rows of R_j never change once added, so z_c restricted to a completed
+            // 16-row block is the same at every later step: its sums z.z and z.z_h
+            // are kept per slot (fz_s, fz_c) and only the block holding the newest
+            // row is recomputed.  The first scored step computes every block.
+            // (The float64 kernel, whose register budget is taken by Q, recomputes
+            // every block instead.)
+            constexpr bool FROZEN = MIXED;
+            const int ib_hi = (j - 1) >> 4;
+            const int ib_lo = (FROZEN && j != n0) ? ib_hi : 0;
+            const bool closes = FROZEN && (j & 15) == 0;  // this step completes block ib_hi
+            auto block = [&](int ib, int cg, T (&sp)[G], T (&cp)[G]) {
+                Acc acc[G];
+#pragma unroll
+                for (int q = 0; q < G; q++) acc[q] = Acc{0, 0, 0, 0};
+#pragma unroll
+                for (int kg = 0; kg < KG; kg++) {
+                    if (kg * 4 < j && kg <= ib * 4 + 3) {
+                        const T av = RA[(ib * KG + kg) * 64 + lane];
+#pragma unroll
+                        for (int q = 0; q < G; q++) acc[q] = Mma<T>::run(av, Q[cg + q][kg], acc[q]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const T zr = zhT[ib * 16 + Mma<T>::row(lane, r)];
+#pragma unroll
+                    for (int q = 0; q < G; q++) {
+                        const T z = acc[q][r];
+                        sp[q] += z * z;
+                        cp[q] += z * zr;
+                    }
+                }
+            };
 #pragma unroll
             for (int cg = 0; cg < CBW; cg += G) {
                 T sp[G], cp[G];
 #pragma unroll
                 for (int q = 0; q < G; q++) sp[q] = cp[q] = (T)0;
+                T s_[G], c_[G];
+                if constexpr (FROZEN) {
+                    T dp[G], dc[G];
+#pragma unroll
+                    for (int q = 0; q < G; q++) dp[q] = dc[q] = (T)0;
 #pragma unroll 1
-                for (int ib = 0; ib < nib; ib++) {
-                    Acc acc[G];
+                    for (int ib = ib_lo; ib < ib_hi; ib++) block(ib, cg, dp, dc);
+                    block(ib_hi, cg, sp, cp);
 #pragma unroll
-                    for (int q = 0; q < G; q++) acc[q] = Acc{0, 0, 0, 0};
-#pragma unroll
-                    for (int kg = 0; kg < KG; kg++) {
-                        if (kg * 4 < j && kg <= ib * 4 + 3) {
-                            const T av = RA[(ib * KG + kg) * 64 + lane];
-#pragma unroll
-                            for (int q = 0; q < G; q++) acc[q] = Mma<T>::run(av, Q[cg + q][kg], acc[q]);
+                    for (int q = 0; q < G; q++) {
+                        const int slot = wbase + (cg + q) * 16 + (lane & 15);
+                        T fs = fz_s[slot], fc = fz_c[slot];
+                        if (ib_lo < ib_hi) {
+                            fs += row_sum4(dp[q]);
+                            fc += row_sum4(dc[q]);
+                        }
+                        s_[q] = fs + row_sum4(sp[q]);
+                        c_[q] = fc + row_sum4(cp[q]);
+                        if ((ib_lo < ib_hi || closes) && lane < 16) {
+                            fz_s[slot] = closes ? s_[q] : fs;
+                            fz_c[slot] = closes ? c_[q] : fc;
                         }
                     }
+                } else {
+#pragma unroll 1
+                    for (int ib = 0; ib <= ib_hi; ib++) block(ib, cg, sp, cp);
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const T zr = zhT[ib * 16 + Mma<T>::row(lane, r)];
-#pragma unroll
-                        for (int q = 0; q < G; q++) {
-                            const T z = acc[q][r];
-                            sp[q] += z * z;
-                            cp[q] += z * zr;
-                        }
+                    for (int q = 0; q < G; q++) {
+                        s_[q] = row_sum4(sp[q]);
+                        c_[q] = row_sum4(cp[q]);
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < G; q++) {
-                    const T s_ = row_sum4(sp[q]);
-                    const T c_ = row_sum4(cp[q]);
                     const int slot = wbase + (cg + q) * 16 + (lane & 15);
                     const bool live = cflag[slot] == 0;
-                    const T sv = (T)kappa - s_;
-                    const T cv = (T)cxv[slot] - c_;
-                    const T score = (live && sv > (T)0) ? cv * cv / sv : (T)-1;
+                    const T sv = (T)kappa - s_[q];
+                    const T cv = (T)cxv[slot] - c_[q];
+                    T score;
+                    if constexpr (MIXED)
+                        score = (live && sv > 0.0f) ? cv * cv * __builtin_amdgcn_rcpf(sv) : -1.0f;
+                    else
+                        score = (live && sv > 0.0) ? cv * cv / sv : -1.0;
                     if constexpr (MIXED) {
                         if (live && !(sv > kSmallS * (float)kappa)) susp = true;
                         sc[cg + q] = score;
@@ -263,15 +325,27 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             if constexpr (MIXED)
                 if (susp) ctl_susp = 1;
             __syncthreads();
-            bs = red_s[0];
-            int32_t bi = red_i[0];
-            win_hint = red_k[0];
-            for (int q = 1; q < NW; q++)
-                if (beats(red_s[q], red_i[q], bs, bi)) {
-                    bs = red_s[q];
-                    bi = red_i[q];
-                    win_hint = red_k[q];
-                }
+            if constexpr (MIXED) {
+                // lane q holds wave q's best; one wave-wide argmax combines them
+                bs = lane < NW ? red_s[lane] : (T)-1;
+                int32_t bi = lane < NW ? red_i[lane] : INT32_MAX;
+                win_hint = lane < NW ? red_k[lane] : -1;
+                wave_argmax(bs, bi, win_hint);
+                // lane 0's copy, so that control flow is uniform even on invalid ties
+                bs = uniform(bs);
+                win_hint = __builtin_amdgcn_readfirstlane(win_hint);
+            } else {
+                // few waves: a short serial pass keeps register pressure low
+                bs = red_s[0];
+                int32_t bi = red_i[0];
+                win_hint = red_k[0];
+                for (int q = 1; q < NW; q++)
+                    if (beats(red_s[q], red_i[q], bs, bi)) {
+                        bs = red_s[q];
+                        bi = red_i[q];
+                        win_hint = red_k[q];
+                    }
+            }
             if (!(bs >= (T)0)) {  // no candidate with a positive conditional variance
                 status = kLocStepFail;
                 break;
@@ -327,18 +401,29 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             rec_n[w] = cnt;
         }
         __syncthreads();
-        double v = rec_v[0];
-        int32_t vi = rec_i[0];
-        int vw = 0, total = 0;
-        err = 0.0;
-        for (int q = 0; q < NW; q++) {
-            if (q > 0 && beats(rec_v[q], rec_i[q], v, vi)) {
-                v = rec_v[q];
-                vi = rec_i[q];
-                vw = q;
-            }
-            err = fmax(err, rec_e[q]);
-            total += rec_n[q];
+        double v;
+        int vw, total = 0;
+        if constexpr (MIXED) {
+            // lane q holds wave q's record: argmax of the float64 scores, max error, member count
+            v = lane < NW ? rec_v[lane] : -1.0;
+            int32_t vi = lane < NW ? rec_i[lane] : INT32_MAX;
+            vw = lane < NW ? lane : -1;
+            wave_argmax(v, vi, vw);
+            v = uniform(v);
+            vw = __builtin_amdgcn_readfirstlane(vw);
+            err = wave_max(lane < NW ? rec_e[lane] : 0.0);
+            total = (int)wave_sum(lane < NW ? (float)rec_n[lane] : 0.0f);
+        } else {
+            // few waves: a short serial pass keeps register pressure low
+            v = rec_v[0];
+            int32_t vi = rec_i[0];
+            vw = 0;
+            for (int q = 1; q < NW; q++)
+                if (beats(rec_v[q], rec_i[q], v, vi)) {
+                    v = rec_v[q];
+                    vi = rec_i[q];
+                    vw = q;
+                }
         }
         if constexpr (MIXED)
             if (j >= n0 && !fallback && (!(v > 0.0) || err > kTrustErr || total > kWaveBandCap)) fallback = true;
@@ -357,19 +442,20 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                 rec_k[w] = bk;
             }
             __syncthreads();
-            v = rec_v[0];
-            vi = rec_i[0];
-            vw = 0;
-            for (int q = 1; q < NW; q++)
-                if (beats(rec_v[q], rec_i[q], v, vi)) {
-                    v = rec_v[q];
-                    vi = rec_i[q];
-                    vw = q;
-                }
+            v = lane < NW ? rec_v[lane] : -1.0;
+            int32_t vi = lane < NW ? rec_i[lane] : INT32_MAX;
+            vw = lane < NW ? lane : -1;
+            wave_argmax(v, vi, vw);
+            v = uniform(v);
+            vw = __builtin_amdgcn_readfirstlane(vw);
             guard_steps++;
         }
 
         // ===== (3) float64 update with l = zbest[vw] and s* = rec_s[vw]
+        if (vw < 0) {
+            status = j < n0 ? kLocInitNotPd : kLocStepFail;
+            break;
+        }
         const int win = rec_k[vw];
         const double sstar = rec_s[vw];
         if (win < 0 || !(sstar > 0.0) || !isfinite(sstar)) {
@@ -398,12 +484,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             const double zt = wave_sum(ell[lane] * tY[lane]);
             if (lane == 0) {
                 zh[j] = (cxv[win] - zz) / lam;
-                tY[j] = (a.Y[cid[win]] - zt) / lam;
+                tY[j] = (cY[win] - zt) / lam;
                 if constexpr (MIXED) zh32[j] = (float)zh[j];
                 cflag[win] = 1;
                 selslot[j] = win;
-                a.sel[m * n + j] = cid[win];
-                if (a.alc) a.alc[m * n + j] = j >= n0 ? v : NAN;
+                alc_out[j] = j >= n0 ? v : NAN;
                 ctl_susp = 0;
             }
         }
@@ -415,9 +500,14 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
 #pragma unroll
             for (int t = 0; t < CBW / 4; t++) {
                 const int slot = wbase + t * kWave + lane;
-                const double v64 =
-                    slot < Np ? corr64(sqdist_strict(cx + slot, SLOTS, cx + win, SLOTS, p), d) : 0.0;
-                const T vt = (T)v64;
+                T vt = (T)0;
+                if (slot < Np) {
+                    const double r2 = sqdist_strict(cx + slot, SLOTS, cx + win, SLOTS, p);
+                    if constexpr (MIXED)
+                        vt = __expf((float)r2 * ninv_d32);  // float32 kernel vector entry
+                    else
+                        vt = corr64(r2, d);
+                }
 #pragma unroll
                 for (int c4 = 0; c4 < 4; c4++) {
                     const T moved = __shfl(vt, c4 * 16 + (lane & 15), kWave);
@@ -431,7 +521,13 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     }
     __syncthreads();
 
-    // ===== local prediction (eqs. predgp, preds2): mu = z_h.(R Y), psi = |R Y|^2
+    const int lane = lane0;
+    // ===== outputs: the design in the order added, its scores, the prediction
+    for (int jj = tid; jj < j; jj += kThreads) {
+        a.sel[m * n + jj] = cid[selslot[jj]];
+        if (a.alc) a.alc[m * n + jj] = alc_out[jj];
+    }
+    // local prediction (eqs. predgp, preds2): mu = z_h.(R Y), psi = |R Y|^2
     if (w == 0) {
         const double zi = (status == kLocOk && lane < n) ? zh[lane] : 0.0;
         const double ti = (status == kLocOk && lane < n) ? tY[lane] : 0.0;
@@ -478,7 +574,8 @@ hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st)
         return launch_t<double, 8, 8, 13, 1>(a, st);
     }
     if (a.Np <= 512) return launch_t<float, 8, 4, 16, 4>(a, st);
-    return launch_t<float, 16, 4, 16, 4>(a, st);
+    if (a.n <= 52) return launch_t<float, 8, 8, 13, 4>(a, st);
+    return launch_t<float, 8, 8, 16, 4>(a, st);
 }
 
 }  // namespace lagp

@@ -105,6 +105,20 @@ __device__ __forceinline__ double xsum(double v)
     return p.a + p.b;
 }
 
+template <int S>
+__device__ __forceinline__ double xmax(double v)
+{
+    const PairF64 p = xchg<S>(v);
+    return fmax(p.a, p.b);
+}
+
+template <int S>
+__device__ __forceinline__ float xmax(float v)
+{
+    const Pair32 p = xchg<S>(__builtin_bit_cast(unsigned, v));
+    return fmaxf(__builtin_bit_cast(float, p.a), __builtin_bit_cast(float, p.b));
+}
+
 // Sum over the four 16-lane rows (lanes l, l^16, l^32, l^48 hold partials).
 template <typename T>
 __device__ __forceinline__ T row_sum4(T v)
@@ -132,6 +146,17 @@ __device__ __forceinline__ double readlane(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Lane 0's value, as a wave-uniform quantity.
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, v)));
+}
+
+__device__ __forceinline__ double uniform(double v)
+{
+    return readlane(v, 0);
+}
+
 template <int S>
 __device__ __forceinline__ void argmax_stage(float &s, int &idx, int &slot)
 {
@@ -153,6 +178,17 @@ __device__ __forceinline__ void argmax_stage(double &s, int &idx, int &slot)
     s = take_b ? ps.b : ps.a;
     idx = (int)(take_b ? pi.b : pi.a);
     slot = (int)(take_b ? pk.b : pk.a);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+    v = xmax<0>(v);
+    v = xmax<1>(v);
+    v = xmax<2>(v);
+    v = xmax<3>(v);
+    v = xmax<4>(v);
+    return xmax<5>(v);
 }
 
 // Wave-wide argmax of (score, design index, slot); every lane gets the result.
