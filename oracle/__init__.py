@@ -62,6 +62,12 @@ class Oracle:
         L.orc_alc.restype = i32
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = i32
+        L.orc_nll.argtypes = [P, P, i32, i32, f64, f64, P]
+        L.orc_nll.restype = i32
+        L.orc_mle_d.argtypes = [P, P, i32, i32, f64, f64, f64, f64, i32, P]
+        L.orc_mle_d.restype = i32
+        L.orc_local_mle.argtypes = [P, P, i32, P, i64, i32, P, f64, f64, f64, i32, i32, P]
+        L.orc_local_mle.restype = i32
         self.L = L
 
     def nn_pool(self, X, XX, Np: int, threads: int = 0) -> np.ndarray:
@@ -124,6 +130,33 @@ class Oracle:
     def max_threads(self) -> int:
         return self.L.orc_max_threads()
 
+    def nll(self, D, Yd, d: float, g: float) -> dict:
+        """Negative log of eq. gpk and its derivatives: nll, dd, dg, d2 (d2nll/dd2)."""
+        D, Yd = _f64(np.atleast_2d(D)), _f64(Yd)
+        out = np.empty(4)
+        rc = self.L.orc_nll(_p(D), _p(Yd), D.shape[0], D.shape[1], d, g, _p(out))
+        return dict(nll=out[0], dd=out[1], dg=out[2], d2=out[3], status=rc)
+
+    def mle_d(self, D, Yd, d0: float, g: float, dmin: float = 1e-3, dmax: float = 5.0,
+              maxit: int = 100) -> dict:
+        """Projected-Newton maximum-likelihood lengthscale on one fixed design."""
+        D, Yd = _f64(np.atleast_2d(D)), _f64(Yd)
+        out = np.empty(4)
+        self.L.orc_mle_d(_p(D), _p(Yd), D.shape[0], D.shape[1], d0, g, dmin, dmax, maxit, _p(out))
+        return dict(d=out[0], nll=out[1], iters=int(out[2]), status=int(out[3]))
+
+    def local_mle(self, X, Y, sel, d0, g: float, dmin: float = 1e-3, dmax: float = 5.0,
+                  maxit: int = 100, threads: int = 0) -> dict:
+        """mle_d for every location's design (sel: M x n design indices)."""
+        X, Y = _f64(X), _f64(Y)
+        sel = _i32(np.atleast_2d(sel))
+        M, n = sel.shape
+        d0 = _f64(np.broadcast_to(np.asarray(d0, dtype=np.float64), (M,)))
+        out = np.empty((M, 4))
+        self.L.orc_local_mle(_p(X), _p(Y), X.shape[1], _p(sel), M, n, _p(d0), g, dmin, dmax, maxit,
+                             threads, _p(out))
+        return dict(d=out[:, 0], nll=out[:, 1], iters=out[:, 2].astype(int), status=out[:, 3].astype(int))
+
 
 _default: Oracle | None = None
 
@@ -153,3 +186,15 @@ def lagp(*a, **k):
 
 def max_threads() -> int:
     return default().max_threads()
+
+
+def nll(*a, **k):
+    return default().nll(*a, **k)
+
+
+def mle_d(*a, **k):
+    return default().mle_d(*a, **k)
+
+
+def local_mle(*a, **k):
+    return default().local_mle(*a, **k)

@@ -45,6 +45,7 @@
  * Squared distances are summed left to right over coordinates; the file is
  * compiled with -ffp-contract=off so no multiply-add is fused.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -519,4 +520,167 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Local likelihood in the lengthscale d (eq. gpk; Fig. 1 step 3).      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Negative log of eq. gpk for the design D (n x p) with responses Yd:
+ *   nll = -lgamma(n/2) + (n/2) log(2 pi) + (1/2) log|K| + (n/2) log(psi/2),
+ *   K = exp(-D2/d) + g I,  psi = Y^T K^{-1} Y.
+ * With A = K^{-1}, alpha = A Y, Kd = dK/dd = exp(-D2/d) * D2 / d^2 and
+ * Kdd = d2K/dd2 = exp(-D2/d) * (D2^2/d^4 - 2 D2/d^3):
+ *   dnll/dd   = (1/2) tr(A Kd) - (n/2) (alpha^T Kd alpha) / psi
+ *   dnll/dg   = (1/2) tr(A)    - (n/2) (alpha^T alpha) / psi
+ *   d2nll/dd2 = (1/2) tr(A Kdd - A Kd A Kd)
+ *               - (n/2) [ (alpha^T Kdd alpha - 2 alpha^T Kd A Kd alpha) / psi
+ *                         + (alpha^T Kd alpha)^2 / psi^2 ]
+ * out = {nll, dnll/dd, dnll/dg, d2nll/dd2}.  Returns 1 if K is not PD.
+ */
+int orc_nll(const double *D, const double *Yd, int n, int p, double d, double g, double *out)
+{
+    size_t nn = (size_t)n * n;
+    double *K = (double *)malloc(sizeof(double) * nn);
+    double *L = (double *)malloc(sizeof(double) * nn);
+    double *A = (double *)malloc(sizeof(double) * nn);
+    double *Kd = (double *)malloc(sizeof(double) * nn);
+    double *Kdd = (double *)malloc(sizeof(double) * nn);
+    double *B = (double *)malloc(sizeof(double) * nn);
+    double *e = (double *)malloc(sizeof(double) * n);
+    double *col = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *alpha = (double *)malloc(sizeof(double) * n);
+    double *v = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            double r2 = sqdist(D + a * p, D + b * p, p);
+            double c = exp(-r2 / d);
+            K[a * n + b] = c + (a == b ? g : 0.0);
+            Kd[a * n + b] = c * r2 / (d * d);
+            Kdd[a * n + b] = c * (r2 * r2 / (d * d * d * d) - 2.0 * r2 / (d * d * d));
+        }
+    if (cholesky(K, L, n)) {
+        rc = 1;
+        for (int q = 0; q < 4; q++) out[q] = NAN;
+    } else {
+        /* A = K^{-1}, column by column */
+        for (int c = 0; c < n; c++) {
+            for (int r = 0; r < n; r++) e[r] = r == c ? 1.0 : 0.0;
+            forward_solve(L, e, w, n);
+            backward_solve_t(L, w, col, n);
+            for (int r = 0; r < n; r++) A[r * n + c] = col[r];
+        }
+        forward_solve(L, Yd, w, n);
+        backward_solve_t(L, w, alpha, n);
+        double psi = dot(Yd, alpha, n);
+        double logdet = 0.0;
+        for (int r = 0; r < n; r++) logdet += 2.0 * log(L[r * n + r]);
+        double nll = -lgamma(0.5 * n) + 0.5 * n * log(2.0 * M_PI) + 0.5 * logdet + 0.5 * n * log(0.5 * psi);
+        /* B = A Kd */
+        for (int r = 0; r < n; r++)
+            for (int c = 0; c < n; c++) {
+                double s = 0.0;
+                for (int k = 0; k < n; k++) s += A[r * n + k] * Kd[k * n + c];
+                B[r * n + c] = s;
+            }
+        double trAKd = 0.0, trAKdd = 0.0, trBB = 0.0, trA = 0.0;
+        for (int r = 0; r < n; r++) {
+            trAKd += B[r * n + r];
+            trA += A[r * n + r];
+            for (int c = 0; c < n; c++) {
+                trAKdd += A[r * n + c] * Kdd[c * n + r];
+                trBB += B[r * n + c] * B[c * n + r];
+            }
+        }
+        /* v = Kd alpha */
+        for (int r = 0; r < n; r++) v[r] = dot(Kd + r * n, alpha, n);
+        double aKda = dot(alpha, v, n);
+        double aa = dot(alpha, alpha, n);
+        double aKdda = 0.0;
+        for (int r = 0; r < n; r++) aKdda += alpha[r] * dot(Kdd + r * n, alpha, n);
+        /* Kd A Kd quadratic form: v^T A v */
+        double vAv = 0.0;
+        for (int r = 0; r < n; r++) vAv += v[r] * dot(A + r * n, v, n);
+        out[0] = nll;
+        out[1] = 0.5 * trAKd - 0.5 * n * aKda / psi;
+        out[2] = 0.5 * trA - 0.5 * n * aa / psi;
+        out[3] = 0.5 * (trAKdd - trBB) - 0.5 * n * ((aKdda - 2.0 * vAv) / psi + aKda * aKda / (psi * psi));
+    }
+    free(K); free(L); free(A); free(Kd); free(Kdd); free(B);
+    free(e); free(col); free(w); free(alpha); free(v);
+    return rc;
+}
+
+/*
+ * Maximum likelihood lengthscale on a fixed local design (Fig. 1 step 3),
+ * g held fixed.  The paper only says "Newton-like" with analytic
+ * derivatives; the reading taken is a projected Newton iteration on
+ * [dmin, dmax]: step -f'/f'' when f'' > 0, else a gradient step of length
+ * 0.1 d along -f'; backtracking halvings (at most 40) until the sufficient
+ * decrease f(d+s) <= f(d) + 1e-4 f' s holds; stop when |step| <= 1e-10 d,
+ * when |f'| <= 1e-10, when the iterate sits on a bound with f' pointing out
+ * of the interval, or after maxit iterations.
+ * out = {d_hat, nll(d_hat), iterations, status}; status 0 converged,
+ * 1 not PD, 2 iteration limit, 3 line search failed.
+ */
+int orc_mle_d(const double *D, const double *Yd, int n, int p, double d0, double g, double dmin,
+              double dmax, int maxit, double *out)
+{
+    double d = d0 < dmin ? dmin : (d0 > dmax ? dmax : d0);
+    double f[4], ft[4];
+    int status = 2, it = 0;
+    if (orc_nll(D, Yd, n, p, d, g, f)) { out[0] = d; out[1] = NAN; out[2] = 0; out[3] = 1; return 1; }
+    for (it = 0; it < maxit; it++) {
+        double gr = f[1], h = f[3];
+        if (fabs(gr) <= 1e-10 || (d <= dmin && gr > 0.0) || (d >= dmax && gr < 0.0)) { status = 0; break; }
+        double step = h > 0.0 ? -gr / h : (gr > 0.0 ? -0.1 * d : 0.1 * d);
+        double dn = 0.0;
+        int ok = 0;
+        for (int half = 0; half < 40; half++) {
+            dn = d + step;
+            if (dn < dmin) dn = dmin;
+            if (dn > dmax) dn = dmax;
+            if (orc_nll(D, Yd, n, p, dn, g, ft) == 0 && ft[0] <= f[0] + 1e-4 * gr * (dn - d)) { ok = 1; break; }
+            step *= 0.5;
+        }
+        if (!ok) { status = 3; break; }
+        double moved = fabs(dn - d);
+        d = dn;
+        for (int q = 0; q < 4; q++) f[q] = ft[q];
+        if (moved <= 1e-10 * d) { status = 0; it++; break; }
+    }
+    out[0] = d;
+    out[1] = f[0];
+    out[2] = it;
+    out[3] = status;
+    return 0;
+}
+
+/* Batched over M designs of n rows (sel: M x n design indices into X). */
+int orc_local_mle(const double *X, const double *Y, int p, const int32_t *sel, int64_t M, int n,
+                  const double *d0, double g, double dmin, double dmax, int maxit, int nthreads,
+                  double *out /* M x 4 */)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        double *Dn = (double *)malloc(sizeof(double) * (size_t)n * p);
+        double *Yn = (double *)malloc(sizeof(double) * n);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t m = 0; m < M; m++) {
+            for (int a = 0; a < n; a++) {
+                memcpy(Dn + (size_t)a * p, X + (int64_t)sel[m * n + a] * p, sizeof(double) * p);
+                Yn[a] = Y[sel[m * n + a]];
+            }
+            orc_mle_d(Dn, Yn, n, p, d0[m], g, dmin, dmax, maxit, out + m * 4);
+        }
+        free(Dn);
+        free(Yn);
+    }
+    return ORC_OK;
 }

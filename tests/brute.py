@@ -72,3 +72,42 @@ def greedy(X: np.ndarray, x: np.ndarray, P: np.ndarray, n0: int, n: int, d: floa
         sel.append(c)
         best.append(s)
     return np.array(sel, dtype=np.int32), np.array(best)
+
+
+def nll(D: np.ndarray, Yd: np.ndarray, d: float, g: float) -> float:
+    """Negative log of eq. gpk via numpy.linalg.slogdet and solve."""
+    import math
+
+    n = D.shape[0]
+    K = corr(D, D, d) + g * np.eye(n)
+    sign, logdet = np.linalg.slogdet(K)
+    assert sign > 0
+    psi = Yd @ np.linalg.solve(K, Yd)
+    return -math.lgamma(n / 2) + n / 2 * math.log(2 * math.pi) + 0.5 * logdet + n / 2 * math.log(psi / 2)
+
+
+def nll_by_quadrature(D: np.ndarray, Yd: np.ndarray, d: float, g: float) -> float:
+    """-log of the marginal of N(Y; 0, tau2 K) over tau2 with prior 1/tau2, by quadrature.
+
+    Independent of eq. gpk's closed form: the Gamma function and the
+    (psi/2)^(-n/2) factor come out of the integral numerically.
+    """
+    import math
+
+    from scipy import integrate
+
+    n = D.shape[0]
+    K = corr(D, D, d) + g * np.eye(n)
+    sign, logdet = np.linalg.slogdet(K)
+    psi = Yd @ np.linalg.solve(K, Yd)
+
+    # substitute u = log tau2; integrand of the log-scale marginal, scaled by exp(-c)
+    def log_f(u):
+        t = math.exp(u)
+        return -n / 2 * math.log(2 * math.pi * t) - 0.5 * logdet - psi / (2 * t)
+
+    umode = math.log(psi / n)
+    c = log_f(umode)
+    val, _ = integrate.quad(lambda u: math.exp(log_f(u) - c), umode - 40, umode + 40, limit=400,
+                            epsabs=0, epsrel=1e-12)
+    return -(c + math.log(val))

@@ -21,6 +21,12 @@ What pins what:
   route_b           - the paper's partitioned-inverse route (eq. piedef) and the
                       literal three-term eq. dxy agree with mode A
   forced            - evaluating a given sequence reproduces the free run
+  nll_textbook      - negative log of eq. gpk = slogdet/solve form, and = the
+                      marginal over the scale computed by quadrature (pins
+                      the Gamma-function and (psi/2)^(-n/2) constants)
+  nll_derivatives_fd- d/dd, d/dg and d2/dd2 = central finite differences
+  mle_optimality    - the Newton MLE is a stationary point (or a bound with
+                      the gradient pointing out) and beats a fine local grid
 """
 from __future__ import annotations
 
@@ -217,5 +223,53 @@ def forced(orc):
         assert _rel(c["mean"][m], ref["mean"]) < 1e-9
 
 
+def nll_textbook(orc):
+    r = np.random.default_rng(21)
+    for n, p, d, g in ((4, 2, 0.4, 1e-2), (9, 3, 0.25, 1e-3), (30, 4, 0.2, 1e-3), (50, 4, 0.6, 1e-4)):
+        D = r.random((n, p))
+        Yd = np.sin(3 * D).sum(axis=1) + r.normal(0, 0.05, n)
+        got = orc.nll(D, Yd, d, g)
+        assert got["status"] == 0
+        assert abs(got["nll"] - brute.nll(D, Yd, d, g)) <= 1e-9 * max(1.0, abs(got["nll"])), (n, got)
+        if n <= 9:
+            q = brute.nll_by_quadrature(D, Yd, d, g)
+            assert abs(got["nll"] - q) <= 1e-8 * max(1.0, abs(q)), (n, got["nll"], q)
+
+
+def nll_derivatives_fd(orc):
+    r = np.random.default_rng(22)
+    for n, p, d, g in ((6, 2, 0.3, 1e-2), (25, 4, 0.2, 1e-3), (50, 4, 0.7, 1e-3)):
+        D = r.random((n, p))
+        Yd = np.cos(4 * D).sum(axis=1) + r.normal(0, 0.03, n)
+        f = orc.nll(D, Yd, d, g)
+        hd, hg = 1e-5 * d, 1e-5 * g
+        fdd = (orc.nll(D, Yd, d + hd, g)["nll"] - orc.nll(D, Yd, d - hd, g)["nll"]) / (2 * hd)
+        fdg = (orc.nll(D, Yd, d, g + hg)["nll"] - orc.nll(D, Yd, d, g - hg)["nll"]) / (2 * hg)
+        fd2 = (orc.nll(D, Yd, d + hd, g)["dd"] - orc.nll(D, Yd, d - hd, g)["dd"]) / (2 * hd)
+        assert abs(fdd - f["dd"]) <= 1e-6 * max(1.0, abs(f["dd"])), (n, fdd, f["dd"])
+        assert abs(fdg - f["dg"]) <= 1e-6 * max(1.0, abs(f["dg"])), (n, fdg, f["dg"])
+        assert abs(fd2 - f["d2"]) <= 1e-5 * max(1.0, abs(f["d2"])), (n, fd2, f["d2"])
+
+
+def mle_optimality(orc):
+    W = workloads.make(4, N=4000, M=6)
+    out = orc.lagp(W.X, W.Y, W.XX, 6, 30, 300, 0.2, W.g)
+    dmin, dmax = 1e-3, 5.0
+    for m in range(W.M):
+        D, Yd = W.X[out["sel"][m]], W.Y[out["sel"][m]]
+        res = orc.mle_d(D, Yd, 0.2, W.g, dmin, dmax)
+        assert res["status"] == 0, res
+        dh = res["d"]
+        f = orc.nll(D, Yd, dh, W.g)
+        if dmin < dh < dmax:
+            assert abs(f["dd"]) <= 1e-6 * max(1.0, abs(f["nll"])) and f["d2"] > 0, (m, f)
+        else:
+            assert (dh == dmin and f["dd"] > 0) or (dh == dmax and f["dd"] < 0)
+        # no point of a fine grid around the optimum does better
+        for t in np.geomspace(max(dmin, dh / 1.5), min(dmax, dh * 1.5), 61):
+            assert orc.nll(D, Yd, t, W.g)["nll"] >= f["nll"] - 1e-9 * abs(f["nll"])
+
+
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
-       special_cases, design_point, predict_textbook, route_b, forced]
+       special_cases, design_point, predict_textbook, route_b, forced, nll_textbook,
+       nll_derivatives_fd, mle_optimality]

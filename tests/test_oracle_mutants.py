@@ -28,7 +28,8 @@ MUTANTS = {
     # Student-t scale divided by n - 1
     "s2_divisor": ("double s2 = psi * v / n;", "double s2 = psi * v / (n - 1);"),
     # psi = Y^T Y instead of Y^T K^{-1} Y
-    "psi_wrong": ("double psi = dot(Yd, alpha, n);", "double psi = dot(Yd, Yd, n);"),
+    "psi_wrong": ("double psi = dot(Yd, alpha, n);\n        double v = kappa",
+                  "double psi = dot(Yd, Yd, n);\n        double v = kappa"),
     # NN start skips the nearest point
     "init_off_by_one": ("                take_slot = j;\n", "                take_slot = j + 1;\n"),
     # last coordinate dropped from the distance
@@ -39,6 +40,17 @@ MUTANTS = {
                     "for (int a = 0; a < j; a++) gv[a] = m * u[a];\n    int J"),
     # Cholesky diagonal without the square root
     "chol_no_sqrt": ("L[r * j + r] = sqrt(s);", "L[r * j + r] = s;"),
+    # eq. gpk without its Gamma-function constant
+    "nll_no_lgamma": ("double nll = -lgamma(0.5 * n) + 0.5 * n * log(2.0 * M_PI)",
+                      "double nll = 0.5 * n * log(2.0 * M_PI)"),
+    # derivative of K in d with the wrong power of d
+    "kd_power": ("Kd[a * n + b] = c * r2 / (d * d);", "Kd[a * n + b] = c * r2 / d;"),
+    # trace term without its factor 1/2
+    "dd_trace_half": ("out[1] = 0.5 * trAKd - 0.5 * n * aKda / psi;", "out[1] = trAKd - 0.5 * n * aKda / psi;"),
+    # nugget derivative with the wrong quadratic form
+    "dg_form": ("out[2] = 0.5 * trA - 0.5 * n * aa / psi;", "out[2] = 0.5 * trA - 0.5 * n * aKda / psi;"),
+    # second derivative missing the psi^2 term
+    "d2_missing_term": ("+ aKda * aKda / (psi * psi));", ");"),
 }
 
 
