@@ -124,6 +124,60 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                              double *mean, double *s2, double *var, int32_t *sel, double *alc,
                              int32_t *status, int32_t *guard, void *stream);
 
+/*
+ * Local likelihood on fixed local designs (Sec. 2.1 eq. gpk, Fig. 1 step 3).
+ * For each location m the design is rows sel[m][0 .. n-1] of X (sel: M x n
+ * int32, e.g. the `sel` output of lagp_alc_from_pool), with responses Y.
+ * K = exp(-||x_a - x_b||^2 / d) + g I.  The negative log likelihood is
+ *   nll = -lgamma(n/2) + (n/2) log(2 pi) + (1/2) log|K| + (n/2) log(psi/2),
+ *   psi = Y^T K^{-1} Y.
+ * Supported: 1 <= n <= 64, p <= 16.  All arithmetic in float64.
+ * Per-location status (nullable): 0 ok, 1 K not positive definite or the
+ * value not finite, 4 a design index outside [0, N).
+ *
+ * lagp_local_nll -- nll[M] and, for every non-NULL output, dnll_dd[M],
+ *   dnll_dg[M], d2nll_dd2[M] at d[M], g[M] (device arrays, > 0).
+ */
+lagp_status lagp_local_nll(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                           int64_t M, int32_t n, const double *d, const double *g, double *nll,
+                           double *dnll_dd, double *dnll_dg, double *d2nll_dd2, int32_t *status,
+                           void *stream);
+
+/*
+ * lagp_local_nll_backward -- hand-written reverse pass of lagp_local_nll:
+ *   grad_d[m] = grad_out[m] * dnll/dd,  grad_g[m] = grad_out[m] * dnll/dg
+ * (grad_out NULL means ones; either gradient output may be NULL).
+ */
+lagp_status lagp_local_nll_backward(const double *X, const double *Y, int64_t N, int32_t p,
+                                    const int32_t *sel, int64_t M, int32_t n, const double *d,
+                                    const double *g, const double *grad_out, double *grad_d,
+                                    double *grad_g, void *stream);
+
+/*
+ * lagp_local_mle_d -- maximum-likelihood lengthscale per location with the
+ * nugget g fixed (Fig. 1 step 3): projected Newton on [dmin, dmax] from
+ * d0[m] with analytic first and second derivatives, backtracking halvings
+ * (at most 40) to sufficient decrease nll(d+s) <= nll(d) + 1e-4 nll'(d) s,
+ * a gradient step of 0.1 d when nll'' <= 0; stops when |step| <= 1e-10 d,
+ * |nll'| <= 1e-10, on a bound with nll' pointing out, or after maxit steps.
+ * Outputs: d_hat[M], nll[M] (nullable), iters[M] (nullable), status[M]
+ * (nullable: 0 converged, 1 not PD, 2 iteration limit, 3 line search failed,
+ * 4 bad design index).
+ */
+lagp_status lagp_local_mle_d(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                             int64_t M, int32_t n, const double *d0, double g, double dmin, double dmax,
+                             int32_t maxit, double *d_hat, double *nll, int32_t *iters, int32_t *status,
+                             void *stream);
+
+/*
+ * lagp_local_predict -- predictive mean, scale and variance at XX[m] (M x p)
+ * on the fixed design sel[m] with per-location lengthscale d[M] and nugget
+ * g (eqs. predgp, preds2 with N -> n; Fig. 1 step 5).  status as above.
+ */
+lagp_status lagp_local_predict(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                               int64_t M, int32_t n, const double *XX, const double *d, double g,
+                               double *mean, double *s2, double *var, int32_t *status, void *stream);
+
 /* Name of a status code. */
 const char *lagp_status_string(lagp_status s);
 

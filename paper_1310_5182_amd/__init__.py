@@ -11,7 +11,8 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "PRECISIONS", "version"]
+__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "local_nll", "LocalNLL", "local_mle_d",
+           "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED}
 
@@ -99,3 +100,100 @@ def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precisio
         o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["status"].data_ptr(),
         o["guard"].data_ptr(), _stream(X.device)))
     return o
+
+
+def _sel(sel: torch.Tensor) -> torch.Tensor:
+    if sel.dtype != torch.int32 or not sel.is_contiguous() or not sel.is_cuda or sel.dim() != 2:
+        raise ValueError("sel must be a contiguous M x n int32 device tensor")
+    return sel
+
+
+def _per_loc(v, M: int, device, name: str) -> torch.Tensor:
+    if isinstance(v, torch.Tensor):
+        return _f64(v.reshape(M) if v.numel() == M else v, name)
+    return torch.full((M,), float(v), dtype=torch.float64, device=device)
+
+
+def local_nll(X, Y, sel, d, g, order: int = 0) -> dict:
+    """Negative log of eq. gpk on each location's fixed design (float64).
+
+    order 0: nll; 1: + dnll/dd, dnll/dg; 2: + d2nll/dd2.  d, g: scalars or M-vectors.
+    """
+    L = _lib.load()
+    X, Y, sel = _f64(X, "X"), _f64(Y, "Y"), _sel(sel)
+    M, n = sel.shape
+    dev = X.device
+    d, g = _per_loc(d, M, dev, "d"), _per_loc(g, M, dev, "g")
+    out = {"nll": torch.empty(M, dtype=torch.float64, device=dev),
+           "status": torch.empty(M, dtype=torch.int32, device=dev)}
+    if order >= 1:
+        out["dd"] = torch.empty(M, dtype=torch.float64, device=dev)
+        out["dg"] = torch.empty(M, dtype=torch.float64, device=dev)
+    if order >= 2:
+        out["d2"] = torch.empty(M, dtype=torch.float64, device=dev)
+    ptr = lambda k: out[k].data_ptr() if k in out else None  # noqa: E731
+    _lib.check(L.lagp_local_nll(X.data_ptr(), Y.data_ptr(), X.shape[0], X.shape[1], sel.data_ptr(), M, n,
+                                d.data_ptr(), g.data_ptr(), ptr("nll"), ptr("dd"), ptr("dg"), ptr("d2"),
+                                ptr("status"), _stream(dev)))
+    return out
+
+
+class LocalNLL(torch.autograd.Function):
+    """nll[m](d[m], g[m]) on fixed local designs; the backward is the library's
+    hand-written reverse kernel (lagp_local_nll_backward)."""
+
+    @staticmethod
+    def forward(ctx, d, g, X, Y, sel):
+        out = local_nll(X, Y, sel, d.detach().contiguous(), g.detach().contiguous(), order=0)
+        ctx.save_for_backward(d.detach().contiguous(), g.detach().contiguous())
+        ctx.data = (X, Y, sel)
+        return out["nll"]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        L = _lib.load()
+        d, g = ctx.saved_tensors
+        X, Y, sel = ctx.data
+        M, n = sel.shape
+        go = grad_out.contiguous().to(torch.float64)
+        gd = torch.empty_like(d) if ctx.needs_input_grad[0] else None
+        gg = torch.empty_like(g) if ctx.needs_input_grad[1] else None
+        _lib.check(L.lagp_local_nll_backward(
+            X.data_ptr(), Y.data_ptr(), X.shape[0], X.shape[1], sel.data_ptr(), M, n, d.data_ptr(),
+            g.data_ptr(), go.data_ptr(), None if gd is None else gd.data_ptr(),
+            None if gg is None else gg.data_ptr(), _stream(X.device)))
+        return gd, gg, None, None, None
+
+
+def local_mle_d(X, Y, sel, d0, g: float, dmin: float = 1e-3, dmax: float = 5.0, maxit: int = 100) -> dict:
+    """Maximum-likelihood lengthscale per location (projected Newton, g fixed)."""
+    L = _lib.load()
+    X, Y, sel = _f64(X, "X"), _f64(Y, "Y"), _sel(sel)
+    M, n = sel.shape
+    dev = X.device
+    d0 = _per_loc(d0, M, dev, "d0")
+    out = {"d": torch.empty(M, dtype=torch.float64, device=dev),
+           "nll": torch.empty(M, dtype=torch.float64, device=dev),
+           "iters": torch.empty(M, dtype=torch.int32, device=dev),
+           "status": torch.empty(M, dtype=torch.int32, device=dev)}
+    _lib.check(L.lagp_local_mle_d(X.data_ptr(), Y.data_ptr(), X.shape[0], X.shape[1], sel.data_ptr(), M, n,
+                                  d0.data_ptr(), float(g), float(dmin), float(dmax), int(maxit),
+                                  out["d"].data_ptr(), out["nll"].data_ptr(), out["iters"].data_ptr(),
+                                  out["status"].data_ptr(), _stream(dev)))
+    return out
+
+
+def local_predict(X, Y, sel, XX, d, g: float) -> dict:
+    """Prediction at XX[m] on the fixed design sel[m] with lengthscale d[m] (eqs. predgp, preds2)."""
+    L = _lib.load()
+    X, Y, XX, sel = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX"), _sel(sel)
+    M, n = sel.shape
+    dev = X.device
+    d = _per_loc(d, M, dev, "d")
+    out = {k: torch.empty(M, dtype=torch.float64, device=dev) for k in ("mean", "s2", "var")}
+    out["status"] = torch.empty(M, dtype=torch.int32, device=dev)
+    _lib.check(L.lagp_local_predict(X.data_ptr(), Y.data_ptr(), X.shape[0], X.shape[1], sel.data_ptr(), M, n,
+                                    XX.data_ptr(), d.data_ptr(), float(g), out["mean"].data_ptr(),
+                                    out["s2"].data_ptr(), out["var"].data_ptr(), out["status"].data_ptr(),
+                                    _stream(dev)))
+    return out

@@ -21,6 +21,10 @@ EXPORTS = (
     "lagp_nn_pool",
     "lagp_alc_from_pool",
     "lagp_alc_predict",
+    "lagp_local_nll",
+    "lagp_local_nll_backward",
+    "lagp_local_mle_d",
+    "lagp_local_predict",
     "lagp_status_string",
     "lagp_last_error",
     "lagp_version",
@@ -54,6 +58,14 @@ def load():
     L.lagp_alc_predict.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, f64, f64, i32, P,
                                    P, P, P, P, P, P, P, P]
     L.lagp_alc_predict.restype = i32
+    L.lagp_local_nll.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P, P, P]
+    L.lagp_local_nll.restype = i32
+    L.lagp_local_nll_backward.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P]
+    L.lagp_local_nll_backward.restype = i32
+    L.lagp_local_mle_d.argtypes = [P, P, i64, i32, P, i64, i32, P, f64, f64, f64, i32, P, P, P, P, P]
+    L.lagp_local_mle_d.restype = i32
+    L.lagp_local_predict.argtypes = [P, P, i64, i32, P, i64, i32, P, P, f64, P, P, P, P, P]
+    L.lagp_local_predict.restype = i32
     L.lagp_status_string.argtypes = [i32]
     L.lagp_status_string.restype = ctypes.c_char_p
     L.lagp_last_error.argtypes = []

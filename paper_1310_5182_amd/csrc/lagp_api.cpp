@@ -115,6 +115,91 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                               status, guard, stream);
 }
 
+static lagp_status check_local(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                               int64_t M, int32_t n)
+{
+    if (M < 0) return fail(LAGP_EINVAL, "M = %lld < 0", (long long)M);
+    if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
+    if (N < 1 || N >= (int64_t)1 << 31) return fail(LAGP_EINVAL, "N = %lld outside [1, 2^31)", (long long)N);
+    if (n < 1 || n > N) return fail(LAGP_EINVAL, "n = %d outside [1, N]", n);
+    if (M > 0 && (!X || !Y || !sel)) return fail(LAGP_EINVAL, "X, Y and sel must be non-NULL");
+    if (!lagp::local_gp_supported(n, p)) return fail(LAGP_EUNSUPPORTED, "local design of n = %d, p = %d", n, p);
+    if (M > (int64_t)0x7fffffff) return fail(LAGP_EUNSUPPORTED, "M = %lld exceeds one launch", (long long)M);
+    return LAGP_OK;
+}
+
+lagp_status lagp_local_nll(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                           int64_t M, int32_t n, const double *d, const double *g, double *nll,
+                           double *dnll_dd, double *dnll_dg, double *d2nll_dd2, int32_t *status, void *stream)
+{
+    lagp_status s = check_local(X, Y, N, p, sel, M, n);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && (!d || !g)) return fail(LAGP_EINVAL, "d and g must be non-NULL");
+    if (M == 0) return ok();
+    lagp::GpArgs a{};
+    a.X = X; a.Y = Y; a.N = N; a.p = p; a.sel = sel; a.M = M; a.n = n;
+    a.d_arr = d; a.g_arr = g; a.nll = nll; a.dd = dnll_dd; a.dg = dnll_dg; a.d2 = d2nll_dd2; a.status = status;
+    hipError_t e = lagp::launch_local_gp(a, lagp::kGpNll, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "local_nll launch");
+    return ok();
+}
+
+lagp_status lagp_local_nll_backward(const double *X, const double *Y, int64_t N, int32_t p,
+                                    const int32_t *sel, int64_t M, int32_t n, const double *d,
+                                    const double *g, const double *grad_out, double *grad_d, double *grad_g,
+                                    void *stream)
+{
+    lagp_status s = check_local(X, Y, N, p, sel, M, n);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && (!d || !g)) return fail(LAGP_EINVAL, "d and g must be non-NULL");
+    if (M == 0) return ok();
+    lagp::GpArgs a{};
+    a.X = X; a.Y = Y; a.N = N; a.p = p; a.sel = sel; a.M = M; a.n = n;
+    a.d_arr = d; a.g_arr = g; a.grad_out = grad_out; a.dd = grad_d; a.dg = grad_g;
+    hipError_t e = lagp::launch_local_gp(a, lagp::kGpBackward, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "local_nll_backward launch");
+    return ok();
+}
+
+lagp_status lagp_local_mle_d(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                             int64_t M, int32_t n, const double *d0, double g, double dmin, double dmax,
+                             int32_t maxit, double *d_hat, double *nll, int32_t *iters, int32_t *status,
+                             void *stream)
+{
+    lagp_status s = check_local(X, Y, N, p, sel, M, n);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && (!d0 || !d_hat)) return fail(LAGP_EINVAL, "d0 and d_hat must be non-NULL");
+    if (!(g > 0.0) || !isfinite(g)) return fail(LAGP_EINVAL, "nugget g must be finite and > 0");
+    if (!(dmin > 0.0) || !(dmax >= dmin) || !isfinite(dmax))
+        return fail(LAGP_EINVAL, "need 0 < dmin <= dmax < inf");
+    if (maxit < 0) return fail(LAGP_EINVAL, "maxit = %d < 0", maxit);
+    if (M == 0) return ok();
+    lagp::GpArgs a{};
+    a.X = X; a.Y = Y; a.N = N; a.p = p; a.sel = sel; a.M = M; a.n = n;
+    a.d_arr = d0; a.g_scalar = g; a.dmin = dmin; a.dmax = dmax; a.maxit = maxit;
+    a.d_hat = d_hat; a.nll = nll; a.iters = iters; a.status = status;
+    hipError_t e = lagp::launch_local_gp(a, lagp::kGpMle, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "local_mle_d launch");
+    return ok();
+}
+
+lagp_status lagp_local_predict(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
+                               int64_t M, int32_t n, const double *XX, const double *d, double g, double *mean,
+                               double *s2, double *var, int32_t *status, void *stream)
+{
+    lagp_status s = check_local(X, Y, N, p, sel, M, n);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && (!XX || !d)) return fail(LAGP_EINVAL, "XX and d must be non-NULL");
+    if (!(g > 0.0) || !isfinite(g)) return fail(LAGP_EINVAL, "nugget g must be finite and > 0");
+    if (M == 0) return ok();
+    lagp::GpArgs a{};
+    a.X = X; a.Y = Y; a.N = N; a.p = p; a.sel = sel; a.M = M; a.n = n;
+    a.d_arr = d; a.g_scalar = g; a.XX = XX; a.mean = mean; a.s2 = s2; a.var = var; a.status = status;
+    hipError_t e = lagp::launch_local_gp(a, lagp::kGpPredict, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "local_predict launch");
+    return ok();
+}
+
 const char *lagp_status_string(lagp_status s)
 {
     switch (s) {

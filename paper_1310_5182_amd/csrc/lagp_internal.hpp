@@ -40,4 +40,33 @@ hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, i
 bool alc_supported(int precision, int p, int Np, int n);
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st);
 
+// Local likelihood / MLE / fixed-design prediction, one wave per location.
+struct GpArgs {
+    const double *X, *Y;
+    int64_t N;
+    int p;
+    const int32_t *sel;
+    int64_t M;
+    int n;
+    // per-location parameters (arrays of M) or scalars
+    const double *d_arr;
+    double d_scalar;
+    const double *g_arr;
+    double g_scalar;
+    // outputs / inputs by mode
+    double *nll, *dd, *dg, *d2;
+    const double *grad_out;
+    double dmin, dmax;
+    int maxit;
+    double *d_hat;
+    int32_t *iters, *status;
+    const double *XX;
+    double *mean, *s2, *var;
+};
+
+enum GpMode { kGpNll = 0, kGpBackward = 1, kGpMle = 2, kGpPredict = 3 };
+bool local_gp_supported(int n, int p);
+size_t local_gp_lds(int n, int p);
+hipError_t launch_local_gp(const GpArgs &a, int mode, hipStream_t st);
+
 }  // namespace lagp

@@ -104,3 +104,19 @@ def test_python_binding_rejects_cpu_tensors():
 
     with pytest.raises(ValueError):
         lagp.nn_pool(torch.zeros(10, 2, dtype=torch.float64), torch.zeros(2, 2, dtype=torch.float64), 3)
+
+
+def test_local_validation(L):
+    P = FAKE
+    # n outside [1, 64]
+    assert L.lagp_local_nll(P, P, 100, 2, P, 3, 0, P, P, P, None, None, None, None, None) == -1
+    assert L.lagp_local_nll(P, P, 100, 2, P, 3, 65, P, P, P, None, None, None, None, None) == -4
+    assert L.lagp_local_nll(P, P, 100, 2, None, 3, 10, P, P, P, None, None, None, None, None) == -1
+    assert L.lagp_local_nll(P, P, 100, 2, P, 0, 10, P, P, P, None, None, None, None, None) == 0
+    # MLE bounds and nugget
+    assert L.lagp_local_mle_d(P, P, 100, 2, P, 3, 10, P, 1e-3, 0.0, 5.0, 100, P, None, None, None, None) == -1
+    assert L.lagp_local_mle_d(P, P, 100, 2, P, 3, 10, P, 1e-3, 1.0, 0.5, 100, P, None, None, None, None) == -1
+    assert L.lagp_local_mle_d(P, P, 100, 2, P, 3, 10, P, 0.0, 1e-3, 5.0, 100, P, None, None, None, None) == -1
+    assert L.lagp_local_mle_d(P, P, 100, 2, P, 3, 10, P, 1e-3, 1e-3, 5.0, -1, P, None, None, None, None) == -1
+    assert L.lagp_local_predict(P, P, 100, 2, P, 3, 10, None, P, 1e-3, None, None, None, None, None) == -1
+    assert L.lagp_local_nll_backward(P, P, 100, 2, P, 3, 10, None, P, None, P, P, None) == -1
