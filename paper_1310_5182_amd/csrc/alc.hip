@@ -69,8 +69,6 @@ constexpr double kTrustErr = 1.0 / 256;
 constexpr float kSmallS = 1.0f / 131072;
 constexpr int kPmax = 8;
 
-constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4;
-
 // Element (i, l) of an R-sized matrix stored in 16x4 A-fragment tiles.
 template <int KG>
 __device__ __forceinline__ int ridx(int i, int l)
@@ -559,16 +557,24 @@ static hipError_t launch_t(const AlcArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-bool alc_supported(int precision, int p, int Np, int n)
+static bool mfma_supported(int precision, int p, int Np, int n)
 {
     if (p > kPmax || Np > 1024) return false;
     return precision == 0 ? n <= 52 : n <= 64;
 }
 
+bool alc_supported(int precision, int p, int Np, int n)
+{
+    if (precision == 0 && alc_inc_supported(p, Np, n)) return true;
+    return mfma_supported(precision, p, Np, n);
+}
+
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st)
 {
     if (a.M == 0) return hipSuccess;
-    if (!alc_supported(precision, a.p, a.Np, a.n)) return hipErrorNotSupported;
+    // float64: incremental Cholesky columns where a schedule fits, else the MFMA kernel
+    if (precision == 0 && alc_inc_supported(a.p, a.Np, a.n)) return launch_alc_inc(a, st);
+    if (!mfma_supported(precision, a.p, a.Np, a.n)) return hipErrorNotSupported;
     if (precision == 0) {
         if (a.Np <= 512) return launch_t<double, 4, 8, 13, 1>(a, st);
         return launch_t<double, 8, 8, 13, 1>(a, st);

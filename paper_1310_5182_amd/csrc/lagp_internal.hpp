@@ -8,6 +8,9 @@ namespace lagp {
 
 constexpr int kMaxP = 16;  // largest input dimension any kernel accepts
 
+// Per-location status codes (the LAGP_LOC_* values of the public header).
+constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4;
+
 struct AlcArgs {
     const double *X;
     const double *Y;
@@ -39,6 +42,10 @@ hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, i
 // covers (p, Np, n, precision).
 bool alc_supported(int precision, int p, int Np, int n);
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st);
+
+// Float64 greedy ALC by incremental Cholesky columns.
+bool alc_inc_supported(int p, int Np, int n);
+hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st);
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

@@ -83,7 +83,7 @@ def test_alc_validation(L):
     assert alc(L, Y=None) == -1
     assert alc(L, sel=None) == -1
     assert alc(L, N=5000, Np=2000, n=50) == -4
-    assert alc(L, n=60, Np=100, prec=0) == -4
+    assert alc(L, N=5000, n=130, Np=200, prec=0) == -4
     assert alc(L, p=9) == -4
     assert alc(L, M=0) == 0
 
