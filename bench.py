@@ -1,14 +1,17 @@
 """Benchmark of the local approximate GP hot path on one MI355X.
 
 One step = the whole path over one batch of predictive locations: NN
-candidate pools, greedy ALC local designs (n0 -> n) and local predictions.
-Default workload: N = 100,000 design points uniform on [0,1]^8, M = 10,000
-predictive locations, n0 = 6, n = 50, N' = 1000, d = 0.5, g = 1e-4 (seeded
-synthetic data).  `value` is predictive locations per second of the
-mixed-precision path with inputs resident in HBM; the float64 path is timed
-beside it.
+candidate pools, greedy ALC local designs (n0 -> n) and local predictions
+(config 4 adds the per-location MLE of d and the re-prediction).  Inputs are
+seeded synthetic data resident in HBM before the timed region.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Default workload (config 2): N = 100,000 design points uniform on [0,1]^8,
+M = 10,000 predictive locations, n0 = 6, n = 50, N' = 1000, d = 0.5,
+g = 1e-4.  `value` is predictive locations per second of the headline
+precision; the other precision is timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C] [--M M]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -23,13 +26,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_vector": 78.6e12, "hbm": 8.0e12}
 
 
-def alc_flops(n0: int, n: int, Np: int) -> float:
-    """Algorithmic flops of the candidate scoring for one location: every
-    step j scores the Np - j candidates at 2 j^2 flops each (the O(j^2)
-    per-candidate cost of eq. dxy, Sec. 3.1)."""
+def inc_flops(n0: int, n: int, Np: int) -> float:
+    """Algorithmic flops of the float64 incremental-column ALC for one location:
+    adding design point j (0 <= j < n - 1) extends the factor row of each of the
+    Np - j - 1 remaining candidates by one entry, a j-term dot product
+    (2 j flops) plus the update of its variance and covariance (4 flops)."""
+    return float(sum((Np - j - 1) * (2.0 * j + 4.0) for j in range(n - 1)))
+
+
+def mfma_flops(n0: int, n: int, Np: int) -> float:
+    """Algorithmic flops of the per-step re-scoring route (the paper's O(j^2)
+    per-candidate evaluation of eq. dxy, Sec. 3.1), used by the MFMA kernels."""
     return float(sum(2.0 * (Np - j) * j * j for j in range(n0, n)))
 
 
@@ -37,12 +47,29 @@ def alc_evals(n0: int, n: int, Np: int) -> int:
     return sum(Np - j for j in range(n0, n))
 
 
+class Timer:
+    """HIP events on the stream the library launches on (torch's current one)."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, fn, reps):
+        ev = lambda: self.torch.cuda.Event(enable_timing=True)  # noqa: E731
+        e0, e1 = ev(), ev()
+        e0.record(self.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(self.stream)
+        self.torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--M", type=int, default=None, help="predictive locations (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
@@ -72,66 +99,108 @@ def main() -> int:
     import paper_1310_5182_amd as lagp
     import workloads
 
-    W = workloads.make(args.config, M=args.M)
+    cfg = args.config
+    W = workloads.make(cfg, M=args.M)
     n0, n, Np, d, g = W.n0, W.n, W.Np, W.d, W.g
-    print(f"[bench] workload config{args.config}: N={W.N} p={W.p} M={W.M} n0={n0} n={n} Np={Np}",
+    M = W.M
+    print(f"[bench] workload config{cfg}: N={W.N} p={W.p} M={M} n0={n0} n={n} Np={Np}",
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     X = torch.from_numpy(W.X).to(dev)
     Y = torch.from_numpy(W.Y).to(dev)
     XX = torch.from_numpy(W.XX).to(dev)
-    M = W.M
-    precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
-    outs = {p: None for p in precs}
     stream = torch.cuda.current_stream(dev)
+    timer = Timer(torch, stream)
 
-    def full_step(prec):
-        outs[prec] = lagp.alc_predict(X, Y, XX, n0, n, Np, d, g, prec, out=outs[prec])
+    # ---- the whole step per path
+    paths = {}
+    if cfg == 3:
+        n_per, Np_per = torch.from_numpy(W.n_per).to(dev), torch.from_numpy(W.Np_per).to(dev)
+        o3 = {}
+
+        def step_uneven():
+            lagp.alc_uneven_predict(X, Y, XX, n0, n, Np, d, g, n_per=n_per, Np_per=Np_per, out=o3)
+
+        paths["fp64"] = (step_uneven, o3)
+        precs = ["fp64"]
+    elif cfg == 4:
+        o4 = {}
+        d0 = torch.full((M,), d, dtype=torch.float64, device=dev)
+
+        def step_mle():
+            lagp.alc_predict(X, Y, XX, n0, n, Np, d, g, "fp64", out=o4)
+            o4["mle"] = lagp.local_mle_d(X, Y, o4["sel"], d0, g, 1e-3, 5.0, 100)
+            o4["pred"] = lagp.local_predict(X, Y, o4["sel"], XX, o4["mle"]["d"], g)
+
+        paths["fp64"] = (step_mle, o4)
+        precs = ["fp64"]
+    else:
+        precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+        for prec in precs:
+            o = {}
+
+            def step(prec=prec, o=o):
+                lagp.alc_predict(X, Y, XX, n0, n, Np, d, g, prec, out=o)
+
+            paths[prec] = (step, o)
 
     res = {}
     for prec in precs:
+        fn, _ = paths[prec]
         for _ in range(args.warmup):
-            full_step(prec)
+            fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            full_step(prec)
+            fn()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         res[prec] = dict(ms_per_step=dt * 1e3, loc_per_s=M / dt)
         print(f"[bench] {prec}: {dt * 1e3:.2f} ms/step, {M / dt:.1f} loc/s", file=sys.stderr, flush=True)
 
-    # Per-kernel timing with HIP events on the stream the library launches on.
-    pool = outs[precs[0]]["pool"]
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    e0, e1 = ev(), ev()
-    e0.record(stream)
-    for _ in range(args.steps):
-        lagp.nn_pool(X, XX, Np, out=pool)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    nn_ms = e0.elapsed_time(e1) / args.steps
-    alc_ms = {}
-    for prec in precs:
-        o = outs[prec]
-        e0, e1 = ev(), ev()
-        e0.record(stream)
-        for _ in range(args.steps):
-            lagp.alc_from_pool(X, Y, XX, pool, n0, n, d, g, prec, out=o)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        alc_ms[prec] = e0.elapsed_time(e1) / args.steps
-        print(f"[bench] kernels: nn_pool {nn_ms:.3f} ms, alc[{prec}] {alc_ms[prec]:.3f} ms",
-              file=sys.stderr, flush=True)
+    # ---- per-kernel timing with HIP events, same launches as in the step
+    o = paths[precs[0]][1]
+    pool = o["pool"]
+    kms = {"nn_pool": timer.run(lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool), args.steps)}
+    if cfg == 3:
+        kms["alc_fp64_uneven"] = timer.run(
+            lambda: lagp.alc_uneven_from_pool(X, Y, XX, pool, n0, n, d, g, n_per=n_per, Np_per=Np_per,
+                                              out=o), args.steps)
+    else:
+        for prec in precs:
+            op = paths[prec][1]
+            kms[f"alc_{prec}"] = timer.run(
+                lambda op=op, prec=prec: lagp.alc_from_pool(X, Y, XX, pool, n0, n, d, g, prec, out=op),
+                args.steps)
+    if cfg == 4:
+        kms["local_mle_d"] = timer.run(lambda: lagp.local_mle_d(X, Y, o["sel"], d0, g, 1e-3, 5.0, 100),
+                                       args.steps)
+        kms["local_predict"] = timer.run(lambda: lagp.local_predict(X, Y, o["sel"], XX, o["mle"]["d"], g),
+                                         args.steps)
+    print(f"[bench] kernels (ms): {json.dumps(kms)}", file=sys.stderr, flush=True)
 
+    # ---- roofline of the ALC kernel of the headline path
     head = "mixed" if "mixed" in precs else "fp64"
-    flops = alc_flops(n0, n, Np) * M
-    peak = PEAK["fp32_mfma"] if head == "mixed" else PEAK["fp64_mfma"]
-    achieved = flops / (alc_ms[head] * 1e-3)
-    o = outs[head]
-    status = o["status"].cpu().numpy()
-    guard = o["guard"].cpu().numpy()
-    evals = alc_evals(n0, n, Np) * M
+    st = o["status"].cpu().numpy()
+    if cfg == 3:
+        nn_, Npn = W.n_per.astype(np.int64), W.Np_per.astype(np.int64)
+        flops = float(sum(inc_flops(n0, int(a), int(b)) for a, b in zip(nn_, Npn)))
+        evals = int(sum(alc_evals(n0, int(a), int(b)) for a, b in zip(nn_, Npn)))
+        kname, kms_head = "alc_inc_kernel (uneven, float64)", kms["alc_fp64_uneven"]
+        bound, peak, unit = "alu", PEAK["fp64_vector"], "TFLOP/s"
+        per_unit = "sum over locations of sum_{j<n_m-1} (N'_m-j-1)(2j+4) flops"
+    elif head == "mixed":
+        flops, evals = mfma_flops(n0, n, Np) * M, alc_evals(n0, n, Np) * M
+        kname, kms_head = "alc_kernel<float> (mixed, MFMA)", kms["alc_mixed"]
+        bound, peak, unit = "mfma", PEAK["fp32_mfma"], "TFLOP/s"
+        per_unit = f"{mfma_flops(n0, n, Np):.4g} flops per location (sum_j 2(N'-j)j^2)"
+    else:
+        flops, evals = inc_flops(n0, n, Np) * M, alc_evals(n0, n, Np) * M
+        kname, kms_head = "alc_inc_kernel (float64)", kms["alc_fp64"]
+        bound, peak, unit = "alu", PEAK["fp64_vector"], "TFLOP/s"
+        per_unit = f"{inc_flops(n0, n, Np):.4g} flops per location (sum_j (N'-j-1)(2j+4))"
+    achieved = flops / (kms_head * 1e-3)
+    guard = o["guard"].cpu().numpy() if "guard" in o else np.zeros(M)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -141,15 +210,27 @@ def main() -> int:
         orc = oracle.default()
         threads = orc.max_threads()
         t0 = time.perf_counter()
-        orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
+        if cfg == 3:
+            pool_h = orc.nn_pool(W.X, W.XX[:S], Np, threads=threads)
+            orc.alc(W.X, W.Y, W.XX[:S], pool_h, n0, n, d, g, n_per=W.n_per[:S], Np_per=W.Np_per[:S],
+                    threads=threads)
+            what = "NN pool + ALC design + prediction with per-location n, N'"
+        elif cfg == 4:
+            r = orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
+            orc.local_mle(W.X, W.Y, r["sel"], d, g, 1e-3, 5.0, 100)
+            what = "NN pool + ALC design at d0 + MLE of d"
+        else:
+            orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
+            what = "NN pool + ALC design + prediction"
         dt = time.perf_counter() - t0
         cpu = dict(value=S / dt, unit="loc/s", cores=threads, kind="oracle",
-                   sample=f"first {S} of the {M} locations, NN pool + ALC design + prediction, "
-                          f"float64, OpenMP over locations ({dt:.1f} s wall)")
+                   sample=f"first {S} of the {M} locations, {what}, float64, OpenMP over "
+                          f"locations ({dt:.1f} s wall)")
         print(f"[bench] cpu oracle: {S / dt:.1f} loc/s on {threads} threads", file=sys.stderr, flush=True)
 
+    metric = "predictive locations/sec (n=50 ALC, N'=1000) mixed vs FP64; ALC evals/sec"
     line = {
-        "metric": "predictive locations/sec (n=50 ALC, N'=1000) mixed vs FP64; ALC evals/sec",
+        "metric": metric,
         "value": res[head]["loc_per_s"],
         "unit": "loc/s",
         "n_gpus": 1,
@@ -161,18 +242,20 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"config{args.config}: N={W.N} p={W.p} uniform design, M={M} "
-                               f"locations, n0={n0}, n={n}, N'={Np}, d={d}, g={g}",
+        "config": {"workload": f"config{cfg}: N={W.N} p={W.p} uniform design, M={M} locations, n0={n0}, "
+                               + (f"n=U[20,100], N'=U[200,2000] per location" if cfg == 3 else
+                                  f"n={n}, N'={Np}") + f", d={d}, g={g}"
+                               + (", then MLE of d in [1e-3, 5]" if cfg == 4 else ""),
                    "precision": head},
-        "fp64_loc_per_s": res.get("fp64", {}).get("loc_per_s"),
-        "mixed_over_fp64": (res["mixed"]["loc_per_s"] / res["fp64"]["loc_per_s"]) if len(precs) == 2 else None,
-        "alc_evals_per_s": evals / (alc_ms[head] * 1e-3),
-        "kernel_ms": {"nn_pool": nn_ms, **{f"alc_{k}": v for k, v in alc_ms.items()}},
-        "guard_steps_frac": float(guard.sum()) / (M * (n - n0)),
-        "status_nonzero": int(np.count_nonzero(status)),
-        "roofline": {"kernel": f"alc_kernel<{'float' if head == 'mixed' else 'double'}>",
-                     "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None},
+        "loc_per_s": {k: v["loc_per_s"] for k, v in res.items()},
+        "mixed_over_fp64": (res["mixed"]["loc_per_s"] / res["fp64"]["loc_per_s"])
+        if "mixed" in res and "fp64" in res else None,
+        "alc_evals_per_s": evals / (kms_head * 1e-3),
+        "kernel_ms": kms,
+        "guard_steps_frac": float(guard.sum()) / max(1, M * (n - n0)),
+        "status_nonzero": int(np.count_nonzero(st)),
+        "roofline": {"kernel": kname, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": unit, "frac": achieved / peak, "traffic": None, "per_unit": per_unit},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

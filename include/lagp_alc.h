@@ -63,6 +63,8 @@ typedef int32_t lagp_status;
 #define LAGP_LOC_NONFINITE 3    /* x not finite                                 */
 #define LAGP_LOC_BAD_POOL 4     /* a pool entry outside [0, N): the location is */
                                 /* skipped, no design row is read               */
+#define LAGP_LOC_BAD_SHAPE 5    /* per-location n or N' outside the bounds of   */
+                                /* lagp_alc_uneven_from_pool                    */
 
 /*
  * lagp_nn_pool -- nearest-neighbour candidate pools (Sec. 2.2, Sec. 3.1).
@@ -104,8 +106,10 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
  *                           were not trusted and were redone in float64; 0 for
  *                           LAGP_FP64
  * Exact score ties go to the smallest design index.
- * Supported sizes: p <= 8, Np <= 1024, n <= 52 for LAGP_FP64 and n <= 64
- * for LAGP_MIXED.  Others return LAGP_EUNSUPPORTED.
+ * Supported sizes: p <= 8 and Np <= 1024; LAGP_MIXED needs n <= 64, and
+ * LAGP_FP64 needs every candidate's factor row on chip (n <= 50 at p = 8,
+ * N' = 1024; larger n at smaller p or N').  Others return LAGP_EUNSUPPORTED
+ * (lagp_alc_uneven_from_pool covers them in float64).
  */
 lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,
@@ -123,6 +127,45 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                              double d, double g, int32_t precision, int32_t *pool,
                              double *mean, double *s2, double *var, int32_t *sel, double *alc,
                              int32_t *status, int32_t *guard, void *stream);
+
+/*
+ * lagp_alc_uneven_workspace -- bytes of device workspace that
+ * lagp_alc_uneven_from_pool needs for these bounds on the current device.
+ */
+lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes);
+
+/*
+ * lagp_alc_uneven_from_pool -- lagp_alc_from_pool with a design size n_m
+ * and a pool size N'_m of its own for every location (float64).
+ *
+ *   pool [M x Np_max]       pools as written by lagp_nn_pool with Np_max;
+ *                           location m uses its first N'_m entries, which are
+ *                           exactly its N'_m nearest neighbours
+ *   n_per [M], Np_per [M]   per-location n and N' (device int32; NULL means
+ *                           n_max, respectively Np_max, everywhere); each
+ *                           needs n0 <= n_m <= n_max and n_m <= N'_m <= Np_max,
+ *                           else status[m] = LAGP_LOC_BAD_SHAPE
+ *   sel_off [M + 1]         device int64 row offsets of sel and alc (row m is
+ *                           [sel_off[m], sel_off[m] + n_m)); NULL: row m
+ *                           starts at m * n_max and entries n_m .. n_max - 1
+ *                           are set to -1 (alc NaN)
+ *   workspace               device memory of at least the size reported by
+ *                           lagp_alc_uneven_workspace (else LAGP_EWORKSPACE);
+ *                           holds the location queue and the factor-row
+ *                           entries that do not fit on chip.  Calls that
+ *                           overlap must not share it.
+ * Locations are ordered on the device by pool size class and then by
+ * decreasing cost N'_m n_m^2; persistent workgroups take them from that
+ * queue.  Other arguments and outputs as for lagp_alc_from_pool.
+ * Supported: precision LAGP_FP64, p <= 8, Np_max <= 2048, n_max <= 128.
+ */
+lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
+                                      const double *XX, int64_t M, const int32_t *pool, int32_t Np_max,
+                                      int32_t n0, int32_t n_max, const int32_t *n_per,
+                                      const int32_t *Np_per, const int64_t *sel_off, double d, double g,
+                                      int32_t precision, double *mean, double *s2, double *var,
+                                      int32_t *sel, double *alc, int32_t *status, int32_t *guard,
+                                      void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Local likelihood on fixed local designs (Sec. 2.1 eq. gpk, Fig. 1 step 3).

@@ -6,13 +6,15 @@ path runs in the library's HIP kernels.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "local_nll", "LocalNLL", "local_mle_d",
-           "local_predict", "PRECISIONS", "version"]
+__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict",
+           "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED}
 
@@ -55,16 +57,15 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
     return out
 
 
-def _outputs(M: int, n: int, device) -> dict:
-    return dict(
-        mean=torch.empty(M, dtype=torch.float64, device=device),
-        s2=torch.empty(M, dtype=torch.float64, device=device),
-        var=torch.empty(M, dtype=torch.float64, device=device),
-        sel=torch.empty((M, n), dtype=torch.int32, device=device),
-        alc=torch.empty((M, n), dtype=torch.float64, device=device),
-        status=torch.empty(M, dtype=torch.int32, device=device),
-        guard=torch.empty(M, dtype=torch.int32, device=device),
-    )
+def _outputs(M: int, n: int, device, out: dict | None = None) -> dict:
+    """The output tensors of an ALC call; entries missing from `out` are added to it."""
+    o = out if out is not None else {}
+    f64, i32 = torch.float64, torch.int32
+    for k, shape, dt in (("mean", (M,), f64), ("s2", (M,), f64), ("var", (M,), f64), ("sel", (M, n), i32),
+                         ("alc", (M, n), f64), ("status", (M,), i32), ("guard", (M,), i32)):
+        if k not in o:
+            o[k] = torch.empty(shape, dtype=dt, device=device)
+    return o
 
 
 def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision="fp64",
@@ -76,7 +77,7 @@ def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision
         raise ValueError("pool must be a contiguous int32 device tensor")
     M, p = XX.shape
     Np = pool.shape[1]
-    o = out if out is not None else _outputs(M, n, X.device)
+    o = _outputs(M, n, X.device, out)
     _lib.check(L.lagp_alc_from_pool(
         X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np, n0, n,
         float(d), float(g), _prec(precision), o["mean"].data_ptr(), o["s2"].data_ptr(),
@@ -91,7 +92,7 @@ def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precisio
     L = _lib.load()
     X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
     M, p = XX.shape
-    o = out if out is not None else _outputs(M, n, X.device)
+    o = _outputs(M, n, X.device, out)
     if "pool" not in o:
         o["pool"] = torch.empty((M, Np), dtype=torch.int32, device=X.device)
     _lib.check(L.lagp_alc_predict(
@@ -100,6 +101,62 @@ def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precisio
         o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["status"].data_ptr(),
         o["guard"].data_ptr(), _stream(X.device)))
     return o
+
+
+def _i32(t, name: str, M: int) -> int:
+    if t is None:
+        return 0
+    if t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda or t.numel() != M:
+        raise ValueError(f"{name} must be a contiguous int32 device tensor of length M")
+    return t.data_ptr()
+
+
+def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float, n_per=None,
+                         Np_per=None, sel_off=None, precision="fp64", out: dict | None = None) -> dict:
+    """Greedy ALC designs with a design size n_per[m] and a pool size Np_per[m]
+    of each location's own (int32 device tensors, None = n_max / the pool
+    width).  pool: M x Np_max from nn_pool(X, XX, Np_max).  Without sel_off,
+    sel and alc are M x n_max with entries past n_per[m] set to -1 / NaN;
+    with sel_off (int64, M + 1 offsets) they are flat rows, and `out` must
+    supply sel and alc of length sel_off[M]."""
+    L = _lib.load()
+    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
+    if pool.dtype != torch.int32 or not pool.is_contiguous() or not pool.is_cuda:
+        raise ValueError("pool must be a contiguous int32 device tensor")
+    M, p = XX.shape
+    Np_max = pool.shape[1]
+    dev = X.device
+    if sel_off is not None:
+        if sel_off.dtype != torch.int64 or not sel_off.is_contiguous() or sel_off.numel() != M + 1:
+            raise ValueError("sel_off must be a contiguous int64 device tensor of length M + 1")
+        if out is None or "sel" not in out or "alc" not in out:
+            raise ValueError("with sel_off, out must supply flat sel (int32) and alc (float64)")
+    o = _outputs(M, n_max, dev, out)
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(L.lagp_alc_uneven_workspace(p, M, Np_max, n_max, ctypes.byref(nbytes)))
+    ws = o.get("workspace")
+    if ws is None or ws.numel() < nbytes.value:
+        ws = o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+    _lib.check(L.lagp_alc_uneven_from_pool(
+        X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np_max, n0, n_max,
+        _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M),
+        sel_off.data_ptr() if sel_off is not None else 0, float(d), float(g), _prec(precision),
+        o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
+        o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), ws.data_ptr(), ws.numel(),
+        _stream(dev)))
+    return o
+
+
+def alc_uneven_predict(X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
+                       Np_per=None, precision="fp64", out: dict | None = None) -> dict:
+    """The whole path with per-location n and N': one pool of the Np_max nearest
+    neighbours per location (each location uses its own prefix), then
+    alc_uneven_from_pool."""
+    X, XX = _f64(X, "X"), _f64(XX, "XX")
+    o = out if out is not None else {}
+    o["pool"] = nn_pool(X, XX, Np_max, out=o.get("pool"))
+    return alc_uneven_from_pool(X, Y, XX, o["pool"], n0, n_max, d, g, n_per=n_per, Np_per=Np_per,
+                                precision=precision, out=o)
 
 
 def _sel(sel: torch.Tensor) -> torch.Tensor:

@@ -21,6 +21,8 @@ EXPORTS = (
     "lagp_nn_pool",
     "lagp_alc_from_pool",
     "lagp_alc_predict",
+    "lagp_alc_uneven_workspace",
+    "lagp_alc_uneven_from_pool",
     "lagp_local_nll",
     "lagp_local_nll_backward",
     "lagp_local_mle_d",
@@ -58,6 +60,11 @@ def load():
     L.lagp_alc_predict.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, f64, f64, i32, P,
                                    P, P, P, P, P, P, P, P]
     L.lagp_alc_predict.restype = i32
+    L.lagp_alc_uneven_workspace.argtypes = [i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_alc_uneven_workspace.restype = i32
+    L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, f64, f64,
+                                            i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.lagp_alc_uneven_from_pool.restype = i32
     L.lagp_local_nll.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P, P, P]
     L.lagp_local_nll.restype = i32
     L.lagp_local_nll_backward.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P]

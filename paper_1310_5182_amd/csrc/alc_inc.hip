@@ -13,309 +13,632 @@
 // length j per candidate (O(N' j)) instead of the O(N' j^2) of re-forming
 // every quadratic form, and needs no inverse at all; the arithmetic is that
 // of a row-by-row forward substitution, the same as a fresh factorisation.
+// The new entries of z_h and of t = L^{-1} Y need no dot products either:
+// w_h = cov*/lambda and t_j = r*/lambda, where cov* and r* = y* - z_{x*}.t
+// are the chosen candidate's carried conditional covariance and residual.
+// The prediction (eqs. predgp, preds2) accumulates mu = z_h.t, psi = t.t and
+// z_h.z_h entry by entry.
 //
-// Work split.  One workgroup per location; lane t owns the pool positions
-// t + s * TB (s < S).  Their z rows sit in registers (first ZR entries) and,
-// past ZR, in LDS columns.  A step: each wave reduces the argmax of its
-// candidates, every wave combines the per-wave winners, the winning lane
+// Work split.  One workgroup per location at a time; lane t owns the pool
+// positions t + s * TB (s < S).  Entry q of their z rows sits in registers
+// (q < ZR), in LDS columns (q < ZR + zl_cols) or in a per-workgroup global
+// workspace column (beyond), laid out [entry][position] so that every access
+// is a coalesced, lane-private one.  A step: each wave reduces the argmax of
+// its candidates, every wave combines the per-wave winners, the winning lane
 // publishes its z row (l) in LDS, and after one barrier every lane extends its
 // own rows.  Two barriers per scored step, one per forced (initial) step.
+//
+// Locations come either one per workgroup (uniform n and N', grid = M) or
+// from a queue that persistent workgroups drain with an atomic counter
+// (per-location n and N'; the queue is ordered by schedule and, within a
+// schedule, by decreasing cost so that the longest designs start first).
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
 #include <math.h>
+#include <mutex>
 
 namespace lagp {
 
 namespace {
 
-constexpr int kIncNmax = 128;  // largest n: z_h and R Y live in two lanes' worth of one wave
+constexpr int kIncNmax = 128;  // z_h and L^{-1} Y live in two lanes' worth of one wave
 constexpr int kIncPmax = 8;
+constexpr bool kIncRL = true;
 
-template <int TB, int S, int ZR>
-__global__ __launch_bounds__(TB) void alc_inc_kernel(AlcArgs a, int zl_cols)
+struct IncArgs {
+    AlcArgs a;                // a.n / a.Np: uniform values, or the upper bounds
+    const int32_t *n_per;     // [M] or NULL
+    const int32_t *Np_per;    // [M] or NULL
+    const int64_t *sel_off;   // [M + 1] or NULL: row m of sel / alc at m * a.n
+    int pool_stride;          // row stride of the pool (N'_max)
+    const int32_t *queue;     // location list, NULL: location = blockIdx.x
+    const int32_t *qinfo;     // [2]: first queue entry and count of this schedule
+    int32_t *counter;         // next queue entry of this schedule
+    double *gz;               // global z columns, gcols * CAP doubles per workgroup
+    int gcols;
+    int zl_cols;
+};
+
+// RL: the chosen row l reaches the lanes by v_readlane from a per-lane copy
+// (VALU) instead of uniform-address LDS reads (LDS return bandwidth).
+template <int TB, int S, int ZR, bool RL>
+__global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 {
     constexpr int NW = TB / kWave;
     constexpr int CAP = TB * S;
     constexpr int NCH = ZR / 8;
-    static_assert(ZR % 8 == 0 && NW <= kWave, "schedule shape");
+    static_assert(ZR % 8 == 0 && NW <= kWave && ZR <= kWave, "schedule shape");
+    const AlcArgs &a = x.a;
 
     extern __shared__ double dyn[];
     double *cx = dyn;                            // candidate coordinates, [k][pos]
     double *cY = cx + a.p * CAP;                 // response of each pool position
-    double *zl = cY + CAP;                       // z entries past ZR, [entry - ZR][pos]
-    int32_t *cid = (int32_t *)(zl + (size_t)zl_cols * CAP);  // design index, INT32_MAX if none
+    double *zl = cY + CAP;                       // z entries ZR.., [entry - ZR][pos]
+    int32_t *cid = (int32_t *)(zl + (size_t)x.zl_cols * CAP);  // design index, INT32_MAX if none
 
     __shared__ double ell[2][kIncNmax];  // z row of the point being added (by step parity)
-    __shared__ double pub_s[2];          // its conditional variance s*
-    __shared__ double zhs[kIncNmax], tYs[kIncNmax], alc_out[kIncNmax];
+    __shared__ double pub[2][3];         // its variance s*, covariance cov* and residual r*
+    __shared__ double alc_out[kIncNmax];
     __shared__ int32_t selpos[kIncNmax];
     __shared__ double xs[kIncPmax];
     __shared__ double red_s[NW];
     __shared__ int32_t red_i[NW], red_k[NW];
-    __shared__ int ctl_status;
+    __shared__ int ctl_status, ctl_loc;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t m = blockIdx.x;
-    const int p = a.p, Np = a.Np, n = a.n, n0 = a.n0;
+    const int p = a.p, n0 = a.n0;
     const double d = a.d, kappa = 1.0 + a.g;
+    const int G0 = ZR + x.zl_cols;  // first entry kept in global memory
+    double *gz = x.gz ? x.gz + (size_t)blockIdx.x * x.gcols * CAP : nullptr;
 
-    // ---- stage the location and its pool in LDS
-    if (tid == 0) ctl_status = kLocOk;
-    if (tid < p) xs[tid] = a.XX[m * p + tid];
-    __syncthreads();
-    for (int pos = tid; pos < CAP; pos += TB) {
-        bool valid = pos < Np;
-        int32_t di = valid ? a.pool[m * Np + pos] : INT32_MAX;
-        if (valid && (di < 0 || di >= a.N)) {  // never read outside X
-            ctl_status = kLocBadPool;
-            valid = false;
-        }
-        cid[pos] = valid ? di : INT32_MAX;
-        cY[pos] = valid ? a.Y[di] : 0.0;
-        for (int k = 0; k < p; k++) cx[k * CAP + pos] = valid ? a.X[(int64_t)di * p + k] : 0.0;
-    }
-    __syncthreads();
-    int status = ctl_status;
-    for (int k = 0; k < p; k++)
-        if (status == kLocOk && !isfinite(xs[k])) status = kLocNonfinite;
-
-    // ---- per-slot state: z row, conditional variance, conditional covariance
-    double z[S][ZR];
-    double sv[S], cv[S];
-    int32_t di[S];
-#pragma unroll
-    for (int s = 0; s < S; s++) {
-        const int pos = tid + s * TB;
-        di[s] = cid[pos];
-        const bool live = di[s] != INT32_MAX;
-        cv[s] = live ? corr64(sqdist_strict(cx + pos, CAP, xs, 1, p), d) : 0.0;
-        sv[s] = live ? kappa : -1.0;  // a negative variance marks "not a candidate"
-#pragma unroll
-        for (int q = 0; q < ZR; q++) z[s][q] = 0.0;
-    }
-
-    int j = 0;
-    for (; status == kLocOk && j < n; j++) {
-        const int par = j & 1;
-        // ===== (1) the point to add: forced pool order for the initial design,
-        // else the argmax of Delta (ties to the smaller design index)
-        int wpos = j;
-        double vbest = NAN;
-        if (j >= n0) {
-            double bs = -1.0;
-            int32_t bi = INT32_MAX;
-            int bk = -1;
-#pragma unroll
-            for (int s = 0; s < S; s++) {
-                if (sv[s] > 0.0) {
-                    const double sc = cv[s] * cv[s] / sv[s];
-                    if (beats(sc, di[s], bs, bi)) {
-                        bs = sc;
-                        bi = di[s];
-                        bk = tid + s * TB;
-                    }
-                }
-            }
-            wave_argmax(bs, bi, bk);
-            if (lane == 0) {
-                red_s[w] = bs;
-                red_i[w] = bi;
-                red_k[w] = bk;
-            }
+    for (int iter = 0;; iter++) {
+        // ---- next location
+        int64_t m;
+        if (x.queue) {
+            if (tid == 0) ctl_loc = atomicAdd(x.counter, 1);
             __syncthreads();
-            double v = lane < NW ? red_s[lane] : -1.0;
-            int32_t vi = lane < NW ? red_i[lane] : INT32_MAX;
-            int vk = lane < NW ? red_k[lane] : -1;
-            wave_argmax(v, vi, vk);
-            vbest = uniform(v);
-            wpos = __builtin_amdgcn_readfirstlane(vk);
-            if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
-                status = kLocStepFail;
-                break;
-            }
+            const int q = ctl_loc;
+            if (q >= x.qinfo[1]) break;
+            m = x.queue[x.qinfo[0] + q];
+        } else {
+            if (iter > 0) break;
+            m = blockIdx.x;
         }
-        // ===== (2) the owner publishes l = z_{x*} and s*, and retires the slot
-        const int ws = wpos / TB;
-        if (tid == wpos - ws * TB) {
-#pragma unroll
-            for (int s = 0; s < S; s++) {
-                if (s == ws) {
-#pragma unroll
-                    for (int c = 0; c < NCH; c++)
-                        if (c * 8 < j)
-#pragma unroll
-                            for (int u = 0; u < 8; u++) ell[par][c * 8 + u] = z[s][c * 8 + u];
-                    pub_s[par] = sv[s];
-                    sv[s] = -1.0;
-                }
+        const int n = x.n_per ? x.n_per[m] : a.n;
+        const int Np = x.Np_per ? x.Np_per[m] : a.Np;
+        const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
+
+        // ---- stage the location and its pool in LDS
+        if (tid == 0) ctl_status = kLocOk;
+        if (tid < p) xs[tid] = a.XX[m * p + tid];
+        __syncthreads();
+        for (int pos = tid; pos < CAP; pos += TB) {
+            bool valid = pos < Np;
+            int32_t di = valid ? a.pool[m * x.pool_stride + pos] : INT32_MAX;
+            if (valid && (di < 0 || di >= a.N)) {  // never read outside X
+                ctl_status = kLocBadPool;
+                valid = false;
             }
-            for (int q = ZR; q < j; q++) ell[par][q] = zl[(q - ZR) * CAP + wpos];
+            cid[pos] = valid ? di : INT32_MAX;
+            cY[pos] = valid ? a.Y[di] : 0.0;
+            for (int k = 0; k < p; k++) cx[k * CAP + pos] = valid ? a.X[(int64_t)di * p + k] : 0.0;
         }
         __syncthreads();
-        const double sstar = pub_s[par];
-        if (!(sstar > 0.0) || !isfinite(sstar)) {
-            status = j < n0 ? kLocInitNotPd : kLocStepFail;
-            break;
-        }
-        const double lam = sqrt(sstar);
-        const double *el = ell[par];
+        int status = ctl_status;
+        for (int k = 0; k < p; k++)
+            if (status == kLocOk && !isfinite(xs[k])) status = kLocNonfinite;
 
-        // ===== (3) z_h and L^{-1} Y gain their entry j (every wave, same bits)
-        double dz = 0.0, dt = 0.0;
-        if (lane < j) {
-            dz = el[lane] * zhs[lane];
-            dt = el[lane] * tYs[lane];
-        }
-        if (lane + kWave < j) {
-            dz = fma(el[lane + kWave], zhs[lane + kWave], dz);
-            dt = fma(el[lane + kWave], tYs[lane + kWave], dt);
-        }
-        dz = wave_sum(dz);
-        dt = wave_sum(dt);
-        const double kxs = corr64(sqdist_strict(cx + wpos, CAP, xs, 1, p), d);
-        const double wh = (kxs - dz) / lam;
-        if (tid == 0) {
-            zhs[j] = wh;
-            tYs[j] = (cY[wpos] - dt) / lam;
-            selpos[j] = wpos;
-            alc_out[j] = vbest;
-        }
-        if (j + 1 == n) continue;  // the design is complete: no more scoring
-
-        // ===== (4) every candidate's z row gains w_c = (K(c, x*) - z_c . l) / lambda
-        double acc[S];
-#pragma unroll
-        for (int s = 0; s < S; s++) acc[s] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NCH; c++) {
-            if (c * 8 < j) {
-                double e[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) e[u] = el[c * 8 + u];
-#pragma unroll
-                for (int u = 0; u < 8; u++)
-#pragma unroll
-                    for (int s = 0; s < S; s++) acc[s] = fma(z[s][c * 8 + u], e[u], acc[s]);
-            }
-        }
-        for (int q = ZR; q < j; q++) {
-            const double e = el[q];
-#pragma unroll
-            for (int s = 0; s < S; s++) acc[s] = fma(zl[(q - ZR) * CAP + tid + s * TB], e, acc[s]);
-        }
-        const int jc = j >> 3, ju = j & 7;
+        // ---- per-slot state: z row, conditional variance, covariance with x
+        // and residual y_c - z_c.t
+        double z[S][ZR];
+        double sv[S], cv[S], ty[S];
+        int32_t di[S];
 #pragma unroll
         for (int s = 0; s < S; s++) {
             const int pos = tid + s * TB;
-            const double kc = corr64(sqdist_strict(cx + pos, CAP, cx + wpos, CAP, p), d);
-            const double wc = (kc - acc[s]) / lam;
-            if (j < ZR) {
+            di[s] = cid[pos];
+            const bool live = di[s] != INT32_MAX;
+            cv[s] = live ? corr64(sqdist_strict(cx + pos, CAP, xs, 1, p), d) : 0.0;
+            sv[s] = live ? kappa : -1.0;  // a negative variance marks "not a candidate"
+            ty[s] = cY[pos];
 #pragma unroll
-                for (int c = 0; c < NCH; c++)
-                    if (c == jc)
-#pragma unroll
-                        for (int u = 0; u < 8; u++)
-                            if (u == ju) z[s][c * 8 + u] = wc;
-            } else {
-                zl[(j - ZR) * CAP + pos] = wc;
-            }
-            sv[s] = fma(-wc, wc, sv[s]);
-            cv[s] = fma(-wc, wh, cv[s]);
+            for (int q = 0; q < ZR; q++) z[s][q] = 0.0;
         }
-    }
-    __syncthreads();
+        double mu = 0.0, psi = 0.0, zz = 0.0;  // z_h.t, t.t, z_h.z_h so far
 
-    // ===== outputs: the design in the order added, its scores, the prediction
-    for (int jj = tid; jj < j; jj += TB) {
-        a.sel[m * n + jj] = cid[selpos[jj]];
-        if (a.alc) a.alc[m * n + jj] = alc_out[jj];
-    }
-    // local prediction (eqs. predgp, preds2): mu = z_h.(L^{-1} Y), psi = |L^{-1} Y|^2
-    if (w == 0) {
-        const bool ok = status == kLocOk;
-        double mu = 0.0, psi = 0.0, zz = 0.0;
-        for (int i = lane; ok && i < n; i += kWave) {
-            mu = fma(zhs[i], tYs[i], mu);
-            psi = fma(tYs[i], tYs[i], psi);
-            zz = fma(zhs[i], zhs[i], zz);
-        }
-        mu = wave_sum(mu);
-        psi = wave_sum(psi);
-        zz = wave_sum(zz);
-        if (lane == 0) {
-            const double s2 = psi * (kappa - zz) / n;
-            if (a.mean) a.mean[m] = ok ? mu : NAN;
-            if (a.s2) a.s2[m] = ok ? s2 : NAN;
-            if (a.var) a.var[m] = (ok && n > 2) ? s2 * n / (n - 2) : NAN;
-            if (a.status) a.status[m] = status;
-            if (a.guard) a.guard[m] = 0;
-        }
-        if (!ok)
-            for (int jj = j + lane; jj < n; jj += kWave) {
-                a.sel[m * n + jj] = -1;
-                if (a.alc) a.alc[m * n + jj] = NAN;
+        int j = 0;
+        for (; status == kLocOk && j < n; j++) {
+            const int par = j & 1;
+            // ===== (1) the point to add: forced pool order for the initial design,
+            // else the argmax of Delta (ties to the smaller design index)
+            int wpos = j;
+            double vbest = NAN;
+            if (j >= n0) {
+                double bs = -1.0;
+                int32_t bi = INT32_MAX;
+                int bk = -1;
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    if (sv[s] > 0.0) {
+                        const double sc = cv[s] * cv[s] / sv[s];
+                        if (beats(sc, di[s], bs, bi)) {
+                            bs = sc;
+                            bi = di[s];
+                            bk = tid + s * TB;
+                        }
+                    }
+                }
+                wave_argmax_ballot(bs, bi, bk);
+                if (lane == 0) {
+                    red_s[w] = bs;
+                    red_i[w] = bi;
+                    red_k[w] = bk;
+                }
+                __syncthreads();
+                double v = lane < NW ? red_s[lane] : -1.0;
+                int32_t vi = lane < NW ? red_i[lane] : INT32_MAX;
+                int vk = lane < NW ? red_k[lane] : -1;
+                wave_argmax(v, vi, vk);
+                vbest = uniform(v);
+                wpos = __builtin_amdgcn_readfirstlane(vk);
+                if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
+                    status = kLocStepFail;
+                    break;
+                }
             }
+            // ===== (2) the owner publishes l = z_{x*} and s*, and retires the slot
+            const int ws = wpos / TB;
+            if (tid == wpos - ws * TB) {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    if (s == ws) {
+#pragma unroll
+                        for (int c = 0; c < NCH; c++)
+                            if (c * 8 < j)
+#pragma unroll
+                                for (int u = 0; u < 8; u++) ell[par][c * 8 + u] = z[s][c * 8 + u];
+                        pub[par][0] = sv[s];
+                        pub[par][1] = cv[s];
+                        pub[par][2] = ty[s];
+                        sv[s] = -1.0;
+                    }
+                }
+                for (int q = ZR; q < j; q++)
+                    ell[par][q] = q < G0 ? zl[(q - ZR) * CAP + wpos] : gz[(size_t)(q - G0) * CAP + wpos];
+            }
+            __syncthreads();
+            const double sstar = pub[par][0];
+            if (!(sstar > 0.0) || !isfinite(sstar)) {
+                status = j < n0 ? kLocInitNotPd : kLocStepFail;
+                break;
+            }
+            const double lam = sqrt(sstar);
+            const double ilam = 1.0 / lam;
+            const double *el = ell[par];
+
+            // ===== (3) z_h and t = L^{-1} Y gain their entry j
+            const double wh = pub[par][1] / lam;
+            const double tn = pub[par][2] / lam;
+            mu = fma(wh, tn, mu);
+            psi = fma(tn, tn, psi);
+            zz = fma(wh, wh, zz);
+            if (tid == 0) {
+                selpos[j] = wpos;
+                alc_out[j] = vbest;
+            }
+            if (j + 1 == n) continue;  // the design is complete: no more scoring
+
+            // ===== (4) every candidate's z row gains w_c = (K(c, x*) - z_c . l) / lambda
+            double acc[S];
+#pragma unroll
+            for (int s = 0; s < S; s++) acc[s] = 0.0;
+            double lrow = 0.0;  // lane i holds l_i (register part of the row)
+            if constexpr (RL) lrow = lane < j && lane < ZR ? el[lane] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NCH; c++) {
+                if (c * 8 < j) {
+                    double e[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        if constexpr (RL)
+                            e[u] = readlane(lrow, c * 8 + u);
+                        else
+                            e[u] = el[c * 8 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+#pragma unroll
+                        for (int s = 0; s < S; s++) acc[s] = fma(z[s][c * 8 + u], e[u], acc[s]);
+                }
+            }
+            const int jl = j < G0 ? j : G0;
+            for (int q = ZR; q < jl; q++) {
+                const double e = el[q];
+#pragma unroll
+                for (int s = 0; s < S; s++) acc[s] = fma(zl[(q - ZR) * CAP + tid + s * TB], e, acc[s]);
+            }
+#pragma unroll 4
+            for (int q = G0; q < j; q++) {
+                const double e = el[q];
+                const double *col = gz + (size_t)(q - G0) * CAP + tid;
+#pragma unroll
+                for (int s = 0; s < S; s++) acc[s] = fma(col[s * TB], e, acc[s]);
+            }
+            const int jc = j >> 3, ju = j & 7;
+#pragma unroll
+            for (int s = 0; s < S; s++) {
+                const int pos = tid + s * TB;
+                const double kc = corr64(sqdist_strict(cx + pos, CAP, cx + wpos, CAP, p), d);
+                const double wc = (kc - acc[s]) * ilam;
+                if (j < ZR) {
+#pragma unroll
+                    for (int c = 0; c < NCH; c++)
+                        if (c == jc)
+#pragma unroll
+                            for (int u = 0; u < 8; u++)
+                                if (u == ju) z[s][c * 8 + u] = wc;
+                } else if (j < G0) {
+                    zl[(j - ZR) * CAP + pos] = wc;
+                } else {
+                    gz[(size_t)(j - G0) * CAP + pos] = wc;
+                }
+                sv[s] = fma(-wc, wc, sv[s]);
+                cv[s] = fma(-wc, wh, cv[s]);
+                ty[s] = fma(-wc, tn, ty[s]);
+            }
+        }
+        __syncthreads();
+
+        // ===== outputs: the design in the order added, its scores, the prediction
+        for (int jj = tid; jj < j; jj += TB) {
+            a.sel[orow + jj] = cid[selpos[jj]];
+            if (a.alc) a.alc[orow + jj] = alc_out[jj];
+        }
+        // local prediction (eqs. predgp, preds2): mu = z_h.t, psi = t.t
+        if (w == 0) {
+            const bool ok = status == kLocOk;
+            if (lane == 0) {
+                const double s2 = psi * (kappa - zz) / n;
+                if (a.mean) a.mean[m] = ok ? mu : NAN;
+                if (a.s2) a.s2[m] = ok ? s2 : NAN;
+                if (a.var) a.var[m] = (ok && n > 2) ? s2 * n / (n - 2) : NAN;
+                if (a.status) a.status[m] = status;
+                if (a.guard) a.guard[m] = 0;
+            }
+            if (!ok)
+                for (int jj = j + lane; jj < n; jj += kWave) {
+                    a.sel[orow + jj] = -1;
+                    if (a.alc) a.alc[orow + jj] = NAN;
+                }
+        }
+        // padded rows (no offsets, n below the row length): fill the tail
+        if (!x.sel_off)
+            for (int jj = n + tid; jj < a.n; jj += TB) {
+                a.sel[orow + jj] = -1;
+                if (a.alc) a.alc[orow + jj] = NAN;
+            }
+        __syncthreads();  // LDS is restaged for the next location
     }
 }
 
+// ---------------------------------------------------------------- schedules
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr size_t kStaticReserve = 8 * 1024;  // the kernel's static LDS, rounded up
+constexpr size_t kDynLds = kLdsLimit - kStaticReserve;
 
-template <int TB, int S, int ZR>
-size_t inc_dyn_lds(int p, int n)
+struct Sched {
+    int tb, s, zr;
+    constexpr int cap() const { return tb * s; }
+    // dynamic LDS bytes for p coordinates and zl LDS columns
+    size_t lds(int p, int zl) const { return (size_t)cap() * (8 * (size_t)p + 8 + 4 + 8 * (size_t)zl); }
+    // LDS columns that fit, capped at the n_max - 1 - ZR that are needed; -1
+    // if not even the coordinates fit
+    int zl_fit(int p, int n_max) const
+    {
+        const size_t base = lds(p, 0);
+        if (base > kDynLds) return -1;
+        const int need = n_max - 1 > zr ? n_max - 1 - zr : 0;
+        const int fit = (int)((kDynLds - base) / (8 * (size_t)cap()));
+        return need < fit ? need : fit;
+    }
+};
+
+// Schedule b serves pools of up to kSched[b].cap() positions.
+constexpr int kNumSched = 3;
+constexpr Sched kSched[kNumSched] = {{256, 2, 40}, {512, 2, 40}, {512, 4, 16}};
+
+template <int B>
+constexpr auto kernel_of()
 {
-    const int zl_cols = n - 1 > ZR ? n - 1 - ZR : 0;
-    return (size_t)TB * S * (8 * (size_t)p + 8 + 4 + 8 * (size_t)zl_cols);
+    if constexpr (B == 0)
+        return &alc_inc_kernel<kSched[0].tb, kSched[0].s, kSched[0].zr, kIncRL>;
+    else if constexpr (B == 1)
+        return &alc_inc_kernel<kSched[1].tb, kSched[1].s, kSched[1].zr, kIncRL>;
+    else
+        return &alc_inc_kernel<kSched[2].tb, kSched[2].s, kSched[2].zr, kIncRL>;
 }
 
-template <int TB, int S, int ZR>
-hipError_t inc_launch(const AlcArgs &a, hipStream_t st)
+const void *kernel_ptr(int b)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)alc_inc_kernel<TB, S, ZR>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kLdsLimit - kStaticReserve));
-        if (e != hipSuccess) return e;
-        attr_set = true;
+    switch (b) {
+    case 0:
+        return (const void *)kernel_of<0>();
+    case 1:
+        return (const void *)kernel_of<1>();
+    default:
+        return (const void *)kernel_of<2>();
     }
-    const int zl_cols = a.n - 1 > ZR ? a.n - 1 - ZR : 0;
-    const size_t lds = inc_dyn_lds<TB, S, ZR>(a.p, a.n);
-    hipLaunchKernelGGL((alc_inc_kernel<TB, S, ZR>), dim3((unsigned)a.M), dim3(TB), lds, st, a, zl_cols);
+}
+
+__host__ __device__ inline int sched_for(int Np)
+{
+    return Np <= kSched[0].cap() ? 0 : Np <= kSched[1].cap() ? 1 : Np <= kSched[2].cap() ? 2 : -1;
+}
+
+// CUs of the current device; the schedules' LDS limit set once per device.
+struct DevInfo {
+    int cus = 0;
+    bool ready = false;
+};
+
+hipError_t dev_info(DevInfo &out)
+{
+    static std::mutex mu;
+    static DevInfo cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    DevInfo &c = cache[dev];
+    if (!c.ready) {
+        e = hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        for (int b = 0; b < kNumSched; b++) {
+            e = hipFuncSetAttribute(kernel_ptr(b), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds);
+            if (e != hipSuccess) return e;
+        }
+        c.ready = true;
+    }
+    out = c;
+    return hipSuccess;
+}
+
+// Persistent grid of schedule b: every CU filled to the residency that its
+// registers and this launch's LDS allow.
+hipError_t persistent_grid(int b, size_t lds, int cus, int64_t *grid)
+{
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_ptr(b), kSched[b].tb, lds);
+    if (e != hipSuccess) return e;
+    *grid = (int64_t)cus * (nb > 0 ? nb : 1);
+    return hipSuccess;
+}
+
+hipError_t launch_sched(int b, const IncArgs &x, dim3 grid, size_t lds, hipStream_t st)
+{
+    switch (b) {
+    case 0:
+        hipLaunchKernelGGL(kernel_of<0>(), grid, dim3(kSched[0].tb), lds, st, x);
+        break;
+    case 1:
+        hipLaunchKernelGGL(kernel_of<1>(), grid, dim3(kSched[1].tb), lds, st, x);
+        break;
+    default:
+        hipLaunchKernelGGL(kernel_of<2>(), grid, dim3(kSched[2].tb), lds, st, x);
+        break;
+    }
     return hipGetLastError();
 }
 
-// Schedules: (threads, slots per lane, register entries per z row).
-enum IncSched { kIncNone = -1, kInc256x2, kInc512x2 };
+// ------------------------------------------------- queue of uneven locations
+constexpr int kBins = 64;  // cost classes per schedule
+constexpr int kKeys = kNumSched * kBins;
+constexpr size_t kHdrBytes = 4096;  // key counts, counters, queue slices
 
-IncSched inc_pick(int p, int Np, int n)
+struct PlanWs {
+    int32_t *hist;     // [kKeys] counts, then running insert offsets
+    int32_t *counter;  // [kNumSched]
+    int32_t *qinfo;    // [kNumSched][2]: first entry, count
+    int32_t *key;      // [M]
+    int32_t *queue;    // [M]
+};
+
+__global__ void plan_zero(PlanWs w)
 {
-    if (p > kIncPmax || n > kIncNmax) return kIncNone;
-    if (Np <= 512 && inc_dyn_lds<256, 2, 40>(p, n) <= kLdsLimit - kStaticReserve) return kInc256x2;
-    if (Np <= 1024 && inc_dyn_lds<512, 2, 40>(p, n) <= kLdsLimit - kStaticReserve) return kInc512x2;
-    return kIncNone;
+    const int t = threadIdx.x;
+    for (int i = t; i < kKeys; i += blockDim.x) w.hist[i] = 0;
+    if (t < kNumSched) {
+        w.counter[t] = 0;
+        w.qinfo[2 * t] = 0;
+        w.qinfo[2 * t + 1] = 0;
+    }
+}
+
+// Classify every location: its schedule and a cost class (four per octave of
+// N' n^2, the order of its update work), or a shape error written in place.
+__global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const AlcArgs &a = x.a;
+    const int n = x.n_per ? x.n_per[m] : a.n;
+    const int Np = x.Np_per ? x.Np_per[m] : a.Np;
+    const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
+    const int64_t rowlen = x.sel_off ? x.sel_off[m + 1] - x.sel_off[m] : a.n;
+    const bool ok = n >= a.n0 && n <= a.n && Np >= n && Np <= x.pool_stride && rowlen >= n;
+    const int b = ok ? sched_for(Np) : -1;
+    if (b < 0) {
+        w.key[m] = -1;
+        if (a.mean) a.mean[m] = NAN;
+        if (a.s2) a.s2[m] = NAN;
+        if (a.var) a.var[m] = NAN;
+        if (a.status) a.status[m] = kLocBadShape;
+        if (a.guard) a.guard[m] = 0;
+        for (int64_t jj = 0; jj < rowlen && jj < a.n; jj++) {
+            a.sel[orow + jj] = -1;
+            if (a.alc) a.alc[orow + jj] = NAN;
+        }
+        return;
+    }
+    const double cost = (double)Np * n * n;
+    int bin = (int)(4.0 * log2(cost)) - 40;
+    bin = bin < 0 ? 0 : bin > kBins - 1 ? kBins - 1 : bin;
+    const int key = b * kBins + (kBins - 1 - bin);  // larger cost first within a schedule
+    w.key[m] = key;
+    atomicAdd(&w.hist[key], 1);
+}
+
+// Exclusive scan of the key counts, and each schedule's slice of the queue.
+__global__ void plan_scan(PlanWs w)
+{
+    if (threadIdx.x != 0) return;
+    int run = 0;
+    for (int b = 0; b < kNumSched; b++) {
+        w.qinfo[2 * b] = run;
+        for (int i = 0; i < kBins; i++) {
+            const int c = w.hist[b * kBins + i];
+            w.hist[b * kBins + i] = run;
+            run += c;
+        }
+        w.qinfo[2 * b + 1] = run - w.qinfo[2 * b];
+    }
+}
+
+__global__ void plan_scatter(PlanWs w, int64_t M)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int key = w.key[m];
+    if (key < 0) return;
+    w.queue[atomicAdd(&w.hist[key], 1)] = (int32_t)m;
+}
+
+size_t align256(size_t v)
+{
+    return (v + 255) & ~(size_t)255;
+}
+
+// Global z columns per workgroup of schedule b for these bounds; -1 if the
+// schedule cannot hold the coordinates at all.
+int gcols_for(int b, int p, int n_max)
+{
+    const int zl = kSched[b].zl_fit(p, n_max);
+    if (zl < 0) return -1;
+    const int need = n_max - 1 - kSched[b].zr - zl;
+    return need > 0 ? need : 0;
 }
 
 }  // namespace
 
+// ---------------------------------------------------------------- host API
 bool alc_inc_supported(int p, int Np, int n)
 {
-    return inc_pick(p, Np, n) != kIncNone;
+    if (p > kIncPmax || n > kIncNmax) return false;
+    const int b = sched_for(Np);
+    return b >= 0 && gcols_for(b, p, n) == 0;
 }
 
 hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st)
 {
     if (a.M == 0) return hipSuccess;
-    switch (inc_pick(a.p, a.Np, a.n)) {
-    case kInc256x2:
-        return inc_launch<256, 2, 40>(a, st);
-    case kInc512x2:
-        return inc_launch<512, 2, 40>(a, st);
-    default:
-        return hipErrorNotSupported;
+    if (!alc_inc_supported(a.p, a.Np, a.n)) return hipErrorNotSupported;
+    DevInfo info;
+    hipError_t e = dev_info(info);
+    if (e != hipSuccess) return e;
+    const int b = sched_for(a.Np);
+    IncArgs x{};
+    x.a = a;
+    x.pool_stride = a.Np;
+    x.zl_cols = kSched[b].zl_fit(a.p, a.n);
+    return launch_sched(b, x, dim3((unsigned)a.M), kSched[b].lds(a.p, x.zl_cols), st);
+}
+
+bool alc_uneven_supported(int p, int Np_max, int n_max)
+{
+    if (p > kIncPmax || n_max > kIncNmax) return false;
+    const int top = sched_for(Np_max);
+    if (top < 0) return false;
+    for (int b = 0; b <= top; b++)
+        if (gcols_for(b, p, n_max) < 0) return false;
+    return true;
+}
+
+hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes)
+{
+    DevInfo info;
+    hipError_t e = dev_info(info);
+    if (e != hipSuccess) return e;
+    size_t total = kHdrBytes + 2 * align256((size_t)M * 4);
+    const int top = sched_for(Np_max);
+    for (int b = 0; b <= top; b++) {
+        const int gc = gcols_for(b, p, n_max);
+        int64_t grid = 0;
+        e = persistent_grid(b, kSched[b].lds(p, kSched[b].zl_fit(p, n_max)), info.cus, &grid);
+        if (e != hipSuccess) return e;
+        total += align256((size_t)grid * kSched[b].cap() * gc * 8);
     }
+    *bytes = total;
+    return hipSuccess;
+}
+
+hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
+                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    if (a.M == 0) return hipSuccess;
+    DevInfo info;
+    hipError_t e = dev_info(info);
+    if (e != hipSuccess) return e;
+    size_t need = 0;
+    e = alc_uneven_workspace(a.p, a.M, a.Np, a.n, &need);
+    if (e != hipSuccess) return e;
+    if (ws_bytes < need) return hipErrorInvalidValue;
+
+    char *base = (char *)ws;
+    PlanWs w;
+    w.hist = (int32_t *)base;
+    w.counter = w.hist + kKeys;
+    w.qinfo = w.counter + kNumSched;
+    size_t off = kHdrBytes;
+    w.key = (int32_t *)(base + off);
+    off += align256((size_t)a.M * 4);
+    w.queue = (int32_t *)(base + off);
+    off += align256((size_t)a.M * 4);
+
+    IncArgs x{};
+    x.a = a;
+    x.n_per = n_per;
+    x.Np_per = Np_per;
+    x.sel_off = sel_off;
+    x.pool_stride = a.Np;
+    x.queue = w.queue;
+
+    const unsigned lgrid = (unsigned)((a.M + 255) / 256);
+    hipLaunchKernelGGL(plan_zero, dim3(1), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(plan_classify, dim3(lgrid), dim3(256), 0, st, x, w, a.M);
+    hipLaunchKernelGGL(plan_scan, dim3(1), dim3(64), 0, st, w);
+    hipLaunchKernelGGL(plan_scatter, dim3(lgrid), dim3(256), 0, st, w, a.M);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    const int top = sched_for(a.Np);
+    for (int b = 0; b <= top; b++) {
+        const int gc = gcols_for(b, a.p, a.n);
+        x.zl_cols = kSched[b].zl_fit(a.p, a.n);
+        const size_t lds = kSched[b].lds(a.p, x.zl_cols);
+        int64_t grid64 = 0;
+        if ((e = persistent_grid(b, lds, info.cus, &grid64)) != hipSuccess) return e;
+        const unsigned grid = (unsigned)(grid64 < a.M ? grid64 : a.M);
+        x.qinfo = w.qinfo + 2 * b;
+        x.counter = w.counter + b;
+        x.gcols = gc;
+        x.gz = gc > 0 ? (double *)(base + off) : nullptr;
+        off += align256((size_t)grid64 * kSched[b].cap() * gc * 8);
+        e = launch_sched(b, x, dim3(grid), lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lagp

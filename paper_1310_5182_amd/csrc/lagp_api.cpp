@@ -115,6 +115,47 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                               status, guard, stream);
 }
 
+lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes)
+{
+    if (!bytes) return fail(LAGP_EINVAL, "bytes must be non-NULL");
+    if (M < 0 || p < 1 || Np_max < 1 || n_max < 1)
+        return fail(LAGP_EINVAL, "need M >= 0, p >= 1, Np_max >= 1, n_max >= 1");
+    if (!lagp::alc_uneven_supported(p, Np_max, n_max))
+        return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np_max = %d, n_max = %d", p, Np_max, n_max);
+    hipError_t e = lagp::alc_uneven_workspace(p, M, Np_max, n_max, bytes);
+    if (e != hipSuccess) return hip_fail(e, "workspace query");
+    return ok();
+}
+
+lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
+                                      const double *XX, int64_t M, const int32_t *pool, int32_t Np_max,
+                                      int32_t n0, int32_t n_max, const int32_t *n_per,
+                                      const int32_t *Np_per, const int64_t *sel_off, double d, double g,
+                                      int32_t precision, double *mean, double *s2, double *var,
+                                      int32_t *sel, double *alc, int32_t *status, int32_t *guard,
+                                      void *workspace, size_t workspace_bytes, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np_max);
+    if (s != LAGP_OK) return s;
+    s = check_alc(Y, Np_max, n0, n_max, d, g, precision, sel, M);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (precision != LAGP_FP64)
+        return fail(LAGP_EUNSUPPORTED, "per-location designs are computed in float64 only (LAGP_FP64)");
+    if (!lagp::alc_uneven_supported(p, Np_max, n_max))
+        return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np_max = %d, n_max = %d", p, Np_max, n_max);
+    if (M == 0) return ok();
+    size_t need = 0;
+    hipError_t e = lagp::alc_uneven_workspace(p, M, Np_max, n_max, &need);
+    if (e != hipSuccess) return hip_fail(e, "workspace query");
+    if (!workspace || workspace_bytes < need)
+        return fail(LAGP_EWORKSPACE, "workspace of %zu bytes given, %zu needed", workspace_bytes, need);
+    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, status, guard};
+    e = lagp::launch_alc_uneven(a, n_per, Np_per, sel_off, workspace, workspace_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "uneven alc launch");
+    return ok();
+}
+
 static lagp_status check_local(const double *X, const double *Y, int64_t N, int32_t p, const int32_t *sel,
                                int64_t M, int32_t n)
 {

@@ -191,6 +191,41 @@ __device__ __forceinline__ T wave_max(T v)
     return xmax<5>(v);
 }
 
+template <int S>
+__device__ __forceinline__ int xmin_i32(int v)
+{
+    const Pair32 p = xchg<S>((unsigned)v);
+    const int a = (int)p.a, b = (int)p.b;
+    return a < b ? a : b;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+    v = xmin_i32<0>(v);
+    v = xmin_i32<1>(v);
+    v = xmin_i32<2>(v);
+    v = xmin_i32<3>(v);
+    v = xmin_i32<4>(v);
+    return xmin_i32<5>(v);
+}
+
+// Wave-wide argmax of (score, design index, slot) for scores that are never
+// NaN: the largest score first, then, only if several lanes hold exactly that
+// score, the smallest design index among them.  Every lane gets the result.
+__device__ __forceinline__ void wave_argmax_ballot(double &s, int &idx, int &slot)
+{
+    const double m = wave_max(s);
+    unsigned long long b = __ballot(s == m);
+    if (b & (b - 1)) {
+        const int v = wave_min_i32(s == m ? idx : INT32_MAX);
+        b = __ballot(s == m && idx == v);
+    }
+    const int l = __builtin_ctzll(b);
+    s = m;
+    idx = __builtin_amdgcn_readlane(idx, l);
+    slot = __builtin_amdgcn_readlane(slot, l);
+}
+
 // Wave-wide argmax of (score, design index, slot); every lane gets the result.
 template <typename T>
 __device__ __forceinline__ void wave_argmax(T &s, int &idx, int &slot)

@@ -9,7 +9,8 @@ namespace lagp {
 constexpr int kMaxP = 16;  // largest input dimension any kernel accepts
 
 // Per-location status codes (the LAGP_LOC_* values of the public header).
-constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4;
+constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4,
+              kLocBadShape = 5;
 
 struct AlcArgs {
     const double *X;
@@ -46,6 +47,11 @@ hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st);
 // Float64 greedy ALC by incremental Cholesky columns.
 bool alc_inc_supported(int p, int Np, int n);
 hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st);
+// Per-location n and N' (a.n, a.Np are the upper bounds; pool rows of a.Np).
+bool alc_uneven_supported(int p, int Np_max, int n_max);
+hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes);
+hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
+                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st);
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

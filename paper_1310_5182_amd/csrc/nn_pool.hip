@@ -1,16 +1,27 @@
 // Nearest-neighbour candidate pools on gfx950 (Sec. 2.2 NN sub-design,
 // Sec. 3.1: the ALC search runs over the N' nearest neighbours of x).
 //
-// One workgroup per predictive location streams the design once.  Each row's
-// squared distance is summed left to right in float64 without fused
-// multiply-adds; its bit pattern (non-negative doubles order like unsigned
-// integers) followed by the row index forms a unique 96-bit composite key.
-// Rows whose key is below the running threshold are appended to an LDS
-// buffer.  When the buffer could overflow, an exact radix select on the
-// composite key finds the Np-th smallest key, the buffer is cut to exactly
-// the Np smallest and the threshold becomes that key.  A final bitonic sort
-// of the Np survivors gives the pool in ascending (distance, index) order:
-// exact, and independent of scheduling.
+// One workgroup serves G predictive locations and streams the design once
+// for all of them: each float64 row is loaded once, rounded to float32 once
+// and compared with the G locations in float32.  A row can only be among a
+// location's nearest if its float32 squared distance, less a rigorous bound
+// on the float32 error, is below the location's running threshold; only such
+// rows get the exact key.  The exact squared distance is summed left to right
+// in float64 without fused multiply-adds; its bit pattern (non-negative
+// doubles order like unsigned integers) followed by the row index forms a
+// unique 96-bit composite key.  Rows whose key is below the running threshold
+// are appended to the location's LDS buffer.  When a buffer could overflow,
+// an exact radix select on the composite key finds the Np-th smallest key,
+// the buffer is cut to exactly the Np smallest and the threshold becomes that
+// key.  A final bitonic sort of the Np survivors gives the pool in ascending
+// (distance, index) order: exact, and independent of scheduling.
+//
+// Float32 error bound.  With u = 2^-24, coordinates bounded by B in
+// magnitude, t = x_k - c_k: rounding x_k and c_k to float32 and subtracting
+// errs by at most ~4uB, squaring adds ~20uB^2 per coordinate in all, and the
+// float32 sum of p terms errs by at most (p-1)u times its value, so
+// |d32 - d| <= 40 p u B^2 + 2 p u d32 (twice the first-order terms).  B is the
+// larger of the row's and the location's largest coordinate magnitude.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -21,23 +32,31 @@ constexpr int kNnWaves = kNnBlock / kWave;
 constexpr int kNnItems = 4;
 constexpr int kNnChunk = kNnBlock * kNnItems;
 constexpr int kNnMaxNp = 2048;
+constexpr int kNnG = 2;    // locations per workgroup, pools of up to 1024
+constexpr int kNnG2k = 1;  // pools of up to 2048
 
 __device__ __forceinline__ bool key_less(uint64_t k1, int32_t i1, uint64_t k2, int32_t i2)
 {
     return k1 < k2 || (k1 == k2 && i1 < i2);
 }
 
+// Selection scratch, shared by the locations of a workgroup (one select at a time).
 struct NnShared {
     uint32_t hist[256];
     int16_t holes[kNnMaxNp];
     uint64_t wmin[kNnWaves], wmax[kNnWaves];
-    int count, nholes, nmove;
-    uint64_t thr_k;
-    int32_t thr_i;
+    int nholes, nmove;
     // radix-select state
     uint64_t sel_k;
     int32_t sel_i;
     int rank, bin, bin_count;
+};
+
+// Buffer fill and threshold of one location.
+struct NnGroup {
+    int count;
+    uint64_t thr_k;
+    int32_t thr_i;
 };
 
 // 256-bin histogram scan by one wave: finds bin b with cum(<b) <= rank < cum(<=b).
@@ -75,7 +94,7 @@ __device__ void hist_pick(NnShared &S, int lane)
 
 // Keeps exactly the Np smallest composite keys of keys/idxs[0, count) in
 // [0, Np) (unordered) and sets the threshold to the largest kept key.
-__device__ void select_keep(uint64_t *keys, int32_t *idxs, NnShared &S, int count, int Np)
+__device__ void select_keep(uint64_t *keys, int32_t *idxs, NnShared &S, NnGroup &grp, int count, int Np)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // common prefix of all keys: min and max
@@ -177,9 +196,9 @@ __device__ void select_keep(uint64_t *keys, int32_t *idxs, NnShared &S, int coun
         }
     }
     if (tid == 0) {
-        S.count = Np;
-        S.thr_k = ks;
-        S.thr_i = is;
+        grp.count = Np;
+        grp.thr_k = ks;
+        grp.thr_i = is;
     }
     __syncthreads();
 }
@@ -209,86 +228,147 @@ __device__ void bitonic_sort(uint64_t *keys, int32_t *idx)
     }
 }
 
-// CAP: LDS buffer entries (>= Np + chunk); SORTN: power of two >= Np.
-// PF > 0: p known at compile time (coordinates of x in registers).
-template <int CAP, int SORTN, int PF>
+// G: locations per workgroup; CAP: LDS buffer entries per location
+// (>= SORTN + chunk); SORTN: power of two >= Np; PF: p at compile time.
+template <int G, int CAP, int SORTN, int PF>
 __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restrict__ X, int64_t N,
-                                                           int p_rt, const double *__restrict__ XX,
+                                                           const double *__restrict__ XX, int64_t M,
                                                            int Np, int32_t *__restrict__ pool)
 {
     static_assert(CAP >= SORTN + kNnChunk, "room for one chunk above the kept set");
-    const int p = PF > 0 ? PF : p_rt;
-    __shared__ uint64_t keys[CAP];
-    __shared__ int32_t idxs[CAP];
-    __shared__ double xs[kMaxP];
+    static_assert(PF >= 1 && PF <= kMaxP, "compile-time dimension");
+    constexpr int p = PF;
+    constexpr float kU = 5.9604645e-8f;  // 2^-24
+    __shared__ uint64_t keys[G][CAP];
+    __shared__ int32_t idxs[G][CAP];
+    __shared__ double xs[G][PF];
+    __shared__ NnGroup grp[G];
     __shared__ NnShared S;
 
-    const int64_t m = blockIdx.x;
-    if (threadIdx.x < p) xs[threadIdx.x] = XX[m * p + threadIdx.x];
-    if (threadIdx.x == 0) {
-        S.count = 0;
-        S.thr_k = ~0ull;
-        S.thr_i = INT32_MAX;
+    const int64_t m0 = (int64_t)blockIdx.x * G;
+    const int ng = (int)(M - m0 < G ? M - m0 : G);  // locations of this workgroup
+    for (int t = threadIdx.x; t < G * PF; t += kNnBlock) {
+        const int g = t / PF, k = t - g * PF;
+        xs[g][k] = g < ng ? XX[(m0 + g) * p + k] : 0.0;
+    }
+    if (threadIdx.x < G) {
+        grp[threadIdx.x].count = 0;
+        grp[threadIdx.x].thr_k = ~0ull;
+        grp[threadIdx.x].thr_i = INT32_MAX;
     }
     __syncthreads();
 
-    double xr[PF > 0 ? PF : 1];
-    if (PF > 0) {
+    // float32 copies of the locations and their error-bound constants
+    float xf[G][PF], lmax[G];
 #pragma unroll
-        for (int k = 0; k < (PF > 0 ? PF : 1); k++) xr[k] = xs[k];
+    for (int g = 0; g < G; g++) {
+        lmax[g] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PF; k++) {
+            xf[g][k] = (float)xs[g][k];
+            lmax[g] = fmaxf(lmax[g], fabsf(xf[g][k]));
+        }
     }
+    constexpr float kSlope = 1.0f - 2.0f * PF * kU;  // d32 (1 - 2pu) - 40 p u B^2 < thr
+    constexpr float kConst = 40.0f * PF * kU;
 
     for (int64_t base = 0; base < N; base += kNnChunk) {
-        const int count = S.count;  // written only before barriers
-        if (count + kNnChunk > CAP) select_keep(keys, idxs, S, count, Np);
-        const uint64_t tk = S.thr_k;
-        const int32_t ti = S.thr_i;
+#pragma unroll 1
+        for (int g = 0; g < G; g++)  // uniform: counts change only before barriers
+            if (grp[g].count + kNnChunk > CAP) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
+        uint64_t tk[G];
+        int32_t ti[G];
+        float tf[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            tk[g] = grp[g].thr_k;
+            ti[g] = grp[g].thr_i;
+            // the threshold distance, rounded up to float32 (+inf before the first select)
+            const double td = tk[g] == ~0ull ? INFINITY : __builtin_bit_cast(double, tk[g]);
+            const float f = (float)td;  // td >= 0: the next float up is the next bit pattern
+            tf[g] = (double)f < td ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
+        }
 #pragma unroll
         for (int it = 0; it < kNnItems; it++) {
             const int64_t i = base + it * kNnBlock + threadIdx.x;
             if (i < N) {
-                double s;
-                if (PF > 0)
-                    s = sqdist_strict(X + i * PF, 1, xr, 1, PF);
-                else
-                    s = sqdist_strict(X + i * p, 1, xs, 1, p);
-                const uint64_t key = __builtin_bit_cast(uint64_t, s);
-                if (key_less(key, (int32_t)i, tk, ti)) {
-                    const int pos = atomicAdd(&S.count, 1);
-                    keys[pos] = key;
-                    idxs[pos] = (int32_t)i;
+                double xr[PF];
+                float xrf[PF];
+                float rmax = 0.0f;
+#pragma unroll
+                for (int k = 0; k < PF; k++) {
+                    xr[k] = X[i * PF + k];
+                    xrf[k] = (float)xr[k];
+                    rmax = fmaxf(rmax, fabsf(xrf[k]));
+                }
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    float d32 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < PF; k++) {
+                        const float t = xrf[k] - xf[g][k];
+                        d32 = fmaf(t, t, d32);
+                    }
+                    const float B = fmaxf(rmax, lmax[g]);
+                    if (d32 * kSlope - kConst * B * B < tf[g] && g < ng) {
+                        const double s = sqdist_strict(xr, 1, xs[g], 1, p);
+                        const uint64_t key = __builtin_bit_cast(uint64_t, s);
+                        if (key_less(key, (int32_t)i, tk[g], ti[g])) {
+                            const int pos = atomicAdd(&grp[g].count, 1);
+                            keys[g][pos] = key;
+                            idxs[g][pos] = (int32_t)i;
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
     }
-    if (S.count > Np) select_keep(keys, idxs, S, S.count, Np);
-    for (int i = Np + threadIdx.x; i < SORTN; i += kNnBlock) {
-        keys[i] = ~0ull;
-        idxs[i] = INT32_MAX;
+#pragma unroll 1
+    for (int g = 0; g < ng; g++) {
+        if (grp[g].count > Np) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
+        for (int i = Np + threadIdx.x; i < SORTN; i += kNnBlock) {
+            keys[g][i] = ~0ull;
+            idxs[g][i] = INT32_MAX;
+        }
+        __syncthreads();
+        bitonic_sort<SORTN>(keys[g], idxs[g]);
+        for (int r = threadIdx.x; r < Np; r += kNnBlock) pool[(m0 + g) * Np + r] = idxs[g][r];
+        __syncthreads();
     }
-    __syncthreads();
-    bitonic_sort<SORTN>(keys, idxs);
-    for (int r = threadIdx.x; r < Np; r += kNnBlock) pool[m * Np + r] = idxs[r];
 }
 
-template <int CAP, int SORTN>
+// Locations per workgroup: more share each pass over X; fewer keep more
+// workgroups resident (each location holds CAP keys in LDS).
+template <int G, int CAP, int SORTN>
 static hipError_t launch_cap(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
                              int32_t *pool, hipStream_t st)
 {
-    dim3 grid((unsigned)M), block(kNnBlock);
+    dim3 grid((unsigned)((M + G - 1) / G)), block(kNnBlock);
     switch (p) {
-    case 2:
-        hipLaunchKernelGGL((nn_pool_kernel<CAP, SORTN, 2>), grid, block, 0, st, X, N, p, XX, Np, pool);
+#define LAGP_NN_CASE(P)                                                                                 \
+    case P:                                                                                             \
+        hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P>), grid, block, 0, st, X, N, XX, M, Np, pool); \
         break;
-    case 4:
-        hipLaunchKernelGGL((nn_pool_kernel<CAP, SORTN, 4>), grid, block, 0, st, X, N, p, XX, Np, pool);
-        break;
-    case 8:
-        hipLaunchKernelGGL((nn_pool_kernel<CAP, SORTN, 8>), grid, block, 0, st, X, N, p, XX, Np, pool);
-        break;
+        LAGP_NN_CASE(1)
+        LAGP_NN_CASE(2)
+        LAGP_NN_CASE(3)
+        LAGP_NN_CASE(4)
+        LAGP_NN_CASE(5)
+        LAGP_NN_CASE(6)
+        LAGP_NN_CASE(7)
+        LAGP_NN_CASE(8)
+        LAGP_NN_CASE(9)
+        LAGP_NN_CASE(10)
+        LAGP_NN_CASE(11)
+        LAGP_NN_CASE(12)
+        LAGP_NN_CASE(13)
+        LAGP_NN_CASE(14)
+        LAGP_NN_CASE(15)
+        LAGP_NN_CASE(16)
+#undef LAGP_NN_CASE
     default:
-        hipLaunchKernelGGL((nn_pool_kernel<CAP, SORTN, 0>), grid, block, 0, st, X, N, p, XX, Np, pool);
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -296,8 +376,8 @@ static hipError_t launch_cap(const double *X, int64_t N, int p, const double *XX
 int nn_pool_cap(int Np)
 {
     if (Np <= 512) return 2048;
-    if (Np <= 1024) return 4096;
-    if (Np <= kNnMaxNp) return 4096 + 1024;
+    if (Np <= 1024) return 2048;
+    if (Np <= kNnMaxNp) return 4096;
     return 0;
 }
 
@@ -305,9 +385,10 @@ hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, i
                           int32_t *pool, hipStream_t st)
 {
     if (M == 0) return hipSuccess;
-    if (Np <= 512) return launch_cap<2048, 512>(X, N, p, XX, M, Np, pool, st);
-    if (Np <= 1024) return launch_cap<4096, 1024>(X, N, p, XX, M, Np, pool, st);
-    if (Np <= kNnMaxNp) return launch_cap<4096 + 1024, 2048>(X, N, p, XX, M, Np, pool, st);
+    if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
+    if (Np <= 512) return launch_cap<kNnG, 2048, 512>(X, N, p, XX, M, Np, pool, st);
+    if (Np <= 1024) return launch_cap<kNnG, 2048, 1024>(X, N, p, XX, M, Np, pool, st);
+    if (Np <= kNnMaxNp) return launch_cap<kNnG2k, 4096, 2048>(X, N, p, XX, M, Np, pool, st);
     return hipErrorInvalidValue;
 }
 

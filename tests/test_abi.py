@@ -120,3 +120,27 @@ def test_local_validation(L):
     assert L.lagp_local_mle_d(P, P, 100, 2, P, 3, 10, P, 1e-3, 1e-3, 5.0, -1, P, None, None, None, None) == -1
     assert L.lagp_local_predict(P, P, 100, 2, P, 3, 10, None, P, 1e-3, None, None, None, None, None) == -1
     assert L.lagp_local_nll_backward(P, P, 100, 2, P, 3, 10, None, P, None, P, P, None) == -1
+
+
+def uneven(L, N=5000, p=4, M=3, Np=2000, n0=6, n=100, prec=0, ws=FAKE, nbytes=1 << 30, sel=FAKE):
+    return L.lagp_alc_uneven_from_pool(FAKE, FAKE, N, p, FAKE, M, FAKE, Np, n0, n, None, None, None,
+                                       0.3, 1e-5, prec, None, None, None, sel, None, None, None,
+                                       ws, nbytes, None)
+
+
+def test_uneven_validation(L):
+    nb = ctypes.c_size_t(0)
+    assert L.lagp_alc_uneven_workspace(4, 10, 2000, 100, None) == -1
+    assert L.lagp_alc_uneven_workspace(4, -1, 2000, 100, ctypes.byref(nb)) == -1
+    assert L.lagp_alc_uneven_workspace(9, 10, 2000, 100, ctypes.byref(nb)) == -4
+    assert L.lagp_alc_uneven_workspace(4, 10, 2049, 100, ctypes.byref(nb)) == -4
+    assert L.lagp_alc_uneven_workspace(4, 10, 2000, 129, ctypes.byref(nb)) == -4
+    assert uneven(L, prec=1) == -4          # float64 only
+    assert uneven(L, prec=3) == -1
+    assert uneven(L, n=129) == -4
+    assert uneven(L, N=10000, Np=2049) == -4
+    assert uneven(L, p=9) == -4
+    assert uneven(L, n0=0) == -1
+    assert uneven(L, n=2001) == -1          # n_max above the pool width
+    assert uneven(L, sel=None) == -1
+    assert uneven(L, M=0) == 0

@@ -1,0 +1,165 @@
+"""Per-location design and pool sizes: the uneven path (through the C ABI)
+against the CPU oracle, including factor rows that spill to LDS and global
+memory, CSR output rows, shape errors and equality with the uniform path."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import parity
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _log(name, rec):
+    print(f"[uneven] {name}: {json.dumps(rec)}", flush=True)
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_log.jsonl"), "a") as f:
+        f.write(json.dumps(dict(test=name, **rec)) + "\n")
+
+
+@pytest.fixture(scope="module")
+def lagp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1310_5182_amd as lagp
+
+    return lagp
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(o):
+    return {k: v.cpu().numpy() for k, v in o.items() if k != "workspace"}
+
+
+def run_uneven(lagp, W, n0, n_max, Np_max, n_per, Np_per):
+    import torch
+
+    o = lagp.alc_uneven_predict(dev(W.X), dev(W.Y), dev(W.XX), n0, n_max, Np_max, W.d, W.g,
+                                n_per=None if n_per is None else dev(n_per),
+                                Np_per=None if Np_per is None else dev(Np_per))
+    torch.cuda.synchronize()
+    return host(o)
+
+
+def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-10):
+    M = W.M
+    n_per = np.full(M, n_max, np.int32) if n_per is None else n_per
+    forced = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per,
+                     forced=g["sel"], mode_b=True)
+    assert np.all(g["status"] == 0), np.unique(g["status"], return_counts=True)
+    assert np.all(forced["status"] == 0)
+    for m in range(M):  # padding past each design
+        assert np.all(g["sel"][m, n_per[m]:] == -1) and np.all(np.isnan(g["alc"][m, n_per[m]:]))
+    seq = parity.sequence_check(g["sel"], g["pool"], forced, n0, n_per=n_per)
+    mean_floor = 1e-6 * np.sqrt(np.mean(W.Y ** 2))
+    worst, rep = 0.0, {}
+    for k in ("mean", "s2", "var"):
+        rel = np.empty(M)
+        tol = np.empty(M)
+        for m in range(M):
+            kc = parity.cond_bounds(W.X, g["sel"][m:m + 1, :n_per[m]], W.d, W.g)[0]
+            b = forced[k][m]
+            floor = mean_floor if k == "mean" else 0.0
+            rel[m] = abs(g[k][m] - b) / max(abs(b), floor)
+            bound = kc if k == "mean" else kc / abs(forced["v"][m])
+            tol[m] = max(tau_out, 10 * bound)
+        rep[k] = dict(max_rel=float(rel.max()), n_cond_limited=int(np.sum(tol > tau_out)))
+        worst = max(worst, float(np.max(rel / tol)))
+    free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per)
+    same = int(sum(np.array_equal(free["sel"][m, :n_per[m]], g["sel"][m, :n_per[m]]) for m in range(M)))
+    rec = dict(M=M, N=W.N, p=W.p, n_range=[int(n_per.min()), int(n_per.max())],
+               ties=seq["ties"], max_tie_r=seq["max_r"], fails=len(seq["fails"]), same_sequence=same,
+               outputs=rep, worst_over_tol=worst)
+    _log(name, rec)
+    assert not seq["fails"], seq["fails"][:5]
+    assert worst <= 1.0, rep
+
+
+def test_config3_subsample(lagp, orc):
+    """Config-3 shapes: n in 20..100 and N' in 200..2000 per location, p = 4."""
+    W = workloads.make(3, M=40)
+    print(f"[uneven] config3 M={W.M} N={W.N}", flush=True)
+    g = run_uneven(lagp, W, W.n0, 100, 2000, W.n_per, W.Np_per)
+    assert np.array_equal(g["pool"], orc.nn_pool(W.X, W.XX, 2000))
+    check_against_oracle(orc, W, g, W.n0, 100, W.n_per, W.Np_per, "uneven_config3")
+
+
+@pytest.mark.parametrize("case", ["p4_Np2000_n100", "p8_Np1024_n100", "p8_Np2000_n64", "p2_Np512_n128"])
+def test_spill_to_global(lagp, orc, case):
+    """Largest designs: factor-row entries past the registers and LDS live in
+    the global workspace."""
+    p, Np, n = (int(v.lstrip("Npn")) for v in case.split("_"))
+    X, Y, XX = workloads.uniform(77 + p, 30000, p, 6)
+    W = workloads.Workload(case, X, Y, XX, 6, n, Np, 0.3 if p <= 4 else 0.5, 1e-4)
+    print(f"[uneven] spill {case}", flush=True)
+    g = run_uneven(lagp, W, 6, n, Np, None, None)
+    check_against_oracle(orc, W, g, 6, n, None, None, f"uneven_spill_{case}")
+
+
+def test_matches_uniform_path(lagp):
+    """n_per = N'_per = None through the queue gives the uniform kernel's bits."""
+    import torch
+
+    W = workloads.make(2, N=30000, M=64)
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    u = host(lagp.alc_predict(X, Y, XX, 6, 50, 1000, W.d, W.g, "fp64"))
+    v = run_uneven(lagp, W, 6, 50, 1000, None, None)
+    torch.cuda.synchronize()
+    for k in ("sel", "mean", "s2", "var", "status"):
+        assert np.array_equal(u[k], v[k]), k
+    assert np.array_equal(np.nan_to_num(u["alc"], nan=-7.0), np.nan_to_num(v["alc"], nan=-7.0))
+
+
+def test_csr_rows_and_bad_shapes(lagp, orc):
+    import torch
+
+    W = workloads.make(3, N=20000, M=12)
+    n_per = W.n_per.copy()
+    Np_per = W.Np_per.copy()
+    n_per[3] = 5            # below n0
+    Np_per[5] = n_per[5] - 1  # pool smaller than the design
+    n_per[7] = 101          # above n_max
+    Np_per[9] = 2001        # above the pool width
+    bad = {3, 5, 7, 9}
+    M = W.M
+    lens = np.where(np.isin(np.arange(M), list(bad)), np.clip(n_per, 0, 100), n_per).astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    pool = lagp.nn_pool(X, XX, 2000)
+    out = dict(sel=torch.full((int(off[-1]),), -9, dtype=torch.int32, device="cuda"),
+               alc=torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda"))
+    o = lagp.alc_uneven_from_pool(X, Y, XX, pool, 6, 100, W.d, W.g, n_per=dev(n_per), Np_per=dev(Np_per),
+                                  sel_off=dev(off), out=out)
+    pad = lagp.alc_uneven_from_pool(X, Y, XX, pool, 6, 100, W.d, W.g, n_per=dev(n_per), Np_per=dev(Np_per))
+    torch.cuda.synchronize()
+    o, pad = host(o), host(pad)
+    for m in range(M):
+        row = o["sel"][off[m]:off[m + 1]]
+        if m in bad:
+            assert o["status"][m] == 5 and pad["status"][m] == 5
+            assert np.isnan(o["mean"][m]) and np.all(row == -1)
+            assert np.all(pad["sel"][m] == -1)
+        else:
+            assert o["status"][m] == 0
+            assert np.array_equal(row, pad["sel"][m, :n_per[m]])
+            assert np.all(pad["sel"][m, n_per[m]:] == -1)
+            assert o["mean"][m] == pad["mean"][m]
+    good = np.array(sorted(set(range(M)) - bad))
+    ref = orc.alc(W.X, W.Y, W.XX[good], pool.cpu().numpy()[good], 6, 100, W.d, W.g,
+                  n_per=n_per[good], Np_per=Np_per[good])
+    for i, m in enumerate(good):
+        same = np.array_equal(ref["sel"][i, :n_per[m]], pad["sel"][m, :n_per[m]])
+        assert same or abs(ref["mean"][i] - pad["mean"][m]) <= 1e-8 * max(1.0, abs(ref["mean"][i]))
