@@ -168,6 +168,37 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
                                       void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Plans: the whole float64 path with per-location sizes (lagp_nn_pool with
+ * Np_max into `pool`, then lagp_alc_uneven_from_pool) bound to fixed
+ * buffers, autotuned and captured into one HIP graph.
+ *
+ * lagp_plan_create -- arguments as for lagp_alc_uneven_from_pool plus the
+ *   pool [M x Np_max] it fills.  Unless flags has LAGP_PLAN_NO_TUNE, the
+ *   plan first times the variants of each tunable launch on these inputs
+ *   (locations per NN workgroup; for each pool-size schedule of the ALC
+ *   kernel, how the chosen factor row reaches the lanes) and keeps the
+ *   fastest; the chosen launches are then captured into a graph.  Creation
+ *   runs the path several times on `stream` and synchronises it; results of
+ *   those runs are left in the outputs.  M >= 1.  The buffers must stay
+ *   allocated until the plan is destroyed.
+ * lagp_plan_launch -- enqueues one run (one graph launch) on `stream`.
+ * lagp_plan_describe -- the timings and the chosen variants, as text.
+ * lagp_plan_destroy -- frees the plan (NULL is a no-op).
+ */
+typedef struct lagp_plan_s *lagp_plan;
+#define LAGP_PLAN_NO_TUNE 1
+
+lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
+                             int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,
+                             const int32_t *Np_per, const int64_t *sel_off, double d, double g,
+                             int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
+                             double *alc, int32_t *status, int32_t *guard, void *workspace,
+                             size_t workspace_bytes, int32_t flags, void *stream, lagp_plan *out);
+lagp_status lagp_plan_launch(lagp_plan plan, void *stream);
+lagp_status lagp_plan_describe(lagp_plan plan, char *buf, size_t len);
+lagp_status lagp_plan_destroy(lagp_plan plan);
+
+/*
  * Local likelihood on fixed local designs (Sec. 2.1 eq. gpk, Fig. 1 step 3).
  * For each location m the design is rows sel[m][0 .. n-1] of X (sel: M x n
  * int32, e.g. the `sel` output of lagp_alc_from_pool), with responses Y.

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict",
+__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED}
@@ -157,6 +157,54 @@ def alc_uneven_predict(X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: 
     o["pool"] = nn_pool(X, XX, Np_max, out=o.get("pool"))
     return alc_uneven_from_pool(X, Y, XX, o["pool"], n0, n_max, d, g, n_per=n_per, Np_per=Np_per,
                                 precision=precision, out=o)
+
+
+class Plan:
+    """The whole float64 path (NN pools of Np_max, then per-location greedy ALC
+    designs and predictions) bound to fixed buffers, autotuned on these inputs
+    and captured into one HIP graph.  `out` holds the pool and the outputs
+    (sel and alc padded to M x n_max); `launch()` enqueues one run on torch's
+    current stream.  The input tensors must stay alive as long as the plan."""
+
+    def __init__(self, X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
+                 Np_per=None, tune: bool = True):
+        L = _lib.load()
+        X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
+        M, p = XX.shape
+        dev = X.device
+        o = _outputs(M, n_max, dev)
+        o["pool"] = torch.empty((M, Np_max), dtype=torch.int32, device=dev)
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(L.lagp_alc_uneven_workspace(p, M, Np_max, n_max, ctypes.byref(nbytes)))
+        o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+        self._keep = (X, Y, XX, n_per, Np_per)
+        self.out, self._dev, self._h = o, dev, ctypes.c_void_p()
+        _lib.check(L.lagp_plan_create(
+            X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, n0, n_max, Np_max,
+            _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M), 0, float(d), float(g), o["pool"].data_ptr(),
+            o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
+            o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), o["workspace"].data_ptr(),
+            o["workspace"].numel(), 0 if tune else 1, _stream(dev), ctypes.byref(self._h)))
+
+    def launch(self) -> dict:
+        _lib.check(_lib.load().lagp_plan_launch(self._h, _stream(self._dev)))
+        return self.out
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(2048)
+        _lib.check(_lib.load().lagp_plan_describe(self._h, buf, len(buf)))
+        return buf.value.decode()
+
+    def close(self) -> None:
+        if self._h:
+            _lib.check(_lib.load().lagp_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 def _sel(sel: torch.Tensor) -> torch.Tensor:

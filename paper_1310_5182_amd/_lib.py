@@ -23,6 +23,10 @@ EXPORTS = (
     "lagp_alc_predict",
     "lagp_alc_uneven_workspace",
     "lagp_alc_uneven_from_pool",
+    "lagp_plan_create",
+    "lagp_plan_launch",
+    "lagp_plan_describe",
+    "lagp_plan_destroy",
     "lagp_local_nll",
     "lagp_local_nll_backward",
     "lagp_local_mle_d",
@@ -65,6 +69,15 @@ def load():
     L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, f64, f64,
                                             i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
     L.lagp_alc_uneven_from_pool.restype = i32
+    L.lagp_plan_create.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, P, P, P, f64, f64, P, P, P, P, P,
+                                   P, P, P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
+    L.lagp_plan_create.restype = i32
+    L.lagp_plan_launch.argtypes = [P, P]
+    L.lagp_plan_launch.restype = i32
+    L.lagp_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+    L.lagp_plan_describe.restype = i32
+    L.lagp_plan_destroy.argtypes = [P]
+    L.lagp_plan_destroy.restype = i32
     L.lagp_local_nll.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P, P, P]
     L.lagp_local_nll.restype = i32
     L.lagp_local_nll_backward.argtypes = [P, P, i64, i32, P, i64, i32, P, P, P, P, P, P]

@@ -44,7 +44,7 @@ namespace {
 
 constexpr int kIncNmax = 128;  // z_h and L^{-1} Y live in two lanes' worth of one wave
 constexpr int kIncPmax = 8;
-constexpr bool kIncRL = true;
+constexpr int kIncBcastDefault = 0x7;  // v_readlane broadcast on every schedule
 
 struct IncArgs {
     AlcArgs a;                // a.n / a.Np: uniform values, or the upper bounds
@@ -58,6 +58,7 @@ struct IncArgs {
     double *gz;               // global z columns, gcols * CAP doubles per workgroup
     int gcols;
     int zl_cols;
+    int zrow;                 // LDS row length of a proposed z row (>= a.n)
 };
 
 // RL: the chosen row l reaches the lanes by v_readlane from a per-lane copy
@@ -71,25 +72,28 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
     static_assert(ZR % 8 == 0 && NW <= kWave && ZR <= kWave, "schedule shape");
     const AlcArgs &a = x.a;
 
+    // Dynamic LDS: centred candidate coordinates [k][pos], their squared
+    // norms, z entries ZR.. [entry - ZR][pos], and each wave's best z row
+    // [parity][wave][entry].
     extern __shared__ double dyn[];
-    double *cx = dyn;                            // candidate coordinates, [k][pos]
-    double *cY = cx + a.p * CAP;                 // response of each pool position
-    double *zl = cY + CAP;                       // z entries ZR.., [entry - ZR][pos]
-    int32_t *cid = (int32_t *)(zl + (size_t)x.zl_cols * CAP);  // design index, INT32_MAX if none
+    double *cx = dyn;
+    double *cq = cx + a.p * CAP;
+    double *zl = cq + CAP;
+    double *zb = zl + (size_t)x.zl_cols * CAP;
+    const int zrow = x.zrow;
 
-    __shared__ double ell[2][kIncNmax];  // z row of the point being added (by step parity)
-    __shared__ double pub[2][3];         // its variance s*, covariance cov* and residual r*
+    __shared__ double pub[2][NW][3];  // s, cov, residual of each wave's best
+    __shared__ double red_s[2][NW];
+    __shared__ int32_t red_i[2][NW], red_k[2][NW];
     __shared__ double alc_out[kIncNmax];
-    __shared__ int32_t selpos[kIncNmax];
+    __shared__ int32_t seldi[kIncNmax];
     __shared__ double xs[kIncPmax];
-    __shared__ double red_s[NW];
-    __shared__ int32_t red_i[NW], red_k[NW];
     __shared__ int ctl_status, ctl_loc;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = a.p, n0 = a.n0;
-    const double d = a.d, kappa = 1.0 + a.g;
+    const double kappa = 1.0 + a.g, nid = -1.0 / a.d;
     const int G0 = ZR + x.zl_cols;  // first entry kept in global memory
     double *gz = x.gz ? x.gz + (size_t)blockIdx.x * x.gcols * CAP : nullptr;
 
@@ -110,51 +114,60 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         const int Np = x.Np_per ? x.Np_per[m] : a.Np;
         const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
 
-        // ---- stage the location and its pool in LDS
+        // ---- stage the location; every lane loads its own pool positions
         if (tid == 0) ctl_status = kLocOk;
         if (tid < p) xs[tid] = a.XX[m * p + tid];
         __syncthreads();
-        for (int pos = tid; pos < CAP; pos += TB) {
+        double z[S][ZR];
+        double sv[S], cv[S], ty[S];  // conditional variance, covariance with x, residual of y
+        int32_t di[S];
+#pragma unroll
+        for (int s = 0; s < S; s++) {
+            const int pos = tid + s * TB;
             bool valid = pos < Np;
-            int32_t di = valid ? a.pool[m * x.pool_stride + pos] : INT32_MAX;
-            if (valid && (di < 0 || di >= a.N)) {  // never read outside X
+            int32_t id = valid ? a.pool[m * x.pool_stride + pos] : INT32_MAX;
+            if (valid && (id < 0 || id >= a.N)) {  // never read outside X
                 ctl_status = kLocBadPool;
                 valid = false;
             }
-            cid[pos] = valid ? di : INT32_MAX;
-            cY[pos] = valid ? a.Y[di] : 0.0;
-            for (int k = 0; k < p; k++) cx[k * CAP + pos] = valid ? a.X[(int64_t)di * p + k] : 0.0;
+            di[s] = valid ? id : INT32_MAX;
+            double q = 0.0;
+            for (int k = 0; k < p; k++) {
+                const double c = valid ? a.X[(int64_t)id * p + k] - xs[k] : 0.0;
+                cx[k * CAP + pos] = c;
+                q = fma(c, c, q);
+            }
+            cq[pos] = q;
+            cv[s] = valid ? exp(q * nid) : 0.0;  // K(c, x)
+            sv[s] = valid ? kappa : -1.0;         // a negative variance marks "not a candidate"
+            ty[s] = valid ? a.Y[id] : 0.0;
+#pragma unroll
+            for (int e = 0; e < ZR; e++) z[s][e] = 0.0;
         }
         __syncthreads();
         int status = ctl_status;
         for (int k = 0; k < p; k++)
             if (status == kLocOk && !isfinite(xs[k])) status = kLocNonfinite;
-
-        // ---- per-slot state: z row, conditional variance, covariance with x
-        // and residual y_c - z_c.t
-        double z[S][ZR];
-        double sv[S], cv[S], ty[S];
-        int32_t di[S];
-#pragma unroll
-        for (int s = 0; s < S; s++) {
-            const int pos = tid + s * TB;
-            di[s] = cid[pos];
-            const bool live = di[s] != INT32_MAX;
-            cv[s] = live ? corr64(sqdist_strict(cx + pos, CAP, xs, 1, p), d) : 0.0;
-            sv[s] = live ? kappa : -1.0;  // a negative variance marks "not a candidate"
-            ty[s] = cY[pos];
-#pragma unroll
-            for (int q = 0; q < ZR; q++) z[s][q] = 0.0;
-        }
         double mu = 0.0, psi = 0.0, zz = 0.0;  // z_h.t, t.t, z_h.z_h so far
+
+        // the z row of slot s, entries [0, j), into dst (one lane)
+        auto put_row = [&](int s, int j, double *dst) {
+            const int pos = tid + s * TB;
+#pragma unroll
+            for (int c = 0; c < NCH; c++)
+                if (c * 8 < j)
+#pragma unroll
+                    for (int u = 0; u < 8; u++) dst[c * 8 + u] = z[s][c * 8 + u];
+            for (int e = ZR; e < j; e++)
+                dst[e] = e < G0 ? zl[(e - ZR) * CAP + pos] : gz[(size_t)(e - G0) * CAP + pos];
+        };
 
         int j = 0;
         for (; status == kLocOk && j < n; j++) {
             const int par = j & 1;
-            // ===== (1) the point to add: forced pool order for the initial design,
-            // else the argmax of Delta (ties to the smaller design index)
-            int wpos = j;
-            double vbest = NAN;
+            double *zbp = zb + (size_t)par * NW * zrow;
+            // ===== (1) every wave proposes its best candidate (forced pool order
+            // for the initial design) with its z row; one barrier
             if (j >= n0) {
                 double bs = -1.0;
                 int32_t bi = INT32_MAX;
@@ -172,60 +185,69 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 }
                 wave_argmax_ballot(bs, bi, bk);
                 if (lane == 0) {
-                    red_s[w] = bs;
-                    red_i[w] = bi;
-                    red_k[w] = bk;
+                    red_s[par][w] = bs;
+                    red_i[par][w] = bi;
+                    red_k[par][w] = bk;
                 }
-                __syncthreads();
-                double v = lane < NW ? red_s[lane] : -1.0;
-                int32_t vi = lane < NW ? red_i[lane] : INT32_MAX;
-                int vk = lane < NW ? red_k[lane] : -1;
-                wave_argmax(v, vi, vk);
-                vbest = uniform(v);
-                wpos = __builtin_amdgcn_readfirstlane(vk);
+                if (bk >= 0 && tid == bk % TB) {
+                    const int sb = bk / TB;
+#pragma unroll
+                    for (int s = 0; s < S; s++)
+                        if (s == sb) {
+                            put_row(s, j, zbp + w * zrow);
+                            pub[par][w][0] = sv[s];
+                            pub[par][w][1] = cv[s];
+                            pub[par][w][2] = ty[s];
+                        }
+                }
+            } else if (tid == j) {  // pool position j: slot 0 of thread j
+                put_row(0, j, zbp + w * zrow);
+                pub[par][w][0] = sv[0];
+                pub[par][w][1] = cv[0];
+                pub[par][w][2] = ty[0];
+                red_i[par][w] = di[0];
+            }
+            __syncthreads();
+            // ===== (2) the winner: argmax of Delta, ties to the smaller design index
+            int wpos = j;
+            double vbest = NAN;
+            if (j >= n0) {
+                double v = lane < NW ? red_s[par][lane] : -1.0;
+                int32_t vi = lane < NW ? red_i[par][lane] : INT32_MAX;
+                int vk = lane < NW ? red_k[par][lane] : -1;
+                wave_argmax_ballot(v, vi, vk);
+                vbest = v;
+                wpos = vk;
                 if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
                     status = kLocStepFail;
                     break;
                 }
             }
-            // ===== (2) the owner publishes l = z_{x*} and s*, and retires the slot
-            const int ws = wpos / TB;
-            if (tid == wpos - ws * TB) {
-#pragma unroll
-                for (int s = 0; s < S; s++) {
-                    if (s == ws) {
-#pragma unroll
-                        for (int c = 0; c < NCH; c++)
-                            if (c * 8 < j)
-#pragma unroll
-                                for (int u = 0; u < 8; u++) ell[par][c * 8 + u] = z[s][c * 8 + u];
-                        pub[par][0] = sv[s];
-                        pub[par][1] = cv[s];
-                        pub[par][2] = ty[s];
-                        sv[s] = -1.0;
-                    }
-                }
-                for (int q = ZR; q < j; q++)
-                    ell[par][q] = q < G0 ? zl[(q - ZR) * CAP + wpos] : gz[(size_t)(q - G0) * CAP + wpos];
-            }
-            __syncthreads();
-            const double sstar = pub[par][0];
+            const int wt = wpos % TB, ws = wpos / TB;
+            const int vw = wt >> 6;  // the winner's wave
+            const double sstar = pub[par][vw][0];
             if (!(sstar > 0.0) || !isfinite(sstar)) {
                 status = j < n0 ? kLocInitNotPd : kLocStepFail;
                 break;
             }
-            const double lam = sqrt(sstar);
-            const double ilam = 1.0 / lam;
-            const double *el = ell[par];
+            if (tid == wt) {
+#pragma unroll
+                for (int s = 0; s < S; s++)
+                    if (s == ws) sv[s] = -1.0;  // retire the chosen slot
+            }
+            // step scalars, wave-uniform (scalar registers)
+            const double lam = uniform(sqrt(sstar));
+            const double ilam = uniform(1.0 / lam);
+            const double *el = zbp + vw * zrow;
 
             // ===== (3) z_h and t = L^{-1} Y gain their entry j
-            const double wh = pub[par][1] / lam;
-            const double tn = pub[par][2] / lam;
-            mu = fma(wh, tn, mu);
-            psi = fma(tn, tn, psi);
-            zz = fma(wh, wh, zz);
+            const double wh = uniform(pub[par][vw][1] / lam);
+            const double tn = uniform(pub[par][vw][2] / lam);
+            mu = uniform(fma(wh, tn, mu));
+            psi = uniform(fma(tn, tn, psi));
+            zz = uniform(fma(wh, wh, zz));
             if (tid == 0) {
-                selpos[j] = wpos;
+                seldi[j] = red_i[par][vw];
                 alc_out[j] = vbest;
             }
             if (j + 1 == n) continue;  // the design is complete: no more scoring
@@ -266,11 +288,21 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 #pragma unroll
                 for (int s = 0; s < S; s++) acc[s] = fma(col[s * TB], e, acc[s]);
             }
+            // K(c, x*) from centred coordinates: |c - x*|^2 = |c'|^2 + |x*'|^2 - 2 c'.x*'
+            double xw[kIncPmax];  // wave-uniform: held in scalar registers
+#pragma unroll
+            for (int k = 0; k < kIncPmax; k++) xw[k] = uniform(k < p ? cx[k * CAP + wpos] : 0.0);
+            const double qw = uniform(cq[wpos]);
             const int jc = j >> 3, ju = j & 7;
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 const int pos = tid + s * TB;
-                const double kc = corr64(sqdist_strict(cx + pos, CAP, cx + wpos, CAP, p), d);
+                double dt = 0.0;
+#pragma unroll
+                for (int k = 0; k < kIncPmax; k++)
+                    if (k < p) dt = fma(cx[k * CAP + pos], xw[k], dt);
+                const double r2 = fma(-2.0, dt, cq[pos] + qw);
+                const double kc = exp(r2 * nid);
                 const double wc = (kc - acc[s]) * ilam;
                 if (j < ZR) {
 #pragma unroll
@@ -293,7 +325,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 
         // ===== outputs: the design in the order added, its scores, the prediction
         for (int jj = tid; jj < j; jj += TB) {
-            a.sel[orow + jj] = cid[selpos[jj]];
+            a.sel[orow + jj] = seldi[jj];
             if (a.alc) a.alc[orow + jj] = alc_out[jj];
         }
         // local prediction (eqs. predgp, preds2): mu = z_h.t, psi = t.t
@@ -325,19 +357,24 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 
 // ---------------------------------------------------------------- schedules
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr size_t kStaticReserve = 8 * 1024;  // the kernel's static LDS, rounded up
+constexpr size_t kStaticReserve = 4 * 1024;  // the kernel's static LDS, rounded up
 constexpr size_t kDynLds = kLdsLimit - kStaticReserve;
 
 struct Sched {
     int tb, s, zr;
     constexpr int cap() const { return tb * s; }
-    // dynamic LDS bytes for p coordinates and zl LDS columns
-    size_t lds(int p, int zl) const { return (size_t)cap() * (8 * (size_t)p + 8 + 4 + 8 * (size_t)zl); }
+    static int zrow(int n_max) { return (n_max + 1) & ~1; }
+    // dynamic LDS bytes: p coordinates and a norm per position, zl LDS
+    // columns, and the double-buffered proposed rows of the waves
+    size_t lds(int p, int zl, int n_max) const
+    {
+        return (size_t)cap() * 8 * ((size_t)p + 1 + (size_t)zl) + (size_t)2 * (tb / kWave) * zrow(n_max) * 8;
+    }
     // LDS columns that fit, capped at the n_max - 1 - ZR that are needed; -1
     // if not even the coordinates fit
     int zl_fit(int p, int n_max) const
     {
-        const size_t base = lds(p, 0);
+        const size_t base = lds(p, 0, n_max);
         if (base > kDynLds) return -1;
         const int need = n_max - 1 > zr ? n_max - 1 - zr : 0;
         const int fit = (int)((kDynLds - base) / (8 * (size_t)cap()));
@@ -349,27 +386,29 @@ struct Sched {
 constexpr int kNumSched = 3;
 constexpr Sched kSched[kNumSched] = {{256, 2, 40}, {512, 2, 40}, {512, 4, 16}};
 
-template <int B>
+static_assert(kNumSched == kIncSchedules, "schedule count");
+
+template <int B, bool RL>
 constexpr auto kernel_of()
 {
-    if constexpr (B == 0)
-        return &alc_inc_kernel<kSched[0].tb, kSched[0].s, kSched[0].zr, kIncRL>;
-    else if constexpr (B == 1)
-        return &alc_inc_kernel<kSched[1].tb, kSched[1].s, kSched[1].zr, kIncRL>;
-    else
-        return &alc_inc_kernel<kSched[2].tb, kSched[2].s, kSched[2].zr, kIncRL>;
+    return &alc_inc_kernel<kSched[B].tb, kSched[B].s, kSched[B].zr, RL>;
 }
 
-const void *kernel_ptr(int b)
+const void *kernel_ptr(int b, bool rl)
 {
     switch (b) {
     case 0:
-        return (const void *)kernel_of<0>();
+        return rl ? (const void *)kernel_of<0, true>() : (const void *)kernel_of<0, false>();
     case 1:
-        return (const void *)kernel_of<1>();
+        return rl ? (const void *)kernel_of<1, true>() : (const void *)kernel_of<1, false>();
     default:
-        return (const void *)kernel_of<2>();
+        return rl ? (const void *)kernel_of<2, true>() : (const void *)kernel_of<2, false>();
     }
+}
+
+bool rl_of(int bcast, int b)
+{
+    return ((bcast < 0 ? kIncBcastDefault : bcast) >> b) & 1;
 }
 
 __host__ __device__ inline int sched_for(int Np)
@@ -396,10 +435,12 @@ hipError_t dev_info(DevInfo &out)
     if (!c.ready) {
         e = hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
-        for (int b = 0; b < kNumSched; b++) {
-            e = hipFuncSetAttribute(kernel_ptr(b), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDynLds);
-            if (e != hipSuccess) return e;
-        }
+        for (int b = 0; b < kNumSched; b++)
+            for (int rl = 0; rl < 2; rl++) {
+                e = hipFuncSetAttribute(kernel_ptr(b, rl), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kDynLds);
+                if (e != hipSuccess) return e;
+            }
         c.ready = true;
     }
     out = c;
@@ -410,24 +451,33 @@ hipError_t dev_info(DevInfo &out)
 // registers and this launch's LDS allow.
 hipError_t persistent_grid(int b, size_t lds, int cus, int64_t *grid)
 {
-    int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_ptr(b), kSched[b].tb, lds);
+    int nb = 0;  // both broadcast variants use the same registers bound
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_ptr(b, true), kSched[b].tb, lds);
     if (e != hipSuccess) return e;
     *grid = (int64_t)cus * (nb > 0 ? nb : 1);
     return hipSuccess;
 }
 
-hipError_t launch_sched(int b, const IncArgs &x, dim3 grid, size_t lds, hipStream_t st)
+template <int B>
+void launch_b(bool rl, const IncArgs &x, dim3 grid, size_t lds, hipStream_t st)
+{
+    if (rl)
+        hipLaunchKernelGGL((kernel_of<B, true>()), grid, dim3(kSched[B].tb), lds, st, x);
+    else
+        hipLaunchKernelGGL((kernel_of<B, false>()), grid, dim3(kSched[B].tb), lds, st, x);
+}
+
+hipError_t launch_sched(int b, bool rl, const IncArgs &x, dim3 grid, size_t lds, hipStream_t st)
 {
     switch (b) {
     case 0:
-        hipLaunchKernelGGL(kernel_of<0>(), grid, dim3(kSched[0].tb), lds, st, x);
+        launch_b<0>(rl, x, grid, lds, st);
         break;
     case 1:
-        hipLaunchKernelGGL(kernel_of<1>(), grid, dim3(kSched[1].tb), lds, st, x);
+        launch_b<1>(rl, x, grid, lds, st);
         break;
     default:
-        hipLaunchKernelGGL(kernel_of<2>(), grid, dim3(kSched[2].tb), lds, st, x);
+        launch_b<2>(rl, x, grid, lds, st);
         break;
     }
     return hipGetLastError();
@@ -534,6 +584,11 @@ int gcols_for(int b, int p, int n_max)
 }  // namespace
 
 // ---------------------------------------------------------------- host API
+int alc_inc_schedule(int Np)
+{
+    return sched_for(Np);
+}
+
 bool alc_inc_supported(int p, int Np, int n)
 {
     if (p > kIncPmax || n > kIncNmax) return false;
@@ -541,7 +596,7 @@ bool alc_inc_supported(int p, int Np, int n)
     return b >= 0 && gcols_for(b, p, n) == 0;
 }
 
-hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st)
+hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast)
 {
     if (a.M == 0) return hipSuccess;
     if (!alc_inc_supported(a.p, a.Np, a.n)) return hipErrorNotSupported;
@@ -553,7 +608,8 @@ hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st)
     x.a = a;
     x.pool_stride = a.Np;
     x.zl_cols = kSched[b].zl_fit(a.p, a.n);
-    return launch_sched(b, x, dim3((unsigned)a.M), kSched[b].lds(a.p, x.zl_cols), st);
+    x.zrow = Sched::zrow(a.n);
+    return launch_sched(b, rl_of(bcast, b), x, dim3((unsigned)a.M), kSched[b].lds(a.p, x.zl_cols, a.n), st);
 }
 
 bool alc_uneven_supported(int p, int Np_max, int n_max)
@@ -576,7 +632,7 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
     for (int b = 0; b <= top; b++) {
         const int gc = gcols_for(b, p, n_max);
         int64_t grid = 0;
-        e = persistent_grid(b, kSched[b].lds(p, kSched[b].zl_fit(p, n_max)), info.cus, &grid);
+        e = persistent_grid(b, kSched[b].lds(p, kSched[b].zl_fit(p, n_max), n_max), info.cus, &grid);
         if (e != hipSuccess) return e;
         total += align256((size_t)grid * kSched[b].cap() * gc * 8);
     }
@@ -585,7 +641,7 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
 }
 
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
-                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st)
+                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st, int bcast)
 {
     if (a.M == 0) return hipSuccess;
     DevInfo info;
@@ -626,7 +682,8 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
     for (int b = 0; b <= top; b++) {
         const int gc = gcols_for(b, a.p, a.n);
         x.zl_cols = kSched[b].zl_fit(a.p, a.n);
-        const size_t lds = kSched[b].lds(a.p, x.zl_cols);
+        x.zrow = Sched::zrow(a.n);
+        const size_t lds = kSched[b].lds(a.p, x.zl_cols, a.n);
         int64_t grid64 = 0;
         if ((e = persistent_grid(b, lds, info.cus, &grid64)) != hipSuccess) return e;
         const unsigned grid = (unsigned)(grid64 < a.M ? grid64 : a.M);
@@ -635,7 +692,7 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
         x.gcols = gc;
         x.gz = gc > 0 ? (double *)(base + off) : nullptr;
         off += align256((size_t)grid64 * kSched[b].cap() * gc * 8);
-        e = launch_sched(b, x, dim3(grid), lds, st);
+        e = launch_sched(b, rl_of(bcast, b), x, dim3(grid), lds, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -27,6 +27,19 @@ lagp_status ok()
     return LAGP_OK;
 }
 
+}  // namespace
+
+int lagp::set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+namespace {
+
 lagp_status hip_fail(hipError_t e, const char *what)
 {
     return fail(LAGP_EHIP, "%s: %s", what, hipGetErrorString(e));

@@ -6,6 +6,9 @@
 
 namespace lagp {
 
+// Records the calling thread's message for lagp_last_error() and returns code.
+int set_error(int code, const char *fmt, ...);
+
 constexpr int kMaxP = 16;  // largest input dimension any kernel accepts
 
 // Per-location status codes (the LAGP_LOC_* values of the public header).
@@ -36,22 +39,30 @@ struct AlcArgs {
 
 // Largest LDS buffer the NN kernel needs for a pool of Np (0 if unsupported).
 int nn_pool_cap(int Np);
+// Number of location groupings (2^g locations per workgroup) for pools of Np;
+// grouping < 0 picks the default.
+int nn_pool_groupings(int Np);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                          int32_t *pool, hipStream_t st);
+                          int32_t *pool, hipStream_t st, int grouping = -1);
 
 // Returns hipErrorNotSupported (without launching) when no compiled schedule
 // covers (p, Np, n, precision).
 bool alc_supported(int precision, int p, int Np, int n);
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st);
 
-// Float64 greedy ALC by incremental Cholesky columns.
+// Float64 greedy ALC by incremental Cholesky columns.  `bcast` selects, per
+// pool-size schedule, how the chosen factor row reaches the lanes (bit b set:
+// v_readlane, clear: LDS reads); negative: the default.
+constexpr int kIncSchedules = 3;
+int alc_inc_schedule(int Np);  // schedule serving pools of Np (-1: none)
 bool alc_inc_supported(int p, int Np, int n);
-hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st);
+hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1);
 // Per-location n and N' (a.n, a.Np are the upper bounds; pool rows of a.Np).
 bool alc_uneven_supported(int p, int Np_max, int n_max);
 hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes);
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
-                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st);
+                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st,
+                             int bcast = -1);
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

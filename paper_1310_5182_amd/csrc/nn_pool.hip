@@ -32,8 +32,6 @@ constexpr int kNnWaves = kNnBlock / kWave;
 constexpr int kNnItems = 4;
 constexpr int kNnChunk = kNnBlock * kNnItems;
 constexpr int kNnMaxNp = 2048;
-constexpr int kNnG = 2;    // locations per workgroup, pools of up to 1024
-constexpr int kNnG2k = 1;  // pools of up to 2048
 
 __device__ __forceinline__ bool key_less(uint64_t k1, int32_t i1, uint64_t k2, int32_t i2)
 {
@@ -381,14 +379,32 @@ int nn_pool_cap(int Np)
     return 0;
 }
 
+template <int CAP, int SORTN>
+static hipError_t launch_g(int G, const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
+                           int32_t *pool, hipStream_t st)
+{
+    if (G == 1) return launch_cap<1, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+    if constexpr (CAP <= 2048) {  // four buffers of 4096 keys would not fit in LDS
+        if (G == 4) return launch_cap<4, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+    }
+    return launch_cap<2, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+}
+
+int nn_pool_groupings(int Np)
+{
+    return Np <= 1024 ? 3 : 2;
+}
+
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                          int32_t *pool, hipStream_t st)
+                          int32_t *pool, hipStream_t st, int grouping)
 {
     if (M == 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
-    if (Np <= 512) return launch_cap<kNnG, 2048, 512>(X, N, p, XX, M, Np, pool, st);
-    if (Np <= 1024) return launch_cap<kNnG, 2048, 1024>(X, N, p, XX, M, Np, pool, st);
-    if (Np <= kNnMaxNp) return launch_cap<kNnG2k, 4096, 2048>(X, N, p, XX, M, Np, pool, st);
+    // locations per workgroup: 1, 2 or 4 (default 2)
+    const int G = grouping < 0 ? 2 : 1 << (grouping < nn_pool_groupings(Np) ? grouping : 0);
+    if (Np <= 512) return launch_g<2048, 512>(G, X, N, p, XX, M, Np, pool, st);
+    if (Np <= 1024) return launch_g<2048, 1024>(G, X, N, p, XX, M, Np, pool, st);
+    if (Np <= kNnMaxNp) return launch_g<4096, 2048>(G > 2 ? 2 : G, X, N, p, XX, M, Np, pool, st);
     return hipErrorInvalidValue;
 }
 

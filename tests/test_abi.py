@@ -144,3 +144,19 @@ def test_uneven_validation(L):
     assert uneven(L, n=2001) == -1          # n_max above the pool width
     assert uneven(L, sel=None) == -1
     assert uneven(L, M=0) == 0
+
+
+def test_plan_validation(L):
+    h = ctypes.c_void_p()
+    args = [FAKE, FAKE, 5000, 4, FAKE, 3, 6, 100, 2000, None, None, None, 0.3, 1e-5, FAKE, None, None,
+            None, FAKE, None, None, None, FAKE, 1 << 30, 0, None]
+    assert L.lagp_plan_create(*args, None) == -1                       # no handle
+    bad = list(args); bad[5] = 0
+    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -1              # M = 0
+    bad = list(args); bad[7] = 129
+    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -4              # n_max beyond 128
+    bad = list(args); bad[6] = 0
+    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -1              # n0 = 0
+    assert h.value is None
+    assert L.lagp_plan_destroy(None) == 0
+    assert L.lagp_plan_launch(None, None) == -1
