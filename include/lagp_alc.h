@@ -101,6 +101,10 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
  *   alc  [M x n]            float64 score v_j(x) - v_{j+1}(x) of the point
  *                           added at step j (unnormalised, eq. dxy); NaN for
  *                           j < n0
+ *   alc32 [M x n]           LAGP_MIXED: the float32 score of that point as the
+ *                           float32 scoring saw it, for the float32-vs-float64
+ *                           error report; NaN for j < n0, for steps decided
+ *                           entirely in float64, and everywhere for LAGP_FP64
  *   status [M]              LAGP_LOC_* code
  *   guard  [M]              LAGP_MIXED: number of steps whose float32 scores
  *                           were not trusted and were redone in float64; 0 for
@@ -115,7 +119,7 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,
                                int32_t n0, int32_t n, double d, double g, int32_t precision,
                                double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                               int32_t *status, int32_t *guard, void *stream);
+                               double *alc32, int32_t *status, int32_t *guard, void *stream);
 
 /*
  * lagp_alc_predict -- the whole hot path: lagp_nn_pool into `pool`
@@ -126,7 +130,7 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                              const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
                              double d, double g, int32_t precision, int32_t *pool,
                              double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                             int32_t *status, int32_t *guard, void *stream);
+                             double *alc32, int32_t *status, int32_t *guard, void *stream);
 
 /*
  * lagp_alc_uneven_workspace -- bytes of device workspace that

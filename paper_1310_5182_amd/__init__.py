@@ -62,7 +62,8 @@ def _outputs(M: int, n: int, device, out: dict | None = None) -> dict:
     o = out if out is not None else {}
     f64, i32 = torch.float64, torch.int32
     for k, shape, dt in (("mean", (M,), f64), ("s2", (M,), f64), ("var", (M,), f64), ("sel", (M, n), i32),
-                         ("alc", (M, n), f64), ("status", (M,), i32), ("guard", (M,), i32)):
+                         ("alc", (M, n), f64), ("alc32", (M, n), f64), ("status", (M,), i32),
+                         ("guard", (M,), i32)):
         if k not in o:
             o[k] = torch.empty(shape, dtype=dt, device=device)
     return o
@@ -81,8 +82,8 @@ def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision
     _lib.check(L.lagp_alc_from_pool(
         X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np, n0, n,
         float(d), float(g), _prec(precision), o["mean"].data_ptr(), o["s2"].data_ptr(),
-        o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["status"].data_ptr(),
-        o["guard"].data_ptr(), _stream(X.device)))
+        o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["alc32"].data_ptr(),
+        o["status"].data_ptr(), o["guard"].data_ptr(), _stream(X.device)))
     return o
 
 
@@ -98,8 +99,8 @@ def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precisio
     _lib.check(L.lagp_alc_predict(
         X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, n0, n, Np, float(d), float(g),
         _prec(precision), o["pool"].data_ptr(), o["mean"].data_ptr(), o["s2"].data_ptr(),
-        o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["status"].data_ptr(),
-        o["guard"].data_ptr(), _stream(X.device)))
+        o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["alc32"].data_ptr(),
+        o["status"].data_ptr(), o["guard"].data_ptr(), _stream(X.device)))
     return o
 
 

@@ -59,10 +59,10 @@ def load():
     L.lagp_nn_pool.argtypes = [P, i64, i32, P, i64, i32, P, P]
     L.lagp_nn_pool.restype = i32
     L.lagp_alc_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, i32,
-                                     P, P, P, P, P, P, P, P]
+                                     P, P, P, P, P, P, P, P, P]
     L.lagp_alc_from_pool.restype = i32
     L.lagp_alc_predict.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, f64, f64, i32, P,
-                                   P, P, P, P, P, P, P, P]
+                                   P, P, P, P, P, P, P, P, P]
     L.lagp_alc_predict.restype = i32
     L.lagp_alc_uneven_workspace.argtypes = [i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_alc_uneven_workspace.restype = i32

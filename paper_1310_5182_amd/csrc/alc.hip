@@ -124,6 +124,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     __shared__ double cxv[SLOTS];           // K(candidate, x)
     __shared__ double cY[SLOTS];            // response of each slot
     __shared__ double alc_out[NMAX];        // score of the point added at each step
+    __shared__ float alc_out32[MIXED ? NMAX : 1];  // its float32 score (NaN: step decided in float64)
     __shared__ int32_t cid[SLOTS];          // design index of each slot
     __shared__ uint8_t cflag[SLOTS];        // 0 candidate, 1 in design, 2 empty
     __shared__ T fz_s[MIXED ? SLOTS : 1], fz_c[MIXED ? SLOTS : 1];  // z.z, z.z_h over completed row blocks
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     __shared__ T red_s[NW];
     __shared__ int32_t red_i[NW], red_k[NW];
     __shared__ double rec_v[NW], rec_s[NW], rec_e[NW];
+    __shared__ float rec_v32[NW];
     __shared__ int32_t rec_i[NW], rec_k[NW], rec_n[NW];
     __shared__ int ctl_status, ctl_susp;
 
@@ -354,6 +356,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         bool fallback = false;
         if constexpr (MIXED) fallback = j >= n0 && ctl_susp != 0;
         double bv = -1.0, bsv = 0.0, err = 0.0;
+        float bv32 = -1.0f;  // float32 score of this wave's float64 best (-1: none)
         int32_t bi64 = INT32_MAX;
         int bk = -1, cnt = 0;
         auto consider = [&](int slot, double v32) {
@@ -368,6 +371,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                 bi64 = di;
                 bk = slot;
                 bsv = s;
+                bv32 = (float)v32;
                 zbest[w][lane] = z;
             }
         };
@@ -394,6 +398,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             rec_v[w] = bv;
             rec_s[w] = bsv;
             rec_e[w] = err;
+            rec_v32[w] = bv32;
             rec_i[w] = bi64;
             rec_k[w] = bk;
             rec_n[w] = cnt;
@@ -431,6 +436,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             bv = -1.0;
             bi64 = INT32_MAX;
             bk = -1;
+            bv32 = -1.0f;
             for (int s = wbase; s < wbase + WSLOTS; s++)
                 if (cflag[s] == 0) consider(s, -1.0);
             if (lane == 0) {
@@ -438,6 +444,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                 rec_s[w] = bsv;
                 rec_i[w] = bi64;
                 rec_k[w] = bk;
+                rec_v32[w] = bv32;
             }
             __syncthreads();
             v = lane < NW ? rec_v[lane] : -1.0;
@@ -487,6 +494,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                 cflag[win] = 1;
                 selslot[j] = win;
                 alc_out[j] = j >= n0 ? v : NAN;
+                if constexpr (MIXED) alc_out32[j] = (j >= n0 && rec_v32[vw] >= 0.0f) ? rec_v32[vw] : NAN;
                 ctl_susp = 0;
             }
         }
@@ -524,6 +532,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     for (int jj = tid; jj < j; jj += kThreads) {
         a.sel[m * n + jj] = cid[selslot[jj]];
         if (a.alc) a.alc[m * n + jj] = alc_out[jj];
+        if (a.alc32) a.alc32[m * n + jj] = MIXED ? (double)alc_out32[jj] : NAN;
     }
     // local prediction (eqs. predgp, preds2): mu = z_h.(R Y), psi = |R Y|^2
     if (w == 0) {
@@ -546,6 +555,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             for (int jj = j + lane; jj < n; jj += kWave) {
                 a.sel[m * n + jj] = -1;
                 if (a.alc) a.alc[m * n + jj] = NAN;
+                if (a.alc32) a.alc32[m * n + jj] = NAN;
             }
     }
 }

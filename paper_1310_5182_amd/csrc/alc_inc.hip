@@ -327,6 +327,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         for (int jj = tid; jj < j; jj += TB) {
             a.sel[orow + jj] = seldi[jj];
             if (a.alc) a.alc[orow + jj] = alc_out[jj];
+            if (a.alc32) a.alc32[orow + jj] = NAN;  // no float32 scores on this path
         }
         // local prediction (eqs. predgp, preds2): mu = z_h.t, psi = t.t
         if (w == 0) {
@@ -343,6 +344,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 for (int jj = j + lane; jj < n; jj += kWave) {
                     a.sel[orow + jj] = -1;
                     if (a.alc) a.alc[orow + jj] = NAN;
+                    if (a.alc32) a.alc32[orow + jj] = NAN;
                 }
         }
         // padded rows (no offsets, n below the row length): fill the tail

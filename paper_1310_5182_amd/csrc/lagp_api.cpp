@@ -91,7 +91,7 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,
                                int32_t n0, int32_t n, double d, double g, int32_t precision,
                                double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                               int32_t *status, int32_t *guard, void *stream)
+                               double *alc32, int32_t *status, int32_t *guard, void *stream)
 {
     lagp_status s = check_common(X, N, p, XX, M, Np);
     if (s != LAGP_OK) return s;
@@ -102,7 +102,7 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
         return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d, precision = %d", p, Np, n,
                     precision);
     if (M == 0) return ok();
-    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np, n0, n, d, g, mean, s2, var, sel, alc, status, guard};
+    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np, n0, n, d, g, mean, s2, var, sel, alc, alc32, status, guard};
     hipError_t e = lagp::launch_alc(a, precision, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "alc launch");
     return ok();
@@ -112,7 +112,7 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
                              const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
                              double d, double g, int32_t precision, int32_t *pool,
                              double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                             int32_t *status, int32_t *guard, void *stream)
+                             double *alc32, int32_t *status, int32_t *guard, void *stream)
 {
     lagp_status s = check_common(X, N, p, XX, M, Np);
     if (s != LAGP_OK) return s;
@@ -125,7 +125,7 @@ lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_
     s = lagp_nn_pool(X, N, p, XX, M, Np, pool, stream);
     if (s != LAGP_OK) return s;
     return lagp_alc_from_pool(X, Y, N, p, XX, M, pool, Np, n0, n, d, g, precision, mean, s2, var, sel, alc,
-                              status, guard, stream);
+                              alc32, status, guard, stream);
 }
 
 lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes)
@@ -163,7 +163,8 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
     if (e != hipSuccess) return hip_fail(e, "workspace query");
     if (!workspace || workspace_bytes < need)
         return fail(LAGP_EWORKSPACE, "workspace of %zu bytes given, %zu needed", workspace_bytes, need);
-    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, status, guard};
+    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, nullptr, status,
+                    guard};
     e = lagp::launch_alc_uneven(a, n_per, Np_per, sel_off, workspace, workspace_bytes, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "uneven alc launch");
     return ok();

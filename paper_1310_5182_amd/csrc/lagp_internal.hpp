@@ -33,6 +33,7 @@ struct AlcArgs {
     double *var;
     int32_t *sel;
     double *alc;
+    double *alc32;  // mixed: float32 score of each chosen point (nullable)
     int32_t *status;
     int32_t *guard;
 };

@@ -141,7 +141,8 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     if (!X || !Y || !XX || !sel) return plan_fail(LAGP_EINVAL, "X, Y, XX and sel must be non-NULL");
 
     lagp_plan_s *P = new lagp_plan_s();
-    P->a = lagp::AlcArgs{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, status, guard};
+    P->a = lagp::AlcArgs{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, nullptr,
+                         status, guard};
     P->n_per = n_per;
     P->Np_per = Np_per;
     P->sel_off = sel_off;

@@ -53,7 +53,7 @@ def nn(L, N=100, p=2, M=3, Np=10, X=FAKE, XX=FAKE, pool=FAKE):
 
 def alc(L, N=100, p=2, M=3, Np=10, n0=2, n=5, d=0.5, g=1e-3, prec=0, Y=FAKE, sel=FAKE):
     return L.lagp_alc_from_pool(FAKE, Y, N, p, FAKE, M, FAKE, Np, n0, n, d, g, prec,
-                                None, None, None, sel, None, None, None, None)
+                                None, None, None, sel, None, None, None, None, None)
 
 
 def test_nn_pool_validation(L):
@@ -90,10 +90,10 @@ def test_alc_validation(L):
 
 def test_predict_validation(L):
     r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 3, 6, 5, 10, 0.5, 1e-3, 0, FAKE,
-                           None, None, None, FAKE, None, None, None, None)
+                           None, None, None, FAKE, None, None, None, None, None)
     assert r == -1
     r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 0, 2, 5, 10, 0.5, 1e-3, 1, FAKE,
-                           None, None, None, FAKE, None, None, None, None)
+                           None, None, None, FAKE, None, None, None, None, None)
     assert r == 0
 
 

@@ -1,0 +1,117 @@
+"""Full-size workloads in the launch configuration the bench times, checked on
+sampled locations that the oracle recomputes one by one (pool, design,
+prediction), plus properties that hold at any size."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import parity
+import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+SAMPLE = 12
+
+
+def _log(name, rec):
+    print(f"[full] {name}: {json.dumps(rec)}", flush=True)
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_log.jsonl"), "a") as f:
+        f.write(json.dumps(dict(test=name, **rec)) + "\n")
+
+
+@pytest.fixture(scope="module")
+def lagp():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1310_5182_amd as lagp
+
+    return lagp
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sampled_check(orc, W, g, rows, n_of, Np_of, name):
+    """Recompute sampled locations with the oracle and apply the parity protocol."""
+    X, Y = W.X, W.Y
+    pool_ref = orc.nn_pool(X, W.XX[rows], int(max(Np_of(m) for m in rows)))
+    ties, worst = 0, 0.0
+    for i, m in enumerate(rows):
+        n, Np = n_of(m), Np_of(m)
+        assert np.array_equal(g["pool"][m, :Np], pool_ref[i, :Np]), m
+        sel = g["sel"][m, :n][None, :]
+        f = orc.alc(X, Y, W.XX[m:m + 1], g["pool"][m:m + 1, :Np], W.n0, n, W.d, W.g, forced=sel, mode_b=True)
+        seq = parity.sequence_check(sel, g["pool"][m:m + 1, :Np], f, W.n0)
+        assert not seq["fails"], (m, seq["fails"])
+        ties += seq["ties"]
+        kc = parity.cond_bounds(X, sel, W.d, W.g)[0]
+        floor = 1e-6 * np.sqrt(np.mean(Y ** 2))
+        for k in ("mean", "s2", "var"):
+            b = f[k][0]
+            rel = abs(g[k][m] - b) / max(abs(b), floor if k == "mean" else 0.0)
+            bound = kc if k == "mean" else kc / abs(f["v"][0])
+            worst = max(worst, rel / max(1e-10, 10 * bound))
+    _log(name, dict(M=W.M, N=W.N, sampled=len(rows), ties=ties, worst_over_tol=worst))
+    assert worst <= 1.0
+
+
+def global_properties(g, n_of, M):
+    st = g["status"]
+    assert np.all(st == 0), np.unique(st, return_counts=True)
+    for k in ("mean", "s2", "var"):
+        assert np.all(np.isfinite(g[k])), k
+    assert np.all(g["s2"] > 0) and np.all(g["var"] > g["s2"])
+    # every design: the first n0 pool entries, then distinct pool members
+    for m in range(0, M, max(1, M // 2000)):
+        n = n_of(m)
+        row = g["sel"][m, :n]
+        assert len(np.unique(row)) == n
+        assert np.array_equal(row[:6], g["pool"][m, :6])
+
+
+@pytest.mark.parametrize("cfg", [2, 5])
+def test_uniform_full_size(lagp, orc, cfg):
+    import torch
+
+    W = workloads.make(cfg)
+    print(f"[full] config{cfg} N={W.N} M={W.M}", flush=True)
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    o = lagp.alc_predict(X, Y, XX, W.n0, W.n, W.Np, W.d, W.g, "fp64")
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in o.items()}
+    del o
+    global_properties(g, lambda m: W.n, W.M)
+    rows = np.random.default_rng(cfg).choice(W.M, SAMPLE, replace=False)
+    sampled_check(orc, W, g, rows, lambda m: W.n, lambda m: W.Np, f"full_config{cfg}")
+
+
+def test_uneven_full_size(lagp, orc):
+    import torch
+
+    W = workloads.make(3)
+    print(f"[full] config3 N={W.N} M={W.M}", flush=True)
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    o = lagp.alc_uneven_predict(X, Y, XX, W.n0, 100, 2000, W.d, W.g, n_per=dev(W.n_per), Np_per=dev(W.Np_per))
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in o.items() if k != "workspace"}
+    del o
+    n_of = lambda m: int(W.n_per[m])  # noqa: E731
+    Np_of = lambda m: int(W.Np_per[m])  # noqa: E731
+    global_properties(g, n_of, W.M)
+    for m in range(0, W.M, 997):
+        assert np.all(g["sel"][m, n_of(m):] == -1)
+    # the sample covers the extremes of the cost distribution
+    cost = W.Np_per.astype(float) * W.n_per.astype(float) ** 2
+    order = np.argsort(cost)
+    rows = np.concatenate([order[:3], order[-5:], np.random.default_rng(3).choice(W.M, SAMPLE - 8, replace=False)])
+    sampled_check(orc, W, g, rows, n_of, Np_of, "full_config3")

@@ -110,7 +110,17 @@ def check_alc(orc, W, g, n0, n, Np, precision, tau_out, name, expect_ties_max=No
     worst, rep = parity.output_check(g, forced, W.X, W.d, W.g, tau_out, mean_floor)
     free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n, W.d, W.g)
     same_seq = int(np.sum(np.all(free["sel"] == g["sel"], axis=1)))
-    rec = dict(precision=precision, M=W.M, N=W.N, p=W.p, n=n, Np=Np, ties=seq["ties"],
+    # float32 score of each chosen point against its float64 score (mixed error report)
+    e32 = None
+    if precision == "mixed":
+        a32, a64 = g["alc32"][:, n0:], g["alc"][:, n0:]
+        fin = np.isfinite(a32)
+        e32 = float(np.max(np.abs(a32[fin] - a64[fin]) / a64[fin])) if fin.any() else 0.0
+        assert e32 <= 1.0 / 256, e32  # larger errors send the step to float64
+        assert int((~fin).sum()) <= int(g["guard"].sum()) + int(np.sum(a64 <= 0)), "NaN only on float64 steps"
+    else:
+        assert np.all(np.isnan(g["alc32"]))
+    rec = dict(precision=precision, M=W.M, N=W.N, p=W.p, n=n, Np=Np, ties=seq["ties"], alc32_max_rel=e32,
                max_tie_r=seq["max_r"], fails=len(seq["fails"]), same_sequence=same_seq,
                alc_max_rel=float(np.max(a_rel)) if a_rel.size else 0.0, alc_excess=a_excess,
                outputs=rep, worst_over_tol=worst,
