@@ -73,7 +73,7 @@ def main() -> int:
     ap.add_argument("--M", type=int, default=None, help="predictive locations (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
-    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--only", choices=["mixed", "fp64", "fp64_reform", "both"], default="both")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -136,7 +136,7 @@ def main() -> int:
         paths["fp64"] = (step_mle, o4)
         precs = ["fp64"]
     else:
-        precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+        precs = ["mixed", "fp64", "fp64_reform"] if args.only == "both" else [args.only]
         for prec in precs:
             o = {}
 
@@ -192,10 +192,12 @@ def main() -> int:
         kname, kms_head = "alc_inc_kernel (uneven, float64)", kms["alc_fp64_uneven"]
         bound, peak, unit = "alu", PEAK["fp64_vector"], "TFLOP/s"
         per_unit = "sum over locations of sum_{j<n_m-1} (N'_m-j-1)(2j+4) flops"
-    elif head == "mixed":
+    elif head in ("mixed", "fp64_reform"):
         flops, evals = mfma_flops(n0, n, Np) * M, alc_evals(n0, n, Np) * M
-        kname, kms_head = "alc_kernel<float> (mixed, MFMA)", kms["alc_mixed"]
-        bound, peak, unit = "mfma", PEAK["fp32_mfma"], "TFLOP/s"
+        mixed = head == "mixed"
+        kname = "alc_kernel<float> (mixed, MFMA)" if mixed else "alc_kernel<double> (float64, MFMA)"
+        kms_head = kms[f"alc_{head}"]
+        bound, peak, unit = "mfma", PEAK["fp32_mfma" if mixed else "fp64_mfma"], "TFLOP/s"
         per_unit = f"{mfma_flops(n0, n, Np):.4g} flops per location (sum_j 2(N'-j)j^2)"
     else:
         flops, evals = inc_flops(n0, n, Np) * M, alc_evals(n0, n, Np) * M
@@ -261,6 +263,8 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "mixed" else "f64",
+        # every path timed, with the roofline figures of its own kernel
+        "paths": {k: dict(loc_per_s=v["loc_per_s"], alc_ms=kms.get(f"alc_{k}")) for k, v in res.items()},
         "data": "synthetic",
         "config": {"workload": f"config{cfg}: N={W.N} p={W.p} uniform design, M={M} locations, n0={n0}, "
                                + (f"n=U[20,100], N'=U[200,2000] per location" if cfg == 3 else
@@ -270,6 +274,9 @@ def main() -> int:
         "loc_per_s": {k: v["loc_per_s"] for k, v in res.items()},
         "mixed_over_fp64": (res["mixed"]["loc_per_s"] / res["fp64"]["loc_per_s"])
         if "mixed" in res and "fp64" in res else None,
+        # the precision split on the same (per-step re-forming) route
+        "mixed_over_fp64_reform": (res["mixed"]["loc_per_s"] / res["fp64_reform"]["loc_per_s"])
+        if "mixed" in res and "fp64_reform" in res else None,
         "alc_evals_per_s": evals / (kms_head * 1e-3),
         "kernel_ms": kms,
         "guard_steps_frac": float(guard.sum()) / max(1, M * (n - n0)),

@@ -48,12 +48,16 @@ typedef int32_t lagp_status;
 #define LAGP_EUNSUPPORTED (-4)  /* sizes outside the compiled schedules    */
 
 /* Arithmetic of the candidate scoring (Fig. 1 step 2b). */
-#define LAGP_FP64 0   /* everything in float64                                 */
+#define LAGP_FP64 0   /* everything in float64; each candidate's factor row    */
+                      /* grows by one entry per step (O(N' j) per step)        */
 #define LAGP_MIXED 1  /* candidate kernel vectors and scores in float32 with   */
                       /* float32 accumulation; the inverse-factor update, the  */
                       /* Schur complement of the chosen point, a re-score of   */
                       /* the near-best candidates and the prediction in       */
                       /* float64                                               */
+#define LAGP_FP64_REFORM 2  /* float64, every candidate's quadratic form       */
+                            /* re-formed each step on the matrix cores (the   */
+                            /* per-step route of Fig. 3, O(N' j^2) per step)  */
 
 /* Per-location status codes written to status[m]. */
 #define LAGP_LOC_OK 0
@@ -110,10 +114,10 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
  *                           were not trusted and were redone in float64; 0 for
  *                           LAGP_FP64
  * Exact score ties go to the smallest design index.
- * Supported sizes: p <= 8 and Np <= 1024; LAGP_MIXED needs n <= 64, and
- * LAGP_FP64 needs every candidate's factor row on chip (n <= 50 at p = 8,
- * N' = 1024; larger n at smaller p or N').  Others return LAGP_EUNSUPPORTED
- * (lagp_alc_uneven_from_pool covers them in float64).
+ * Supported sizes: p <= 8 and Np <= 1024; LAGP_MIXED needs n <= 64,
+ * LAGP_FP64_REFORM n <= 52, and LAGP_FP64 every candidate's factor row on
+ * chip (n <= 50 at p = 8, N' = 1024; larger n at smaller p or N').  Others
+ * return LAGP_EUNSUPPORTED (lagp_alc_uneven_from_pool covers them in float64).
  */
 lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,

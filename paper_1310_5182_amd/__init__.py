@@ -11,12 +11,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import LAGP_FP64, LAGP_MIXED, LagpError  # noqa: F401
+from ._lib import LAGP_FP64, LAGP_FP64_REFORM, LAGP_MIXED, LagpError  # noqa: F401
 
 __all__ = ["nn_pool", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
-PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED}
+PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED, "fp64_reform": LAGP_FP64_REFORM}
 
 
 def _f64(t: torch.Tensor, name: str) -> torch.Tensor:

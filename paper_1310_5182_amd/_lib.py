@@ -15,6 +15,7 @@ LAGP_EUNSUPPORTED = -4
 
 LAGP_FP64 = 0
 LAGP_MIXED = 1
+LAGP_FP64_REFORM = 2
 
 # Every symbol declared in include/lagp_alc.h.
 EXPORTS = (

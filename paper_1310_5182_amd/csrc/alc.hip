@@ -573,17 +573,20 @@ static bool mfma_supported(int precision, int p, int Np, int n)
     return precision == 0 ? n <= 52 : n <= 64;
 }
 
+// precision 0: float64, incremental columns where a schedule fits, else the
+// MFMA kernel; 1: mixed (MFMA, float32 scores); 2: float64 scores re-formed
+// every step on the matrix cores.
 bool alc_supported(int precision, int p, int Np, int n)
 {
     if (precision == 0 && alc_inc_supported(p, Np, n)) return true;
-    return mfma_supported(precision, p, Np, n);
+    return mfma_supported(precision == 1 ? 1 : 0, p, Np, n);
 }
 
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st)
 {
     if (a.M == 0) return hipSuccess;
-    // float64: incremental Cholesky columns where a schedule fits, else the MFMA kernel
     if (precision == 0 && alc_inc_supported(a.p, a.Np, a.n)) return launch_alc_inc(a, st);
+    if (precision == 2) precision = 0;
     if (!mfma_supported(precision, a.p, a.Np, a.n)) return hipErrorNotSupported;
     if (precision == 0) {
         if (a.Np <= 512) return launch_t<double, 4, 8, 13, 1>(a, st);

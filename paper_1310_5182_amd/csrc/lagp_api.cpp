@@ -60,8 +60,8 @@ lagp_status check_common(const double *X, int64_t N, int32_t p, const double *XX
 lagp_status check_alc(const double *Y, int32_t Np, int32_t n0, int32_t n, double d, double g,
                       int32_t precision, const int32_t *sel, int64_t M)
 {
-    if (precision != LAGP_FP64 && precision != LAGP_MIXED)
-        return fail(LAGP_EINVAL, "precision = %d is neither LAGP_FP64 nor LAGP_MIXED", precision);
+    if (precision != LAGP_FP64 && precision != LAGP_MIXED && precision != LAGP_FP64_REFORM)
+        return fail(LAGP_EINVAL, "precision = %d is not LAGP_FP64, LAGP_MIXED or LAGP_FP64_REFORM", precision);
     if (!(n0 >= 1 && n0 <= n && n <= Np))
         return fail(LAGP_EINVAL, "need 1 <= n0 <= n <= Np (n0 = %d, n = %d, Np = %d)", n0, n, Np);
     if (!(d > 0.0) || !isfinite(d)) return fail(LAGP_EINVAL, "lengthscale d must be finite and > 0");

@@ -79,7 +79,7 @@ def test_alc_validation(L):
     assert alc(L, d=float("nan")) == -1
     assert alc(L, g=0.0) == -1
     assert alc(L, g=float("inf")) == -1
-    assert alc(L, prec=2) == -1
+    assert alc(L, prec=3) == -1
     assert alc(L, Y=None) == -1
     assert alc(L, sel=None) == -1
     assert alc(L, N=5000, Np=2000, n=50) == -4

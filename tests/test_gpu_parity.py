@@ -134,26 +134,26 @@ def check_alc(orc, W, g, n0, n, Np, precision, tau_out, name, expect_ties_max=No
     return rec
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
 def test_alc_config2_subset(lagp, orc, precision):
     W = workloads.make(2, M=64)
     print(f"[parity] alc config2 M=64 {precision}", flush=True)
     g = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
     assert np.array_equal(g["pool"], orc.nn_pool(W.X, W.XX, W.Np))
-    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-10 if precision == "fp64" else 1e-4,
+    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-4 if precision == "mixed" else 1e-10,
               f"config2_M64_{precision}")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
 def test_alc_config1_full(lagp, orc, precision):
     W = workloads.make(1)
     print(f"[parity] alc config1 full {precision}", flush=True)
     g = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
-    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-10 if precision == "fp64" else 1e-4,
+    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-4 if precision == "mixed" else 1e-10,
               f"config1_full_{precision}")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
 @pytest.mark.parametrize("shape", ["n0_eq_n", "Np_eq_n", "ragged_Np", "max_Np", "max_n", "p1", "M1"])
 def test_alc_edge_shapes(lagp, orc, precision, shape):
     base = dict(N=3000, M=24, n0=6, n=20, Np=200)
@@ -167,7 +167,7 @@ def test_alc_edge_shapes(lagp, orc, precision, shape):
     elif shape == "max_Np":
         base.update(Np=1024, n=40, N=20000, M=8)
     elif shape == "max_n":
-        base.update(n=52 if precision == "fp64" else 64, Np=700, N=20000, M=8)
+        base.update(n=64 if precision == "mixed" else 52, Np=700, N=20000, M=8)
     elif shape == "M1":
         base.update(M=1)
     if shape == "p1":
@@ -178,7 +178,7 @@ def test_alc_edge_shapes(lagp, orc, precision, shape):
     n0, n, Np = base["n0"], base["n"], base["Np"]
     print(f"[parity] alc edge {shape} {precision} N={W.N} M={W.M} n0={n0} n={n} Np={Np}", flush=True)
     g = run_gpu(lagp, W, n0, n, Np, precision)
-    rec = check_alc(orc, W, g, n0, n, Np, precision, 1e-9 if precision == "fp64" else 1e-4,
+    rec = check_alc(orc, W, g, n0, n, Np, precision, 1e-4 if precision == "mixed" else 1e-9,
                     f"edge_{shape}_{precision}")
     if shape == "Np_eq_n":
         for m in range(W.M):
