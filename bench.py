@@ -241,8 +241,8 @@ def main() -> int:
         a32 = om["alc32"].cpu().numpy()[:, n0:]
         a64 = om["alc"].cpu().numpy()[:, n0:]
         fin = np.isfinite(a32) & (a64 > 0)
-        rel = lambda k: float(np.max(np.abs(om[k] - of[k]).cpu().numpy()  # noqa: E731
-                                     / np.maximum(np.abs(of[k].cpu().numpy()), 1e-300)))
+        rel = lambda k: float(np.max((om[k] - of[k]).abs().cpu().numpy()  # noqa: E731
+                                     / np.maximum(of[k].abs().cpu().numpy(), 1e-300)))
         mixed_report = {
             "same_designs_frac": float((om["sel"] == of["sel"]).all(dim=1).float().mean().item()),
             "mean_max_rel": rel("mean"), "s2_max_rel": rel("s2"), "var_max_rel": rel("var"),

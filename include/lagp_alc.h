@@ -186,8 +186,9 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  *   (locations per NN workgroup; for each pool-size schedule of the ALC
  *   kernel, how the chosen factor row reaches the lanes) and keeps the
  *   fastest; the chosen launches are then captured into a graph.  Creation
- *   runs the path several times on `stream` and synchronises it; results of
- *   those runs are left in the outputs.  M >= 1.  The buffers must stay
+ *   runs the path on `stream` (several times when tuning), synchronises it,
+ *   and finally enqueues one graph launch, whose results the outputs hold
+ *   once `stream` has been synchronised.  M >= 1.  The buffers must stay
  *   allocated until the plan is destroyed.
  * lagp_plan_launch -- enqueues one run (one graph launch) on `stream`.
  * lagp_plan_describe -- the timings and the chosen variants, as text.

@@ -58,7 +58,7 @@ struct IncArgs {
     double *gz;               // global z columns, gcols * CAP doubles per workgroup
     int gcols;
     int zl_cols;
-    int zrow;                 // LDS row length of a proposed z row (>= a.n)
+    int zrow;                 // LDS row length of a proposed z row (a.n rounded up to 8)
 };
 
 // RL: the chosen row l reaches the lanes by v_readlane from a per-lane copy
@@ -88,6 +88,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
     __shared__ double alc_out[kIncNmax];
     __shared__ int32_t seldi[kIncNmax];
     __shared__ double xs[kIncPmax];
+    __shared__ double acc_pred[3];  // z_h.t, t.t, z_h.z_h so far (thread 0)
     __shared__ int ctl_status, ctl_loc;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         int status = ctl_status;
         for (int k = 0; k < p; k++)
             if (status == kLocOk && !isfinite(xs[k])) status = kLocNonfinite;
-        double mu = 0.0, psi = 0.0, zz = 0.0;  // z_h.t, t.t, z_h.z_h so far
+        if (tid == 0) acc_pred[0] = acc_pred[1] = acc_pred[2] = 0.0;
 
         // the z row of slot s, entries [0, j), into dst (one lane)
         auto put_row = [&](int s, int j, double *dst) {
@@ -243,12 +244,12 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
             // ===== (3) z_h and t = L^{-1} Y gain their entry j
             const double wh = uniform(pub[par][vw][1] / lam);
             const double tn = uniform(pub[par][vw][2] / lam);
-            mu = uniform(fma(wh, tn, mu));
-            psi = uniform(fma(tn, tn, psi));
-            zz = uniform(fma(wh, wh, zz));
             if (tid == 0) {
                 seldi[j] = red_i[par][vw];
                 alc_out[j] = vbest;
+                acc_pred[0] = fma(wh, tn, acc_pred[0]);
+                acc_pred[1] = fma(tn, tn, acc_pred[1]);
+                acc_pred[2] = fma(wh, wh, acc_pred[2]);
             }
             if (j + 1 == n) continue;  // the design is complete: no more scoring
 
@@ -293,7 +294,9 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 #pragma unroll
             for (int k = 0; k < kIncPmax; k++) xw[k] = uniform(k < p ? cx[k * CAP + wpos] : 0.0);
             const double qw = uniform(cq[wpos]);
-            const int jc = j >> 3, ju = j & 7;
+            // the entry index, as a scalar: the write below is a scalar branch, not
+            // a select over every register column
+            const int jc = __builtin_amdgcn_readfirstlane(j >> 3), ju = __builtin_amdgcn_readfirstlane(j & 7);
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 const int pos = tid + s * TB;
@@ -310,7 +313,10 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                         if (c == jc)
 #pragma unroll
                             for (int u = 0; u < 8; u++)
-                                if (u == ju) z[s][c * 8 + u] = wc;
+                                if (u == ju) {
+                                    asm volatile("");  // keeps this a scalar branch, not a select per column
+                                    z[s][c * 8 + u] = wc;
+                                }
                 } else if (j < G0) {
                     zl[(j - ZR) * CAP + pos] = wc;
                 } else {
@@ -333,6 +339,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         if (w == 0) {
             const bool ok = status == kLocOk;
             if (lane == 0) {
+                const double mu = acc_pred[0], psi = acc_pred[1], zz = acc_pred[2];
                 const double s2 = psi * (kappa - zz) / n;
                 if (a.mean) a.mean[m] = ok ? mu : NAN;
                 if (a.s2) a.s2[m] = ok ? s2 : NAN;
@@ -365,7 +372,9 @@ constexpr size_t kDynLds = kLdsLimit - kStaticReserve;
 struct Sched {
     int tb, s, zr;
     constexpr int cap() const { return tb * s; }
-    static int zrow(int n_max) { return (n_max + 1) & ~1; }
+    // the proposed rows are copied in whole chunks of 8 register entries, so a
+    // row slot holds n_max rounded up to a multiple of 8
+    static int zrow(int n_max) { return (n_max + 7) & ~7; }
     // dynamic LDS bytes: p coordinates and a norm per position, zl LDS
     // columns, and the double-buffered proposed rows of the waves
     size_t lds(int p, int zl, int n_max) const

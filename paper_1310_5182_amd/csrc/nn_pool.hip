@@ -400,8 +400,10 @@ hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, i
 {
     if (M == 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
-    // locations per workgroup: 1, 2 or 4 (default 2)
-    const int G = grouping < 0 ? 2 : 1 << (grouping < nn_pool_groupings(Np) ? grouping : 0);
+    // locations per workgroup: 1, 2 or 4.  One is the default: measured on
+    // MI355X, sharing the pass over X costs more in serialised selections and
+    // residency than it saves in L2 traffic (plans time all of them).
+    const int G = grouping < 0 ? 1 : 1 << (grouping < nn_pool_groupings(Np) ? grouping : 0);
     if (Np <= 512) return launch_g<2048, 512>(G, X, N, p, XX, M, Np, pool, st);
     if (Np <= 1024) return launch_g<2048, 1024>(G, X, N, p, XX, M, Np, pool, st);
     if (Np <= kNnMaxNp) return launch_g<4096, 2048>(G > 2 ? 2 : G, X, N, p, XX, M, Np, pool, st);

@@ -169,8 +169,10 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
         if (run != hipSuccess) e = run;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(P->exec, st);  // the outputs hold one run's results
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
+        if (P->exec) (void)hipGraphExecDestroy(P->exec);
         if (P->graph) (void)hipGraphDestroy(P->graph);
         delete P;
         return plan_fail(LAGP_EHIP, "graph capture", e);
