@@ -43,6 +43,28 @@ def mfma_flops(n0: int, n: int, Np: int) -> float:
     return float(sum(2.0 * (Np - j) * j * j for j in range(n0, n)))
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter record kept in
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy calibration), or None
+    if there is none or the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    import re
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for block in re.findall(r"```json\n(.*?)\n```", open(path).read(), re.S):
+            rec = json.loads(block)
+            if rec.get("kernel") != kernel or rec.get("workload") != workload:
+                continue
+            h = hashlib.sha256()
+            for src in rec["sources"]:
+                with open(os.path.join(ROOT, src), "rb") as f:
+                    h.update(f.read())
+            if h.hexdigest() == rec["source_sha256"]:
+                return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
 def alc_evals(n0: int, n: int, Np: int) -> int:
     return sum(Np - j for j in range(n0, n))
 
@@ -185,6 +207,7 @@ def main() -> int:
     head = max(precs, key=lambda k: res[k]["loc_per_s"])
     oh = paths[head][1]
     st = oh["status"].cpu().numpy()
+    traffic = None
     if cfg == 3:
         nn_, Npn = W.n_per.astype(np.int64), W.Np_per.astype(np.int64)
         flops = float(sum(inc_flops(n0, int(a), int(b)) for a, b in zip(nn_, Npn)))
@@ -204,6 +227,8 @@ def main() -> int:
         kname, kms_head = "alc_inc_kernel (float64)", kms["alc_fp64"]
         bound, peak, unit = "alu", PEAK["fp64_vector"], "TFLOP/s"
         per_unit = f"{inc_flops(n0, n, Np):.4g} flops per location (sum_j (N'-j-1)(2j+4))"
+        if cfg == 2 and M == 10000:
+            traffic = measured_traffic("alc_inc_kernel<512, 2, 40, true>", "config2")
     achieved = flops / (kms_head * 1e-3)
     guard = oh["guard"].cpu().numpy() if "guard" in oh else np.zeros(M)
 
@@ -284,7 +309,7 @@ def main() -> int:
         "plan": plan_info,
         "status_nonzero": int(np.count_nonzero(st)),
         "roofline": {"kernel": kname, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": unit, "frac": achieved / peak, "traffic": None, "per_unit": per_unit},
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic, "per_unit": per_unit},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
