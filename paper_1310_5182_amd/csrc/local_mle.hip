@@ -1,10 +1,16 @@
 // Local likelihood, its derivatives, the local MLE of the lengthscale and
 // prediction on a fixed local design (Sec. 2.1 eq. gpk; Fig. 1 steps 3, 5).
 //
-// One wave per location; lane r owns row r of every n x n matrix (n <= 64).
-// The matrices live in LDS with an odd row stride; the wave is its own
-// synchronisation domain, so the only ordering needed between lanes is a
-// wave-scope fence.  Everything is float64.
+// One 256-thread workgroup per location; every n x n step is spread over the
+// whole workgroup (thread t owns the elements (a, b) with a = t/16 mod 16 and
+// b = t mod 16 in steps of 16).  K^{-1} comes from the symmetric sweep
+// (Gauss-Jordan on the positive-definite K, pivots in order): with v the
+// current row k and p = v_k, every element takes A_ab - v_a v_b / p, row and
+// column k become v / p and the pivot -1/p; after all n pivots the matrix is
+// -K^{-1}.  It stays symmetric, so each thread keeps its (up to 16) elements
+// in registers and only row k travels through LDS: one barrier per pivot.
+// The pivots are the Schur complements, so log|K| is the sum of their logs.
+// Everything is float64.
 //
 // Negative log of eq. gpk with K = exp(-D2/d) + g I, A = K^{-1},
 // alpha = A Y, psi = Y^T alpha:
@@ -15,6 +21,8 @@
 //   d2nll/dd2 = (1/2) (tr(A Kdd) - tr(A Kd A Kd))
 //               - (n/2) ((alpha^T Kdd alpha - 2 (Kd alpha)^T A (Kd alpha)) / psi
 //                        + (alpha^T Kd alpha)^2 / psi^2)
+// tr(A Kd) and tr(A Kdd) are element sums (A and Kd symmetric), and
+// tr(A Kd A Kd) = sum_ab B_ab B_ba with B = A Kd, formed pair by pair.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -22,244 +30,230 @@
 
 namespace lagp {
 
-constexpr int kGpWaves = 1;  // waves (locations) per workgroup
+constexpr int kGpThreads = 256;
+constexpr int kGpWaves = kGpThreads / kWave;
 constexpr int kGpNmax = 64;
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+constexpr int kGpSlots = 4;  // rotating reduction slots (one barrier per reduction)
+constexpr int kGpRed = 8;    // values per reduction
 
 struct GpEval {
     double nll, dd, dg, d2;
     bool ok;
 };
 
-// Per-wave LDS workspace.
-struct GpWave {
-    double *M1;  // K, then its Cholesky factor L (lower), then A = K^{-1}
-    double *M2;  // L^{-1}, then scratch
-    double *xs;  // design rows [n][p]
-    double *ys;  // responses [n]
-    int S;       // row stride
-    int n, p, lane;
+// Per-location LDS workspace and the workgroup's view of it.
+struct GpBlock {
+    double *M1;    // K, then A = K^{-1} (row stride S)
+    double *M2;    // Kd
+    double *xs;    // design rows [n][p]
+    double *ys;    // responses [n]
+    double *colk;  // sweep: pivot row (even pivots), then alpha
+    double *rowk;  // sweep: pivot row (odd pivots), then Kd alpha
+    double *piv;   // sweep pivots
+    double (*red)[kGpWaves][kGpRed];
+    int S, n, p, tid, lane, w, slot;
+    double nll0;  // -lgamma(n/2) + (n/2) log(2 pi), the same at every evaluation
 
     __device__ double r2(int a, int b) const
     {
         return sqdist_strict(xs + a * p, 1, xs + b * p, 1, p);
     }
 
-    // Cholesky of M1 in place (lower triangle); false if a pivot is not positive.
-    __device__ bool cholesky()
+    // Block sums of K values (one per thread each); every thread gets them,
+    // summed in the same order.  Contains the barrier that publishes them.
+    template <int K>
+    __device__ void bsum(double (&v)[K])
     {
-        const int i = lane;
-        for (int k = 0; k < n; k++) {
-            const double akk = M1[k * S + k];
-            if (!(akk > 0.0)) return false;
-            const double lkk = sqrt(akk);
-            double lik = 0.0;
-            if (i > k && i < n) {
-                lik = M1[i * S + k] / lkk;
-                M1[i * S + k] = lik;
-            }
-            wave_sync();
-            if (i == k) M1[k * S + k] = lkk;
-            if (i > k && i < n) {
-                int c = k + 1;
-                for (; c + 4 <= i + 1; c += 4) {
-                    const double a0 = M1[i * S + c], a1 = M1[i * S + c + 1];
-                    const double a2 = M1[i * S + c + 2], a3 = M1[i * S + c + 3];
-                    const double l0 = M1[c * S + k], l1 = M1[(c + 1) * S + k];
-                    const double l2 = M1[(c + 2) * S + k], l3 = M1[(c + 3) * S + k];
-                    M1[i * S + c] = a0 - lik * l0;
-                    M1[i * S + c + 1] = a1 - lik * l1;
-                    M1[i * S + c + 2] = a2 - lik * l2;
-                    M1[i * S + c + 3] = a3 - lik * l3;
-                }
-                for (; c <= i; c++) M1[i * S + c] -= lik * M1[c * S + k];
-            }
-            wave_sync();
+        static_assert(K <= kGpRed, "reduction width");
+        double (*r)[kGpRed] = red[slot];
+        slot = (slot + 1) % kGpSlots;
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const double s = wave_sum(v[q]);
+            if (lane == 0) r[w][q] = s;
         }
-        return true;
-    }
-
-    // Solve L w = b (b held one entry per lane), returns w in the lane.
-    __device__ double forward(double b) const
-    {
-        double w = 0.0;
-        for (int t = 0; t < n; t++) {
-            const double wt = readlane(b, t) / M1[t * S + t];
-            if (lane == t) w = wt;
-            if (lane > t && lane < n) b -= M1[lane * S + t] * wt;
-        }
-        return w;
-    }
-
-    // Solve L^T x = w.
-    __device__ double backward(double w) const
-    {
-        double x = 0.0;
-        for (int t = n - 1; t >= 0; t--) {
-            const double xt = readlane(w, t) / M1[t * S + t];
-            if (lane == t) x = xt;
-            if (lane < t) w -= M1[t * S + lane] * xt;
-        }
-        return x;
-    }
-
-    // M2 = L^{-1} (lower), row by row: lane j computes entry (i, j), j < i.
-    __device__ void invert_l()
-    {
-        const int j = lane;
-        for (int i = 0; i < n; i++) {
-            const double lii = M1[i * S + i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < K; q++) {
             double s = 0.0;
-            if (j < i) {
-#pragma unroll 4
-                for (int t = j; t < i; t++) s += M1[i * S + t] * M2[t * S + j];
-                M2[i * S + j] = -s / lii;
-            } else if (j == i) {
-                M2[i * S + i] = 1.0 / lii;
-            } else if (j < n) {
-                M2[i * S + j] = 0.0;
-            }
-            wave_sync();
+#pragma unroll
+            for (int u = 0; u < kGpWaves; u++) s += r[u][q];
+            v[q] = s;
         }
     }
 
-    // M1 = A = L^{-T} L^{-1}: lane a accumulates row a, A_ab = sum_{t >= a, b} Li_ta Li_tb,
-    // reading row t of L^{-1} as broadcasts.
-    __device__ void form_inverse()
+    // M1 = K -> K^{-1} by the symmetric sweep, elements in registers; M1 must
+    // hold K on entry (read once).  False if a pivot is not positive.
+    __device__ bool invert()
     {
-        const int a = lane;
-        double row[kGpNmax];
+        const int ta = tid >> 4 & 15, tb = tid & 15;
+        double e[4][4];
 #pragma unroll
-        for (int b = 0; b < kGpNmax; b++) row[b] = 0.0;
-        for (int t = 0; t < n; t++) {
-            const double lta = (a < n && a <= t) ? M2[t * S + a] : 0.0;
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int b = 0; b < kGpNmax; b++)
-                if (b <= t) row[b] += lta * M2[t * S + b];
+            for (int j = 0; j < 4; j++) {
+                const int a = ta + 16 * i, b = tb + 16 * j;
+                e[i][j] = (a < n && b < n) ? M1[a * S + b] : 0.0;
+            }
+        for (int k = 0; k < n; k++) {
+            double *v = (k & 1) ? rowk : colk;  // double-buffered pivot row
+            if (ta == (k & 15)) {
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    if (ta + 16 * i == k)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if (tb + 16 * j < n) v[tb + 16 * j] = e[i][j];
+            }
+            __syncthreads();
+            const double pk = v[k];
+            if (!(pk > 0.0)) return false;  // uniform: every thread reads the same pivot
+            const double ip = 1.0 / pk;
+            if (tid == 0) piv[k] = pk;
+            double va[4], vb[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                va[i] = ta + 16 * i < n ? v[ta + 16 * i] : 0.0;
+                vb[i] = tb + 16 * i < n ? v[tb + 16 * i] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int a = ta + 16 * i;
+                const double sa = va[i] * ip;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int b = tb + 16 * j;
+                    if (a == k)
+                        e[i][j] = b == k ? -ip : vb[j] * ip;
+                    else if (b == k)
+                        e[i][j] = sa;
+                    else
+                        e[i][j] = fma(-sa, vb[j], e[i][j]);
+                }
+            }
         }
-        wave_sync();
-        if (a < n)
+        // A = K^{-1} = minus the swept matrix
 #pragma unroll
-            for (int b = 0; b < kGpNmax; b++)
-                if (b < n) M1[a * S + b] = row[b];
-        wave_sync();
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int a = ta + 16 * i, b = tb + 16 * j;
+                if (a < n && b < n) M1[a * S + b] = -e[i][j];
+            }
+        __syncthreads();
+        return true;
     }
 
     // order 0: value; 1: + first derivatives; 2: + d2nll/dd2.
     __device__ GpEval eval(double d, double g, int order)
     {
         GpEval e{NAN, NAN, NAN, NAN, false};
-        const int a = lane;
-        for (int b = 0; b < n; b++)
-            if (a < n) M1[a * S + b] = exp(-r2(a, b) / d) + (a == b ? g : 0.0);
-        wave_sync();
-        if (!cholesky()) return e;
-        const double ya = a < n ? ys[a] : 0.0;
-        const double w = forward(ya);
-        const double alpha = backward(w);
-        const double psi = wave_sum(ya * alpha);
-        const double logdet = 2.0 * wave_sum(a < n ? log(M1[a * S + a]) : 0.0);
-        e.nll = -lgamma(0.5 * n) + 0.5 * n * log(2.0 * M_PI) + 0.5 * logdet + 0.5 * n * log(0.5 * psi);
+        const int ta = tid >> 4 & 15, tb = tid & 15;
+        const double nid = -1.0 / d;
+        for (int a = ta; a < n; a += 16)
+            for (int b = tb; b < n; b += 16) M1[a * S + b] = exp(r2(a, b) * nid) + (a == b ? g : 0.0);
+        __syncthreads();
+        if (!invert()) return e;
+        // alpha = A Y (in colk), psi, log|K|
+        double al = 0.0;
+        if (tid < n) {
+            for (int b = 0; b < n; b++) al = fma(M1[tid * S + b], ys[b], al);
+            colk[tid] = al;
+        }
+        double s0[2] = {tid < n ? ys[tid] * al : 0.0, tid < n ? log(piv[tid]) : 0.0};
+        bsum(s0);
+        const double psi = s0[0], logdet = s0[1];
+        e.nll = nll0 + 0.5 * logdet + 0.5 * n * log(0.5 * psi);
         e.ok = isfinite(e.nll);
         if (order == 0 || !e.ok) return e;
 
-        invert_l();
-        form_inverse();  // M1 = A
-        // row a of Kd and Kdd on the fly; traces and quadratic forms
-        double tr_akd = 0.0, tr_akdd = 0.0, kda = 0.0, kdda = 0.0;
-        const double d2i = 1.0 / (d * d);
-        for (int b = 0; b < n; b++) {
-            const double alb = readlane(alpha, b);
-            if (a < n) {
+        // Kd into M2; traces and quadratic forms in one pass over the elements
+        const double d2i = 1.0 / (d * d), d3i = d2i / d;
+        double s1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // tr(A Kd), tr(A Kdd), aKda, aKdda, tr A, a.a
+        for (int a = ta; a < n; a += 16) {
+            const double aa_ = colk[a];
+            for (int b = tb; b < n; b += 16) {
                 const double q = r2(a, b);
-                const double c = exp(-q / d);
+                const double c = exp(q * nid);
                 const double kd = c * q * d2i;
-                const double kdd = c * (q * q * d2i * d2i - 2.0 * q * d2i / d);
+                const double kdd = c * (q * q * d2i * d2i - 2.0 * q * d3i);
+                M2[a * S + b] = kd;
                 const double ab = M1[a * S + b];
-                tr_akd += ab * kd;
-                tr_akdd += ab * kdd;
-                kda += kd * alb;
-                kdda += kdd * alb;
+                s1[0] = fma(ab, kd, s1[0]);
+                s1[1] = fma(ab, kdd, s1[1]);
+                const double ab_ = aa_ * colk[b];
+                s1[2] = fma(ab_, kd, s1[2]);
+                s1[3] = fma(ab_, kdd, s1[3]);
+                if (a == b) s1[4] += ab;
             }
         }
-        const double trA = wave_sum(a < n ? M1[a * S + a] : 0.0);
-        const double aa = wave_sum(alpha * alpha);
-        const double aKda = wave_sum(alpha * kda);
-        e.dd = 0.5 * wave_sum(tr_akd) - 0.5 * n * aKda / psi;
-        e.dg = 0.5 * trA - 0.5 * n * aa / psi;
+        if (tid < n) s1[5] = colk[tid] * colk[tid];
+        bsum(s1);
+        const double aKda = s1[2];
+        e.dd = 0.5 * s1[0] - 0.5 * n * aKda / psi;
+        e.dg = 0.5 * s1[4] - 0.5 * n * s1[5] / psi;
         if (order < 2) return e;
 
-        // (Kd alpha)^T A (Kd alpha): v = Kd alpha is `kda` in the lanes
-        double av = 0.0;
-        for (int b = 0; b < n; b++) {
-            const double vb = readlane(kda, b);
-            if (a < n) av += M1[a * S + b] * vb;
+        // v = Kd alpha (in rowk)
+        if (tid < n) {
+            double v = 0.0;
+            for (int b = 0; b < n; b++) v = fma(M2[tid * S + b], colk[b], v);
+            rowk[tid] = v;
         }
-        const double vAv = wave_sum(kda * av);
-        const double aKdda = wave_sum(alpha * kdda);
-        // tr(A Kd A Kd) = sum_ab B_ab B_ba with B = A Kd: M2 <- Kd, row a of B in
-        // registers (row c of Kd read as broadcasts), B back into M2, then columns
-        if (a < n)
-            for (int b = 0; b < n; b++) {
-                const double q = r2(a, b);
-                M2[a * S + b] = exp(-q / d) * q * d2i;
+        __syncthreads();
+        // v^T A v, and tr(B B) over element pairs a <= b of B = A Kd
+        double s2[2] = {0.0, 0.0};
+        if (tid < n) {
+            double av = 0.0;
+            for (int b = 0; b < n; b++) av = fma(M1[tid * S + b], rowk[b], av);
+            s2[0] = rowk[tid] * av;
+        }
+        for (int a = ta; a < n; a += 16)
+            for (int b = tb; b < n; b += 16) {
+                if (b < a) continue;
+                double bab = 0.0, bba = 0.0;
+                for (int c = 0; c < n; c++) {
+                    bab = fma(M1[a * S + c], M2[c * S + b], bab);
+                    bba = fma(M1[b * S + c], M2[c * S + a], bba);
+                }
+                s2[1] = fma(a == b ? 1.0 : 2.0, bab * bba, s2[1]);
             }
-        wave_sync();
-        double brow[kGpNmax];
-#pragma unroll
-        for (int b = 0; b < kGpNmax; b++) brow[b] = 0.0;
-        for (int c = 0; c < n; c++) {
-            const double aac = a < n ? M1[a * S + c] : 0.0;
-#pragma unroll
-            for (int b = 0; b < kGpNmax; b++)
-                if (b < n) brow[b] += aac * M2[c * S + b];
-        }
-        wave_sync();
-        if (a < n)
-#pragma unroll
-            for (int b = 0; b < kGpNmax; b++)
-                if (b < n) M2[a * S + b] = brow[b];
-        wave_sync();
-        double trbb = 0.0;
-        if (a < n)
-            for (int b = 0; b < n; b++) trbb += M2[a * S + b] * M2[b * S + a];
-        const double trBB = wave_sum(trbb);
-        e.d2 = 0.5 * (wave_sum(tr_akdd) - trBB) - 0.5 * n * ((aKdda - 2.0 * vAv) / psi + aKda * aKda / (psi * psi));
+        bsum(s2);
+        e.d2 = 0.5 * (s1[1] - s2[1]) - 0.5 * n * ((s1[3] - 2.0 * s2[0]) / psi + aKda * aKda / (psi * psi));
         return e;
     }
 };
 
-
 template <int MODE>
-__global__ __launch_bounds__(kGpWaves *kWave) void local_gp_kernel(GpArgs a)
+__global__ __launch_bounds__(kGpThreads) void local_gp_kernel(GpArgs a)
 {
     extern __shared__ double lds[];
-    const int lane = threadIdx.x & 63;
-    const int64_t m = (int64_t)blockIdx.x * kGpWaves + (threadIdx.x >> 6);
-    if (m >= a.M) return;
+    __shared__ double red[kGpSlots][kGpWaves][kGpRed];
+    __shared__ int ctl_bad;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t m = blockIdx.x;
     const int n = a.n, p = a.p, S = n + 1;
-    double *base = lds + (size_t)(threadIdx.x >> 6) * (2 * n * S + n * p + n);
-    GpWave W{base, base + n * S, base + 2 * n * S, base + 2 * n * S + n * p, S, n, p, lane};
+    double *base = lds;
+    GpBlock W{base,           base + n * S,         base + 2 * n * S,
+              base + 2 * n * S + n * p,             base + 2 * n * S + n * p + n,
+              base + 2 * n * S + n * p + 2 * n,     base + 2 * n * S + n * p + 3 * n,
+              red,            S, n, p, tid, lane, w, 0, -lgamma(0.5 * n) + 0.5 * n * log(2.0 * M_PI)};
 
     // stage the design rows and responses
-    int bad = 0;
-    if (lane < n) {
-        const int32_t di = a.sel[m * n + lane];
+    if (tid == 0) ctl_bad = 0;
+    __syncthreads();
+    if (tid < n) {
+        const int32_t di = a.sel[m * n + tid];
         if (di < 0 || di >= a.N) {
-            bad = 1;
+            ctl_bad = 1;
         } else {
-            for (int k = 0; k < p; k++) W.xs[lane * p + k] = a.X[(int64_t)di * p + k];
-            W.ys[lane] = a.Y[di];
+            for (int k = 0; k < p; k++) W.xs[tid * p + k] = a.X[(int64_t)di * p + k];
+            W.ys[tid] = a.Y[di];
         }
     }
-    wave_sync();
-    const bool bad_sel = __ballot(bad) != 0;
+    __syncthreads();
+    const bool bad_sel = ctl_bad != 0;
     const double g = a.g_arr ? a.g_arr[m] : a.g_scalar;
     const double d_in = a.d_arr ? a.d_arr[m] : a.d_scalar;
 
@@ -267,7 +261,7 @@ __global__ __launch_bounds__(kGpWaves *kWave) void local_gp_kernel(GpArgs a)
         const int order = MODE == kGpNll ? (a.d2 ? 2 : ((a.dd || a.dg) ? 1 : 0)) : 1;
         GpEval e{NAN, NAN, NAN, NAN, false};
         if (!bad_sel && d_in > 0.0 && g > 0.0) e = W.eval(d_in, g, order);
-        if (lane == 0) {
+        if (tid == 0) {
             if constexpr (MODE == kGpNll) {
                 if (a.nll) a.nll[m] = e.nll;
                 if (a.dd) a.dd[m] = e.dd;
@@ -324,36 +318,47 @@ __global__ __launch_bounds__(kGpWaves *kWave) void local_gp_kernel(GpArgs a)
                 }
             }
         }
-        if (lane == 0) {
+        if (tid == 0) {
             if (a.d_hat) a.d_hat[m] = d;
             if (a.nll) a.nll[m] = f.nll;
             if (a.iters) a.iters[m] = it;
             if (a.status) a.status[m] = st;
         }
     } else {
-        // prediction at XX[m] on the fixed design (eqs. predgp, preds2)
+        // prediction at XX[m] on the fixed design (eqs. predgp, preds2):
+        // mu = h^T A Y, s2 = psi (kappa - h^T A h) / n
         const double *x = a.XX + m * p;
         const double kappa = 1.0 + g;
         double mu = NAN, s2 = NAN;
         int st = bad_sel ? 4 : 0;
         if (!bad_sel) {
-            const int r = lane;
-            for (int b = 0; b < n; b++)
-                if (r < n) W.M1[r * S + b] = exp(-W.r2(r, b) / d_in) + (r == b ? g : 0.0);
-            wave_sync();
-            if (!W.cholesky()) {
+            const int ta = tid >> 4 & 15, tb = tid & 15;
+            for (int r = ta; r < n; r += 16)
+                for (int b = tb; b < n; b += 16) W.M1[r * S + b] = exp(-W.r2(r, b) / d_in) + (r == b ? g : 0.0);
+            __syncthreads();
+            if (!W.invert()) {
                 st = 1;
             } else {
-                const double ya = r < n ? W.ys[r] : 0.0;
-                const double h = r < n ? corr64(sqdist_strict(W.xs + r * p, 1, x, 1, p), d_in) : 0.0;
-                const double alpha = W.backward(W.forward(ya));
-                const double zh = W.forward(h);
-                const double psi = wave_sum(ya * alpha);
-                mu = wave_sum(h * alpha);
-                s2 = psi * (kappa - wave_sum(zh * zh)) / n;
+                // h in rowk, then A h and A Y row by row
+                if (tid < n) W.rowk[tid] = corr64(sqdist_strict(W.xs + tid * p, 1, x, 1, p), d_in);
+                __syncthreads();
+                double s[3] = {0.0, 0.0, 0.0};  // h.A.Y, Y.A.Y, h.A.h
+                if (tid < n) {
+                    double ay = 0.0, ah = 0.0;
+                    for (int b = 0; b < n; b++) {
+                        ay = fma(W.M1[tid * S + b], W.ys[b], ay);
+                        ah = fma(W.M1[tid * S + b], W.rowk[b], ah);
+                    }
+                    s[0] = W.rowk[tid] * ay;
+                    s[1] = W.ys[tid] * ay;
+                    s[2] = W.rowk[tid] * ah;
+                }
+                W.bsum(s);
+                mu = s[0];
+                s2 = s[1] * (kappa - s[2]) / n;
             }
         }
-        if (lane == 0) {
+        if (tid == 0) {
             if (a.mean) a.mean[m] = mu;
             if (a.s2) a.s2[m] = s2;
             if (a.var) a.var[m] = n > 2 ? s2 * n / (n - 2) : NAN;
@@ -364,7 +369,7 @@ __global__ __launch_bounds__(kGpWaves *kWave) void local_gp_kernel(GpArgs a)
 
 size_t local_gp_lds(int n, int p)
 {
-    return (size_t)kGpWaves * (2 * n * (n + 1) + n * p + n) * sizeof(double);
+    return (size_t)(2 * n * (n + 1) + n * p + 4 * n) * sizeof(double);
 }
 
 bool local_gp_supported(int n, int p)
@@ -375,7 +380,7 @@ bool local_gp_supported(int n, int p)
 hipError_t launch_local_gp(const GpArgs &a, int mode, hipStream_t st)
 {
     if (a.M == 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.M + kGpWaves - 1) / kGpWaves)), block(kGpWaves * kWave);
+    const dim3 grid((unsigned)a.M), block(kGpThreads);
     const size_t lds = local_gp_lds(a.n, a.p);
     if (lds > 64 * 1024) {  // above the default dynamic-LDS limit
         hipError_t e = hipSuccess;

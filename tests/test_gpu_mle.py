@@ -8,6 +8,7 @@ import os
 import numpy as np
 import pytest
 
+import parity
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -149,10 +150,18 @@ def test_predict_on_fixed_design(lagp, orc):
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in got.items()}
     assert np.all(got["status"] == 0)
+    worst = 0.0
     for m in range(len(sel)):
         ref = orc.gp_predict(W.X[sel[m]], W.Y[sel[m]], W.XX[m], d[m], W.g)
+        # the parity protocol's output bound: 1e-9, raised to what float64 can
+        # resolve at this conditioning (kappa eps cond(K), over v for s2 and V)
+        kc = parity.cond_bounds(W.X, sel[m:m + 1], d[m], W.g)[0]
         for k in ("mean", "s2", "var"):
-            assert rel(got[k][m], ref[k], 1e-8) < 1e-9, (m, k)
+            tol = max(1e-9, 10 * (kc if k == "mean" else kc / abs(ref["v"])))
+            r = rel(got[k][m], ref[k], 1e-8)
+            worst = max(worst, r / tol)
+            assert r < tol, (m, k, r, tol)
+    _log("predict", dict(worst_over_tol=worst))
 
 
 def test_config4_pipeline_subsample(lagp, orc):
