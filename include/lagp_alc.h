@@ -183,6 +183,7 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  * lagp_plan_create -- arguments as for lagp_alc_uneven_from_pool plus the
  *   pool [M x Np_max] it fills.  Unless flags has LAGP_PLAN_NO_TUNE, the
  *   plan first times the variants of each tunable launch on these inputs
+ *   (on at most their first 65,536 locations)
  *   (locations per NN workgroup; for each pool-size schedule of the ALC
  *   kernel, how the chosen factor row reaches the lanes) and keeps the
  *   fastest; the chosen launches are then captured into a graph.  Creation

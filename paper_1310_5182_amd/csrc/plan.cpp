@@ -67,8 +67,14 @@ static hipError_t time_path(const lagp_plan_s &P, int grouping, int bcast, hipSt
 }
 
 // Coordinate search: the NN grouping first, then each schedule's broadcast bit.
-static hipError_t tune(lagp_plan_s &P, hipStream_t st)
+// The timing runs use at most the first kTuneLocations locations (their
+// outputs are overwritten later), so that tuning stays short for large M.
+constexpr int64_t kTuneLocations = 65536;
+
+static hipError_t tune(lagp_plan_s &Pfull, hipStream_t st)
 {
+    lagp_plan_s P = Pfull;
+    if (P.a.M > kTuneLocations) P.a.M = kTuneLocations;
     char line[160];
     float best = 0.0f;
     int g_best = 0, mask = 0x7;
@@ -98,10 +104,11 @@ static hipError_t tune(lagp_plan_s &P, hipStream_t st)
             mask = m2;
         }
     }
-    P.grouping = g_best;
-    P.bcast = mask;
-    snprintf(line, sizeof line, "; chosen nn g=%d alc mask=%x (%.3f ms)", 1 << g_best, mask, best);
-    P.info += line;
+    Pfull.grouping = g_best;
+    Pfull.bcast = mask;
+    snprintf(line, sizeof line, "; chosen nn g=%d alc mask=%x (%.3f ms on %lld locations)", 1 << g_best, mask,
+             best, (long long)P.a.M);
+    Pfull.info = P.info + line;
     return hipSuccess;
 }
 
