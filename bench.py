@@ -191,7 +191,11 @@ def main() -> int:
     # ---- per-kernel timing with HIP events, same launches as in the step
     o = paths[precs[0]][1]
     pool = o["pool"]
-    kms = {"nn_pool": timer.run(lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool), args.steps)}
+    # the NN variant the step runs: plans may stream a float32 copy of X
+    nn32 = plan_info is not None and ("chosen" not in plan_info or " x32" in plan_info.split("chosen")[-1])
+    nnws = torch.empty(W.N * W.p * 4 + 256, dtype=torch.uint8, device=dev) if nn32 else None
+    kms = {"nn_pool": timer.run(lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, f32_copy=nn32,
+                                                     workspace=nnws), args.steps)}
     if cfg == 3:
         kms["alc_fp64_uneven"] = timer.run(
             lambda: lagp.alc_uneven_from_pool(X, Y, XX, pool, n0, n, d, g, n_per=n_per, Np_per=Np_per,

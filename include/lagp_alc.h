@@ -84,6 +84,21 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
                          int32_t Np, int32_t *pool, void *stream);
 
 /*
+ * lagp_nn_pool_workspace -- bytes of device workspace that lagp_nn_pool_ws
+ *   needs: a float32 copy of X (N p 4 bytes, rounded up to 256).
+ * lagp_nn_pool_ws -- lagp_nn_pool, streaming a float32 copy of X that it
+ *   first writes into `workspace` (half the bytes per pass over the design);
+ *   the float64 row is read only for the rows that the float32 screen keeps,
+ *   so the pools are identical to lagp_nn_pool's.  workspace: device memory
+ *   of at least lagp_nn_pool_workspace(N, p) bytes, 16-byte aligned (else
+ *   LAGP_EWORKSPACE); calls that overlap must not share it.
+ */
+lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, size_t *bytes);
+lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
+                            int32_t Np, int32_t *pool, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/*
  * lagp_alc_from_pool -- greedy ALC local designs and local predictions
  * (Fig. 1 steps 2a, 2b and 5) from given candidate pools.
  *
@@ -176,17 +191,21 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
                                       void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Plans: the whole float64 path with per-location sizes (lagp_nn_pool with
- * Np_max into `pool`, then lagp_alc_uneven_from_pool) bound to fixed
+ * Plans: the whole float64 path with per-location sizes (lagp_nn_pool_ws
+ * with Np_max into `pool`, then lagp_alc_uneven_from_pool) bound to fixed
  * buffers, autotuned and captured into one HIP graph.
  *
+ * lagp_plan_workspace -- bytes of device workspace that lagp_plan_create
+ *   needs: lagp_alc_uneven_workspace's, then lagp_nn_pool_workspace's.
  * lagp_plan_create -- arguments as for lagp_alc_uneven_from_pool plus the
- *   pool [M x Np_max] it fills.  Unless flags has LAGP_PLAN_NO_TUNE, the
- *   plan first times the variants of each tunable launch on these inputs
- *   (on at most their first 65,536 locations)
- *   (locations per NN workgroup; for each pool-size schedule of the ALC
- *   kernel, how the chosen factor row reaches the lanes) and keeps the
- *   fastest; the chosen launches are then captured into a graph.  Creation
+ *   pool [M x Np_max] it fills; the workspace (16-byte aligned) must hold
+ *   lagp_plan_workspace bytes.  Unless flags has LAGP_PLAN_NO_TUNE, the
+ *   plan first times the variants of each tunable launch on these inputs,
+ *   on at most their first 65,536 locations (locations per NN workgroup;
+ *   whether the NN kernel streams the float32 copy of X; for each pool-size
+ *   schedule of the ALC kernel, how the chosen factor row reaches the
+ *   lanes), and keeps the fastest; the chosen launches are then captured
+ *   into a graph.  Creation
  *   runs the path on `stream` (several times when tuning), synchronises it,
  *   and finally enqueues one graph launch, whose results the outputs hold
  *   once `stream` has been synchronised.  M >= 1.  The buffers must stay
@@ -197,6 +216,9 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  */
 typedef struct lagp_plan_s *lagp_plan;
 #define LAGP_PLAN_NO_TUNE 1
+
+lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max, int32_t n_max,
+                                size_t *bytes);
 
 lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
                              int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,

@@ -43,8 +43,12 @@ def version() -> str:
     return _lib.load().lagp_version().decode()
 
 
-def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None = None) -> torch.Tensor:
-    """M x Np int32 pools: the Np nearest design rows of each location, sorted by (distance, index)."""
+def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None = None,
+            f32_copy: bool = False, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """M x Np int32 pools: the Np nearest design rows of each location, sorted by (distance, index).
+
+    f32_copy: stream a float32 copy of X (lagp_nn_pool_ws; same pools) kept in
+    `workspace` (a uint8 device tensor, allocated here if None or too small)."""
     L = _lib.load()
     X, XX = _f64(X, "X"), _f64(XX, "XX")
     M, p = XX.shape
@@ -52,8 +56,16 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
         raise ValueError("X must be N x p with the p of XX")
     if out is None:
         out = torch.empty((M, Np), dtype=torch.int32, device=X.device)
-    _lib.check(L.lagp_nn_pool(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
-                              _stream(X.device)))
+    if not f32_copy:
+        _lib.check(L.lagp_nn_pool(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
+                                  _stream(X.device)))
+        return out
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(L.lagp_nn_pool_workspace(X.shape[0], p, ctypes.byref(nbytes)))
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
+    _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
+                                 workspace.data_ptr(), workspace.numel(), _stream(X.device)))
     return out
 
 
@@ -176,7 +188,7 @@ class Plan:
         o = _outputs(M, n_max, dev)
         o["pool"] = torch.empty((M, Np_max), dtype=torch.int32, device=dev)
         nbytes = ctypes.c_size_t(0)
-        _lib.check(L.lagp_alc_uneven_workspace(p, M, Np_max, n_max, ctypes.byref(nbytes)))
+        _lib.check(L.lagp_plan_workspace(X.shape[0], p, M, Np_max, n_max, ctypes.byref(nbytes)))
         o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
         self._keep = (X, Y, XX, n_per, Np_per)
         self.out, self._dev, self._h = o, dev, ctypes.c_void_p()

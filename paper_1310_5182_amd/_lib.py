@@ -20,10 +20,13 @@ LAGP_FP64_REFORM = 2
 # Every symbol declared in include/lagp_alc.h.
 EXPORTS = (
     "lagp_nn_pool",
+    "lagp_nn_pool_workspace",
+    "lagp_nn_pool_ws",
     "lagp_alc_from_pool",
     "lagp_alc_predict",
     "lagp_alc_uneven_workspace",
     "lagp_alc_uneven_from_pool",
+    "lagp_plan_workspace",
     "lagp_plan_create",
     "lagp_plan_launch",
     "lagp_plan_describe",
@@ -59,6 +62,10 @@ def load():
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.lagp_nn_pool.argtypes = [P, i64, i32, P, i64, i32, P, P]
     L.lagp_nn_pool.restype = i32
+    L.lagp_nn_pool_workspace.argtypes = [i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_nn_pool_workspace.restype = i32
+    L.lagp_nn_pool_ws.argtypes = [P, i64, i32, P, i64, i32, P, P, ctypes.c_size_t, P]
+    L.lagp_nn_pool_ws.restype = i32
     L.lagp_alc_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, i32,
                                      P, P, P, P, P, P, P, P, P]
     L.lagp_alc_from_pool.restype = i32
@@ -70,6 +77,8 @@ def load():
     L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, f64, f64,
                                             i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
     L.lagp_alc_uneven_from_pool.restype = i32
+    L.lagp_plan_workspace.argtypes = [i64, i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_plan_workspace.restype = i32
     L.lagp_plan_create.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, P, P, P, f64, f64, P, P, P, P, P,
                                    P, P, P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
     L.lagp_plan_create.restype = i32

@@ -87,6 +87,33 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
     return ok();
 }
 
+lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, size_t *bytes)
+{
+    if (!bytes) return fail(LAGP_EINVAL, "bytes must be non-NULL");
+    if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
+    if (p > lagp::kMaxP) return fail(LAGP_EUNSUPPORTED, "p = %d > %d", p, lagp::kMaxP);
+    if (N < 1 || N >= (int64_t)1 << 31) return fail(LAGP_EINVAL, "N = %lld outside [1, 2^31)", (long long)N);
+    *bytes = lagp::nn_pool_workspace(N, p);
+    return ok();
+}
+
+lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
+                            int32_t Np, int32_t *pool, void *workspace, size_t workspace_bytes,
+                            void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (lagp::nn_pool_cap(Np) == 0) return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", Np);
+    if (M == 0) return ok();
+    if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < lagp::nn_pool_workspace(N, p))
+        return fail(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes",
+                    lagp::nn_pool_workspace(N, p));
+    hipError_t e = lagp::launch_nn_pool(X, N, p, XX, M, Np, pool, (hipStream_t)stream, -1, (float *)workspace);
+    if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
+    return ok();
+}
+
 lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,
                                int32_t n0, int32_t n, double d, double g, int32_t precision,

@@ -43,8 +43,11 @@ int nn_pool_cap(int Np);
 // Number of location groupings (2^g locations per workgroup) for pools of Np;
 // grouping < 0 picks the default.
 int nn_pool_groupings(int Np);
+// x32 (nullable): workspace of nn_pool_workspace(N, p) bytes for a float32
+// copy of X, which the stream then reads instead of X.
+size_t nn_pool_workspace(int64_t N, int p);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                          int32_t *pool, hipStream_t st, int grouping = -1);
+                          int32_t *pool, hipStream_t st, int grouping = -1, float *x32 = nullptr);
 
 // Returns hipErrorNotSupported (without launching) when no compiled schedule
 // covers (p, Np, n, precision).

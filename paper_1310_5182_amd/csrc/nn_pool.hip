@@ -21,7 +21,13 @@
 // errs by at most ~4uB, squaring adds ~20uB^2 per coordinate in all, and the
 // float32 sum of p terms errs by at most (p-1)u times its value, so
 // |d32 - d| <= 40 p u B^2 + 2 p u d32 (twice the first-order terms).  B is the
-// larger of the row's and the location's largest coordinate magnitude.
+// larger of the row's and the location's largest coordinate magnitude; taken
+// from the float32 values, it is short of the exact one by a factor of at most
+// 1 - u, far inside the bound's slack.
+//
+// With a float32 copy of X (made once per call into caller workspace), the
+// stream reads half the bytes and the float64 row is fetched only for the rows
+// that pass the float32 test.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -229,7 +235,8 @@ __device__ void bitonic_sort(uint64_t *keys, int32_t *idx)
 // G: locations per workgroup; CAP: LDS buffer entries per location
 // (>= SORTN + chunk); SORTN: power of two >= Np; PF: p at compile time.
 template <int G, int CAP, int SORTN, int PF>
-__global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restrict__ X, int64_t N,
+__global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restrict__ X,
+                                                           const float *__restrict__ X32, int64_t N,
                                                            const double *__restrict__ XX, int64_t M,
                                                            int Np, int32_t *__restrict__ pool)
 {
@@ -293,12 +300,19 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
                 double xr[PF];
                 float xrf[PF];
                 float rmax = 0.0f;
+                if (X32) {  // uniform: a kernel argument
 #pragma unroll
-                for (int k = 0; k < PF; k++) {
-                    xr[k] = X[i * PF + k];
-                    xrf[k] = (float)xr[k];
-                    rmax = fmaxf(rmax, fabsf(xrf[k]));
+                    for (int k = 0; k < PF; k++) xrf[k] = X32[i * PF + k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PF; k++) {
+                        xr[k] = X[i * PF + k];
+                        xrf[k] = (float)xr[k];
+                    }
                 }
+                bool have64 = X32 == nullptr;
+#pragma unroll
+                for (int k = 0; k < PF; k++) rmax = fmaxf(rmax, fabsf(xrf[k]));
 #pragma unroll
                 for (int g = 0; g < G; g++) {
                     float d32 = 0.0f;
@@ -309,6 +323,11 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
                     }
                     const float B = fmaxf(rmax, lmax[g]);
                     if (d32 * kSlope - kConst * B * B < tf[g] && g < ng) {
+                        if (!have64) {
+#pragma unroll
+                            for (int k = 0; k < PF; k++) xr[k] = X[i * PF + k];
+                            have64 = true;
+                        }
                         const double s = sqdist_strict(xr, 1, xs[g], 1, p);
                         const uint64_t key = __builtin_bit_cast(uint64_t, s);
                         if (key_less(key, (int32_t)i, tk[g], ti[g])) {
@@ -339,14 +358,14 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
 // Locations per workgroup: more share each pass over X; fewer keep more
 // workgroups resident (each location holds CAP keys in LDS).
 template <int G, int CAP, int SORTN>
-static hipError_t launch_cap(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                             int32_t *pool, hipStream_t st)
+static hipError_t launch_cap(const double *X, const float *X32, int64_t N, int p, const double *XX, int64_t M,
+                             int Np, int32_t *pool, hipStream_t st)
 {
     dim3 grid((unsigned)((M + G - 1) / G)), block(kNnBlock);
     switch (p) {
 #define LAGP_NN_CASE(P)                                                                                 \
     case P:                                                                                             \
-        hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P>), grid, block, 0, st, X, N, XX, M, Np, pool); \
+        hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P>), grid, block, 0, st, X, X32, N, XX, M, Np, pool); \
         break;
         LAGP_NN_CASE(1)
         LAGP_NN_CASE(2)
@@ -380,14 +399,25 @@ int nn_pool_cap(int Np)
 }
 
 template <int CAP, int SORTN>
-static hipError_t launch_g(int G, const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                           int32_t *pool, hipStream_t st)
+static hipError_t launch_g(int G, const double *X, const float *X32, int64_t N, int p, const double *XX,
+                           int64_t M, int Np, int32_t *pool, hipStream_t st)
 {
-    if (G == 1) return launch_cap<1, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+    if (G == 1) return launch_cap<1, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
     if constexpr (CAP <= 2048) {  // four buffers of 4096 keys would not fit in LDS
-        if (G == 4) return launch_cap<4, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+        if (G == 4) return launch_cap<4, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
     }
-    return launch_cap<2, CAP, SORTN>(X, N, p, XX, M, Np, pool, st);
+    return launch_cap<2, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
+}
+
+__global__ void nn_to_f32(const double *__restrict__ X, float *__restrict__ X32, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        X32[i] = (float)X[i];
+}
+
+size_t nn_pool_workspace(int64_t N, int p)
+{
+    return ((size_t)N * p * sizeof(float) + 255) & ~(size_t)255;
 }
 
 int nn_pool_groupings(int Np)
@@ -396,17 +426,23 @@ int nn_pool_groupings(int Np)
 }
 
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                          int32_t *pool, hipStream_t st, int grouping)
+                          int32_t *pool, hipStream_t st, int grouping, float *x32)
 {
     if (M == 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
+    if (x32) {
+        const int64_t count = N * p;
+        const unsigned grid = (unsigned)((count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096);
+        hipLaunchKernelGGL(nn_to_f32, dim3(grid), dim3(256), 0, st, X, x32, count);
+    }
+    const float *X32 = x32;
     // locations per workgroup: 1, 2 or 4.  One is the default: measured on
     // MI355X, sharing the pass over X costs more in serialised selections and
     // residency than it saves in L2 traffic (plans time all of them).
     const int G = grouping < 0 ? 1 : 1 << (grouping < nn_pool_groupings(Np) ? grouping : 0);
-    if (Np <= 512) return launch_g<2048, 512>(G, X, N, p, XX, M, Np, pool, st);
-    if (Np <= 1024) return launch_g<2048, 1024>(G, X, N, p, XX, M, Np, pool, st);
-    if (Np <= kNnMaxNp) return launch_g<4096, 2048>(G > 2 ? 2 : G, X, N, p, XX, M, Np, pool, st);
+    if (Np <= 512) return launch_g<2048, 512>(G, X, X32, N, p, XX, M, Np, pool, st);
+    if (Np <= 1024) return launch_g<2048, 1024>(G, X, X32, N, p, XX, M, Np, pool, st);
+    if (Np <= kNnMaxNp) return launch_g<4096, 2048>(G > 2 ? 2 : G, X, X32, N, p, XX, M, Np, pool, st);
     return hipErrorInvalidValue;
 }
 

@@ -2,8 +2,9 @@
 //
 // A plan binds one problem's buffers, picks the fastest variant of each
 // tunable launch by timing it on those very inputs (locations per NN
-// workgroup; for every pool-size schedule of the ALC kernel, how the chosen
-// factor row is broadcast), and captures the chosen launches - NN pools,
+// workgroup and whether the NN kernel streams a float32 copy of X; for every
+// pool-size schedule of the ALC kernel, how the chosen factor row is
+// broadcast), and captures the chosen launches - NN pools,
 // queue planning, persistent ALC workgroups - into one HIP graph.  Replaying
 // the graph costs one launch call; every node is a kernel (no memset nodes).
 #include <hip/hip_runtime.h>
@@ -20,9 +21,11 @@ struct lagp_plan_s {
     const int32_t *n_per, *Np_per;
     const int64_t *sel_off;
     int32_t *pool;
-    void *ws;
+    void *ws;         // the ALC kernels' part of the workspace
     size_t ws_bytes;
+    float *x32;       // then the float32 copy of X that the NN kernel may stream
     int grouping = -1;  // NN locations per workgroup: 2^grouping
+    bool use32 = true;  // the NN kernel streams x32
     int bcast = -1;     // ALC broadcast mask
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -32,15 +35,17 @@ struct lagp_plan_s {
 namespace lagp {
 
 // Enqueue the whole path with the given variants.
-static hipError_t run_path(const lagp_plan_s &P, int grouping, int bcast, hipStream_t st)
+static hipError_t run_path(const lagp_plan_s &P, int grouping, bool use32, int bcast, hipStream_t st)
 {
-    hipError_t e = launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, grouping);
+    hipError_t e = launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, grouping,
+                                  use32 ? P.x32 : nullptr);
     if (e != hipSuccess) return e;
     return launch_alc_uneven(P.a, P.n_per, P.Np_per, P.sel_off, P.ws, P.ws_bytes, st, bcast);
 }
 
 // Milliseconds of one run (the best of `reps`, after one untimed run).
-static hipError_t time_path(const lagp_plan_s &P, int grouping, int bcast, hipStream_t st, int reps, float *ms)
+static hipError_t time_path(const lagp_plan_s &P, int grouping, bool use32, int bcast, hipStream_t st, int reps,
+                            float *ms)
 {
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -50,10 +55,10 @@ static hipError_t time_path(const lagp_plan_s &P, int grouping, int bcast, hipSt
         return e;
     }
     float best = 1e30f;
-    e = run_path(P, grouping, bcast, st);
+    e = run_path(P, grouping, use32, bcast, st);
     for (int r = 0; e == hipSuccess && r < reps; r++) {
         if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        if ((e = run_path(P, grouping, bcast, st)) != hipSuccess) break;
+        if ((e = run_path(P, grouping, use32, bcast, st)) != hipSuccess) break;
         if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float t = 0.0f;
@@ -66,7 +71,8 @@ static hipError_t time_path(const lagp_plan_s &P, int grouping, int bcast, hipSt
     return e;
 }
 
-// Coordinate search: the NN grouping first, then each schedule's broadcast bit.
+// Coordinate search: the NN variant (grouping, float32 copy) first, then each
+// schedule's broadcast bit.
 // The timing runs use at most the first kTuneLocations locations (their
 // outputs are overwritten later), so that tuning stays short for large M.
 constexpr int64_t kTuneLocations = 65536;
@@ -78,25 +84,30 @@ static hipError_t tune(lagp_plan_s &Pfull, hipStream_t st)
     char line[160];
     float best = 0.0f;
     int g_best = 0, mask = 0x7;
-    hipError_t e = time_path(P, 0, mask, st, 2, &best);
+    bool u_best = true;
+    hipError_t e = time_path(P, 0, true, mask, st, 2, &best);
     if (e != hipSuccess) return e;
-    snprintf(line, sizeof line, "nn g=1 alc mask=%x: %.3f ms", mask, best);
+    snprintf(line, sizeof line, "nn g=1 x32 alc mask=%x: %.3f ms", mask, best);
     P.info += line;
-    for (int g = 1; g < nn_pool_groupings(P.a.Np); g++) {
-        float t = 0.0f;
-        if ((e = time_path(P, g, mask, st, 2, &t)) != hipSuccess) return e;
-        snprintf(line, sizeof line, "; nn g=%d: %.3f ms", 1 << g, t);
-        P.info += line;
-        if (t < best) {
-            best = t;
-            g_best = g;
+    for (int g = 0; g < nn_pool_groupings(P.a.Np); g++) {
+        for (int u = 1; u >= 0; u--) {
+            if (g == 0 && u == 1) continue;  // timed above
+            float t = 0.0f;
+            if ((e = time_path(P, g, u == 1, mask, st, 2, &t)) != hipSuccess) return e;
+            snprintf(line, sizeof line, "; nn g=%d%s: %.3f ms", 1 << g, u ? " x32" : "", t);
+            P.info += line;
+            if (t < best) {
+                best = t;
+                g_best = g;
+                u_best = u == 1;
+            }
         }
     }
     const int top = alc_inc_schedule(P.a.Np);
     for (int b = 0; b <= top; b++) {
         const int m2 = mask ^ (1 << b);
         float t = 0.0f;
-        if ((e = time_path(P, g_best, m2, st, 2, &t)) != hipSuccess) return e;
+        if ((e = time_path(P, g_best, u_best, m2, st, 2, &t)) != hipSuccess) return e;
         snprintf(line, sizeof line, "; alc mask=%x: %.3f ms", m2, t);
         P.info += line;
         if (t < best) {
@@ -105,9 +116,10 @@ static hipError_t tune(lagp_plan_s &Pfull, hipStream_t st)
         }
     }
     Pfull.grouping = g_best;
+    Pfull.use32 = u_best;
     Pfull.bcast = mask;
-    snprintf(line, sizeof line, "; chosen nn g=%d alc mask=%x (%.3f ms on %lld locations)", 1 << g_best, mask,
-             best, (long long)P.a.M);
+    snprintf(line, sizeof line, "; chosen nn g=%d%s alc mask=%x (%.3f ms on %lld locations)", 1 << g_best,
+             u_best ? " x32" : "", mask, best, (long long)P.a.M);
     Pfull.info = P.info + line;
     return hipSuccess;
 }
@@ -123,6 +135,17 @@ lagp_status plan_fail(lagp_status code, const char *msg, hipError_t e = hipSucce
 }  // namespace
 
 extern "C" {
+
+lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes)
+{
+    size_t nn = 0;
+    lagp_status s = lagp_nn_pool_workspace(N, p, &nn);
+    if (s != LAGP_OK) return s;
+    s = lagp_alc_uneven_workspace(p, M, Np_max, n_max, bytes);
+    if (s != LAGP_OK) return s;
+    *bytes = ((*bytes + 255) & ~(size_t)255) + nn;
+    return LAGP_OK;
+}
 
 lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
                              int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,
@@ -141,10 +164,13 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     if (s != LAGP_OK) return s;  // its message stays in lagp_last_error()
     if (!pool) return plan_fail(LAGP_EINVAL, "pool must be non-NULL");
     if (lagp::nn_pool_cap(Np_max) == 0) return plan_fail(LAGP_EUNSUPPORTED, "Np_max too large for the pool kernel");
-    size_t need = 0;
-    hipError_t e = lagp::alc_uneven_workspace(p, M, Np_max, n_max, &need);
+    size_t need = 0, need_alc = 0;
+    hipError_t e = lagp::alc_uneven_workspace(p, M, Np_max, n_max, &need_alc);
     if (e != hipSuccess) return plan_fail(LAGP_EHIP, "workspace query", e);
-    if (!workspace || workspace_bytes < need) return plan_fail(LAGP_EWORKSPACE, "workspace too small");
+    need_alc = (need_alc + 255) & ~(size_t)255;
+    need = need_alc + lagp::nn_pool_workspace(N, p);
+    if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < need)
+        return lagp::set_error(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes", need);
     if (!X || !Y || !XX || !sel) return plan_fail(LAGP_EINVAL, "X, Y, XX and sel must be non-NULL");
 
     lagp_plan_s *P = new lagp_plan_s();
@@ -155,7 +181,8 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     P->sel_off = sel_off;
     P->pool = pool;
     P->ws = workspace;
-    P->ws_bytes = workspace_bytes;
+    P->ws_bytes = need_alc;
+    P->x32 = (float *)((char *)workspace + need_alc);
     hipStream_t st = (hipStream_t)stream;
     if (flags & LAGP_PLAN_NO_TUNE) {
         P->info = "defaults (not tuned)";
@@ -171,7 +198,7 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     }
     if ((e = hipStreamSynchronize(st)) == hipSuccess &&
         (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
-        hipError_t run = lagp::run_path(*P, P->grouping, P->bcast, cs);
+        hipError_t run = lagp::run_path(*P, P->grouping, P->use32, P->bcast, cs);
         e = hipStreamEndCapture(cs, &P->graph);
         if (run != hipSuccess) e = run;
     }
