@@ -233,9 +233,18 @@ __device__ void bitonic_sort(uint64_t *keys, int32_t *idx)
 }
 
 // G: locations per workgroup; CAP: LDS buffer entries per location
-// (>= SORTN + chunk); SORTN: power of two >= Np; PF: p at compile time.
-template <int G, int CAP, int SORTN, int PF>
-__global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restrict__ X,
+// (>= SORTN + chunk); SORTN: power of two >= Np; PF: p at compile time;
+// F32: stream the float32 copy X32 (else X).
+// Waves per SIMD that the LDS of one-location workgroups allows (five at
+// CAP = 2048, three at 3072): registers are held to that occupancy.
+template <int G, int CAP>
+constexpr int nn_waves()
+{
+    return G != 1 ? 1 : CAP <= 2048 ? 5 : CAP <= 3072 ? 3 : 1;
+}
+
+template <int G, int CAP, int SORTN, int PF, bool F32>
+__global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_waves<G, CAP>()))) void nn_pool_kernel(const double *__restrict__ X,
                                                            const float *__restrict__ X32, int64_t N,
                                                            const double *__restrict__ XX, int64_t M,
                                                            int Np, int32_t *__restrict__ pool)
@@ -278,9 +287,6 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
     constexpr float kConst = 40.0f * PF * kU;
 
     for (int64_t base = 0; base < N; base += kNnChunk) {
-#pragma unroll 1
-        for (int g = 0; g < G; g++)  // uniform: counts change only before barriers
-            if (grp[g].count + kNnChunk > CAP) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
         uint64_t tk[G];
         int32_t ti[G];
         float tf[G];
@@ -293,6 +299,9 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
             const float f = (float)td;  // td >= 0: the next float up is the next bit pattern
             tf[g] = (double)f < td ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
         }
+        // bit g * kNnItems + it: the row of item `it` passed for location g but
+        // found the buffer full; it is tried again after the next selection
+        uint32_t pend = 0;
 #pragma unroll
         for (int it = 0; it < kNnItems; it++) {
             const int64_t i = base + it * kNnBlock + threadIdx.x;
@@ -300,7 +309,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
                 double xr[PF];
                 float xrf[PF];
                 float rmax = 0.0f;
-                if (X32) {  // uniform: a kernel argument
+                if constexpr (F32) {
 #pragma unroll
                     for (int k = 0; k < PF; k++) xrf[k] = X32[i * PF + k];
                 } else {
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
                         xrf[k] = (float)xr[k];
                     }
                 }
-                bool have64 = X32 == nullptr;
+                bool have64 = !F32;
 #pragma unroll
                 for (int k = 0; k < PF; k++) rmax = fmaxf(rmax, fabsf(xrf[k]));
 #pragma unroll
@@ -332,14 +341,44 @@ __global__ __launch_bounds__(kNnBlock) void nn_pool_kernel(const double *__restr
                         const uint64_t key = __builtin_bit_cast(uint64_t, s);
                         if (key_less(key, (int32_t)i, tk[g], ti[g])) {
                             const int pos = atomicAdd(&grp[g].count, 1);
-                            keys[g][pos] = key;
-                            idxs[g][pos] = (int32_t)i;
+                            if (pos < CAP) {
+                                keys[g][pos] = key;
+                                idxs[g][pos] = (int32_t)i;
+                            } else {
+                                pend |= 1u << (g * kNnItems + it);
+                            }
                         }
                     }
                 }
             }
         }
         __syncthreads();
+        // A full buffer: keep the Np smallest of its CAP keys, then insert the
+        // rows that did not fit and still beat the new threshold (at most one
+        // chunk, and CAP >= Np + chunk).  Every thread reads the same count:
+        // it changes only at the end of select_keep, after a barrier.
+#pragma unroll 1
+        for (int g = 0; g < G; g++) {
+            if (grp[g].count > CAP) {
+                select_keep(keys[g], idxs[g], S, grp[g], CAP, Np);
+                const uint64_t nk = grp[g].thr_k;
+                const int32_t ni = grp[g].thr_i;
+#pragma unroll
+                for (int it = 0; it < kNnItems; it++) {
+                    if ((pend >> (g * kNnItems + it)) & 1u) {
+                        const int64_t i = base + it * kNnBlock + threadIdx.x;
+                        const double s = sqdist_strict(X + i * PF, 1, xs[g], 1, p);
+                        const uint64_t key = __builtin_bit_cast(uint64_t, s);
+                        if (key_less(key, (int32_t)i, nk, ni)) {
+                            const int pos = atomicAdd(&grp[g].count, 1);
+                            keys[g][pos] = key;
+                            idxs[g][pos] = (int32_t)i;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
 #pragma unroll 1
     for (int g = 0; g < ng; g++) {
@@ -363,9 +402,14 @@ static hipError_t launch_cap(const double *X, const float *X32, int64_t N, int p
 {
     dim3 grid((unsigned)((M + G - 1) / G)), block(kNnBlock);
     switch (p) {
-#define LAGP_NN_CASE(P)                                                                                 \
-    case P:                                                                                             \
-        hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P>), grid, block, 0, st, X, X32, N, XX, M, Np, pool); \
+#define LAGP_NN_CASE(P)                                                                                    \
+    case P:                                                                                                \
+        if (X32)                                                                                           \
+            hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P, true>), grid, block, 0, st, X, X32, N, XX, M, \
+                               Np, pool);                                                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((nn_pool_kernel<G, CAP, SORTN, P, false>), grid, block, 0, st, X, X32, N, XX, M, \
+                               Np, pool);                                                                  \
         break;
         LAGP_NN_CASE(1)
         LAGP_NN_CASE(2)
@@ -394,7 +438,7 @@ int nn_pool_cap(int Np)
 {
     if (Np <= 512) return 2048;
     if (Np <= 1024) return 2048;
-    if (Np <= kNnMaxNp) return 4096;
+    if (Np <= kNnMaxNp) return 3072;
     return 0;
 }
 
@@ -403,7 +447,7 @@ static hipError_t launch_g(int G, const double *X, const float *X32, int64_t N, 
                            int64_t M, int Np, int32_t *pool, hipStream_t st)
 {
     if (G == 1) return launch_cap<1, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
-    if constexpr (CAP <= 2048) {  // four buffers of 4096 keys would not fit in LDS
+    if constexpr (CAP <= 2048) {  // four buffers of 3072 keys would not fit in LDS
         if (G == 4) return launch_cap<4, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
     }
     return launch_cap<2, CAP, SORTN>(X, X32, N, p, XX, M, Np, pool, st);
@@ -442,7 +486,7 @@ hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, i
     const int G = grouping < 0 ? 1 : 1 << (grouping < nn_pool_groupings(Np) ? grouping : 0);
     if (Np <= 512) return launch_g<2048, 512>(G, X, X32, N, p, XX, M, Np, pool, st);
     if (Np <= 1024) return launch_g<2048, 1024>(G, X, X32, N, p, XX, M, Np, pool, st);
-    if (Np <= kNnMaxNp) return launch_g<4096, 2048>(G > 2 ? 2 : G, X, X32, N, p, XX, M, Np, pool, st);
+    if (Np <= kNnMaxNp) return launch_g<3072, 2048>(G > 2 ? 2 : G, X, X32, N, p, XX, M, Np, pool, st);
     return hipErrorInvalidValue;
 }
 
