@@ -61,8 +61,52 @@ struct IncArgs {
     int zrow;                 // LDS row length of a proposed z row (a.n rounded up to 8)
 };
 
-// RL: the chosen row l reaches the lanes by v_readlane from a per-lane copy
-// (VALU) instead of uniform-address LDS reads (LDS return bandwidth).
+// acc + z_0 l_0 + ... + z_7 l_7 in that order, fused multiply-adds, where l_u
+// is lane OFF + u of the caller's 16-lane row: DPP row_newbcast delivers it as
+// an operand, so the broadcast costs no instruction.  The s_nop gives the two
+// wait states a DPP read needs after a VALU write of its source.
+template <int OFF>
+__device__ __forceinline__ double fma8_rowbcast(double acc, double l, double z0, double z1, double z2, double z3,
+                                                double z4, double z5, double z6, double z7)
+{
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %3 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %4 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %5 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %1, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(l), "v"(z0), "v"(z1), "v"(z2), "v"(z3), "v"(z4), "v"(z5), "v"(z6), "v"(z7), "n"(OFF),
+          "n"(OFF + 1), "n"(OFF + 2), "n"(OFF + 3), "n"(OFF + 4), "n"(OFF + 5), "n"(OFF + 6), "n"(OFF + 7));
+    return acc;
+}
+
+// Register part of the dot products z_c . l: chunk C holds entries 8C .. 8C+7,
+// whose l values sit in lanes 8(C & 1) .. of row group C / 2.  Whole chunks
+// below j: entries from j on are zero on both sides.
+template <int C, int S, int ZR, int NR>
+__device__ __forceinline__ void dot_rowbcast(double (&acc)[S], const double (&lr)[NR], const double (&z)[S][ZR],
+                                             int j)
+{
+    if constexpr (C * 8 < ZR) {
+        if (C * 8 < j) {
+#pragma unroll
+            for (int s = 0; s < S; s++)
+                acc[s] = fma8_rowbcast<(C & 1) * 8>(acc[s], lr[C >> 1], z[s][C * 8], z[s][C * 8 + 1],
+                                                    z[s][C * 8 + 2], z[s][C * 8 + 3], z[s][C * 8 + 4],
+                                                    z[s][C * 8 + 5], z[s][C * 8 + 6], z[s][C * 8 + 7]);
+        }
+        dot_rowbcast<C + 1>(acc, lr, z, j);
+    }
+}
+
+// RL: the chosen row l reaches the lanes through DPP row broadcasts from a
+// per-lane copy (no instruction of its own) instead of uniform-address LDS
+// reads (LDS return bandwidth).
 template <int TB, int S, int ZR, bool RL>
 __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
 {
@@ -257,23 +301,28 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
             double acc[S];
 #pragma unroll
             for (int s = 0; s < S; s++) acc[s] = 0.0;
-            double lrow = 0.0;  // lane i holds l_i (register part of the row)
-            if constexpr (RL) lrow = lane < j && lane < ZR ? el[lane] : 0.0;
+            if constexpr (RL) {
+                // lane i of every 16-lane row holds entries 16 k + i of l (zero
+                // from j on), broadcast across the row inside the FMAs
+                double lr[(ZR + 15) / 16];
 #pragma unroll
-            for (int c = 0; c < NCH; c++) {
-                if (c * 8 < j) {
-                    double e[8];
+                for (int k = 0; k < (ZR + 15) / 16; k++) {
+                    const int e = 16 * k + (lane & 15);
+                    lr[k] = e < j && e < ZR ? el[e] : 0.0;
+                }
+                dot_rowbcast<0>(acc, lr, z, j);
+            } else {
 #pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        if constexpr (RL)
-                            e[u] = readlane(lrow, c * 8 + u);
-                        else
-                            e[u] = el[c * 8 + u];
+                for (int c = 0; c < NCH; c++) {
+                    if (c * 8 < j) {
+                        double e[8];
+#pragma unroll
+                        for (int u = 0; u < 8; u++) e[u] = el[c * 8 + u];
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+#pragma unroll
+                            for (int s = 0; s < S; s++) acc[s] = fma(z[s][c * 8 + u], e[u], acc[s]);
                     }
-#pragma unroll
-                    for (int u = 0; u < 8; u++)
-#pragma unroll
-                        for (int s = 0; s < S; s++) acc[s] = fma(z[s][c * 8 + u], e[u], acc[s]);
                 }
             }
             const int jl = j < G0 ? j : G0;
