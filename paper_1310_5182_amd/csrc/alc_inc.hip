@@ -24,9 +24,10 @@
 // (q < ZR), in LDS columns (q < ZR + zl_cols) or in a per-workgroup global
 // workspace column (beyond), laid out [entry][position] so that every access
 // is a coalesced, lane-private one.  A step: each wave reduces the argmax of
-// its candidates, every wave combines the per-wave winners, the winning lane
-// publishes its z row (l) in LDS, and after one barrier every lane extends its
-// own rows.  Two barriers per scored step, one per forced (initial) step.
+// its candidates and its best lane publishes that candidate's z row and
+// scalars in LDS (double-buffered by step parity); after one barrier every
+// wave combines the per-wave winners and every lane extends its own rows.
+// One barrier per step.
 //
 // Locations come either one per workgroup (uniform n and N', grid = M) or
 // from a queue that persistent workgroups drain with an atomic counter
