@@ -60,6 +60,8 @@ class Oracle:
         L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, f64,
                               P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_alc.restype = i32
+        L.orc_alc_scores.argtypes = [P, i32, i32, P, i64, P, f64, f64, i32, P, P, P]
+        L.orc_alc_scores.restype = i32
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = i32
         L.orc_nll.argtypes = [P, P, i32, i32, f64, f64, P]
@@ -130,6 +132,20 @@ class Oracle:
     def max_threads(self) -> int:
         return self.L.orc_max_threads()
 
+    def alc_scores(self, Xj, Xc, x, d: float, g: float, mode_b: bool = False) -> dict:
+        """Scores v_j(x) - v_{j+1}(x) of every candidate row of Xc against the
+        design Xj at x (eq. dxy): delta (Nc), with K_j^{-1} (Kinv) and
+        h = K(X_j, x) as used by the paper's per-step kernel."""
+        Xj, Xc, x = _f64(np.atleast_2d(Xj)), _f64(np.atleast_2d(Xc)), _f64(x)
+        j, p = Xj.shape
+        Kinv, h = np.empty((j, j)), np.empty(j)
+        delta = np.empty(Xc.shape[0])
+        rc = self.L.orc_alc_scores(_p(Xj), j, p, _p(Xc), Xc.shape[0], _p(x), d, g, int(mode_b), _p(Kinv),
+                                   _p(h), _p(delta))
+        if rc:
+            raise ValueError(f"orc_alc_scores: {STATUS.get(rc, rc)}")
+        return dict(delta=delta, Kinv=Kinv, h=h)
+
     def nll(self, D, Yd, d: float, g: float) -> dict:
         """Negative log of eq. gpk and its derivatives: nll, dd, dg, d2 (d2nll/dd2)."""
         D, Yd = _f64(np.atleast_2d(D)), _f64(Yd)
@@ -182,6 +198,10 @@ def alc(*a, **k):
 
 def lagp(*a, **k):
     return default().lagp(*a, **k)
+
+
+def alc_scores(*a, **k):
+    return default().alc_scores(*a, **k)
 
 
 def max_threads() -> int:

@@ -513,6 +513,91 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
 }
 
 /* Threads OpenMP would use (for reporting). */
+/* ------------------------------------------------------------------ */
+/* Scores of a batch of candidates against one design (eq. dxy; the     */
+/* quantity the paper's per-step GPU kernel evaluates, Fig. 3).         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Design Xj (j x p), location x (p), candidates Xc (Nc x p).  For every
+ * candidate c, delta[c] = v_j(x) - v_{j+1}(x) when c is added to the design:
+ *   mode_b = 0: the plain definition through a Cholesky factor of K_j,
+ *               cov_c^2 / s_c (as in alc_one);
+ *   mode_b = 1: the paper's route, K_j^{-1} and the three terms of eq. dxy.
+ * -INFINITY where the candidate's conditional variance s_c is not positive.
+ * Optional outputs: Kinv (j x j) = K_j^{-1}, formed column by column from the
+ * factor, and h (j) = K(X_j, x).  Returns 0, 1 if K_j is not PD, 5 on bad
+ * arguments.
+ */
+int orc_alc_scores(const double *Xj, int j, int p, const double *Xc, int64_t Nc, const double *x,
+                   double d, double g, int mode_b, double *Kinv, double *h, double *delta)
+{
+    if (j < 1 || p < 1 || Nc < 0 || !(d > 0.0) || !(g > 0.0)) return ORC_BAD_ARGS;
+    const double kappa = 1.0 + g;
+    size_t jj = (size_t)j * j;
+    double *K = (double *)malloc(sizeof(double) * jj);
+    double *L = (double *)malloc(sizeof(double) * jj);
+    double *Ki = (double *)malloc(sizeof(double) * jj);
+    double *hv = (double *)malloc(sizeof(double) * (size_t)j);
+    double *zh = (double *)malloc(sizeof(double) * (size_t)j);
+    double *e = (double *)malloc(sizeof(double) * (size_t)j);
+    double *col = (double *)malloc(sizeof(double) * (size_t)j);
+    int rc = ORC_OK;
+    for (int a = 0; a < j; a++) {
+        for (int b = 0; b < j; b++) K[a * j + b] = kern(Xj + (size_t)a * p, Xj + (size_t)b * p, p, d);
+        K[a * j + a] += g;
+        hv[a] = kern(Xj + (size_t)a * p, x, p, d);
+    }
+    if (cholesky(K, L, j)) {
+        rc = ORC_INIT_NOT_PD;
+        goto done;
+    }
+    /* K^{-1} e_b = L^{-T} L^{-1} e_b */
+    for (int b = 0; b < j; b++) {
+        for (int a = 0; a < j; a++) e[a] = a == b ? 1.0 : 0.0;
+        forward_solve(L, e, zh, j);
+        backward_solve_t(L, zh, col, j);
+        for (int a = 0; a < j; a++) Ki[a * j + b] = col[a];
+    }
+    forward_solve(L, hv, zh, j);
+    if (Kinv) memcpy(Kinv, Ki, sizeof(double) * jj);
+    if (h) memcpy(h, hv, sizeof(double) * (size_t)j);
+#pragma omp parallel
+    {
+        double *kc = (double *)malloc(sizeof(double) * (size_t)j);
+        double *z = (double *)malloc(sizeof(double) * (size_t)j);
+        double *u = (double *)malloc(sizeof(double) * (size_t)j);
+        double *gv = (double *)malloc(sizeof(double) * (size_t)j);
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < Nc; c++) {
+            const double *xc = Xc + (size_t)c * p;
+            for (int a = 0; a < j; a++) kc[a] = kern(Xj + (size_t)a * p, xc, p, d);
+            const double kcx = kern(xc, x, p, d);
+            if (mode_b) {
+                delta[c] = dxy_score(Ki, kc, hv, kcx, kappa, u, gv, j);
+            } else {
+                forward_solve(L, kc, z, j);
+                const double sc = kappa - dot(z, z, j);
+                const double cov = kcx - dot(z, zh, j);
+                delta[c] = sc > 0.0 ? cov * cov / sc : -INFINITY;
+            }
+        }
+        free(kc);
+        free(z);
+        free(u);
+        free(gv);
+    }
+done:
+    free(K);
+    free(L);
+    free(Ki);
+    free(hv);
+    free(zh);
+    free(e);
+    free(col);
+    return rc;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

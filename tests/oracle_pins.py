@@ -27,6 +27,11 @@ What pins what:
   nll_derivatives_fd- d/dd, d/dg and d2/dd2 = central finite differences
   mle_optimality    - the Newton MLE is a stationary point (or a bound with
                       the gradient pointing out) and beats a fine local grid
+  scores_brute      - batch scores of many candidates against one design (both
+                      routes) = brute force v_j - v_{j+1}; K_j^{-1} K_j = I and
+                      h = K(X_j, x) from numpy; the one-point closed form
+  scores_greedy     - the batch scores at a step of a greedy run reproduce that
+                      step's best score and argmax
 """
 from __future__ import annotations
 
@@ -270,6 +275,47 @@ def mle_optimality(orc):
             assert orc.nll(D, Yd, t, W.g)["nll"] >= f["nll"] - 1e-9 * abs(f["nll"])
 
 
+def scores_brute(orc):
+    r = np.random.default_rng(21)
+    d, g = 0.3, 1e-3
+    for j, p in ((1, 2), (3, 2), (7, 3), (12, 1)):
+        Xj, Xc, x = r.random((j, p)), r.random((15, p)), r.random(p)
+        a = orc.alc_scores(Xj, Xc, x, d, g)
+        b = orc.alc_scores(Xj, Xc, x, d, g, mode_b=True)
+        want = np.array([brute.delta(Xj, c, x, d, g) for c in Xc])
+        assert np.all(want >= 0.0)
+        # the brute force differences two variances: errors scale with the largest score
+        scale = np.max(want)
+        assert np.max(np.abs(a["delta"] - want)) <= 1e-9 * scale, (j, p)
+        # the three terms of eq. dxy cancel: route noise grows with cond(K_j)
+        assert np.max(np.abs(b["delta"] - want)) <= 1e-7 * scale, (j, p)
+        K = brute.corr(Xj, Xj, d) + g * np.eye(j)
+        assert np.max(np.abs(a["Kinv"] @ K - np.eye(j))) < 1e-9
+        assert _rel(a["h"], brute.corr(Xj, x[None, :], d)[:, 0]) < 1e-15
+        if j == 1:  # closed form with a one-point design
+            kap = 1.0 + g
+            kc = brute.corr(Xc, Xj, d)[:, 0]
+            kx = brute.corr(Xc, x[None, :], d)[:, 0]
+            hh = a["h"][0]
+            cf = (kx - kc * hh / kap) ** 2 / (kap - kc * kc / kap)
+            assert _rel(a["delta"], cf) < 1e-12
+
+
+def scores_greedy(orc):
+    W = workloads.make(2, N=3000, M=3)
+    n0, n, Np = 6, 18, 120
+    out = orc.lagp(W.X, W.Y, W.XX, n0, n, Np, W.d, W.g)
+    for m in range(W.M):
+        for j in (n0, 11, n - 1):
+            design = out["sel"][m, :j]
+            cand = np.setdiff1d(out["pool"][m], design)
+            sc = orc.alc_scores(W.X[design], W.X[cand], W.XX[m], W.d, W.g)["delta"]
+            best = np.max(sc)
+            arg = int(np.min(cand[sc == best]))
+            assert abs(best - out["dmax"][m, j]) <= 1e-12 * best, (m, j)
+            assert arg == out["amax"][m, j], (m, j)
+
+
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
        special_cases, design_point, predict_textbook, route_b, forced, nll_textbook,
-       nll_derivatives_fd, mle_optimality]
+       nll_derivatives_fd, mle_optimality, scores_brute, scores_greedy]

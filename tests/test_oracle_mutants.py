@@ -9,6 +9,9 @@ import oracle
 import oracle_pins
 
 MUTANTS = {
+    # batch scores: covariance sign flipped, and the nugget left off K_j
+    "scores_cov_sign": ("const double cov = kcx - dot(z, zh, j);", "const double cov = kcx + dot(z, zh, j);"),
+    "scores_no_nugget": ("        K[a * j + a] += g;\n        hv[a]", "        K[a * j + a] += 1e-9;\n        hv[a]"),
     # the sign slip of Fig. 3 step 5 taken literally: (c + u.h)^2 / s
     "cov_sign": ("double cov = kcx - dot(w->zc, w->zh, j);", "double cov = kcx + dot(w->zc, w->zh, j);"),
     # nugget dropped from the candidate self-covariance
