@@ -69,6 +69,40 @@ def alc_evals(n0: int, n: int, Np: int) -> int:
     return sum(Np - j for j in range(n0, n))
 
 
+def scores_microbench(lagp, torch, timer, reps: int = 50) -> dict:
+    """One location against N' = 60,000 candidates at design sizes j = 16 .. 128
+    (the paper's ALC-in-isolation experiment, Sec. 4, on a 2-d design):
+    lagp_alc_scores in float64 and mixed precision.  K_j^{-1} and h are the
+    caller's inputs, formed here with numpy as the paper's host code formed them.
+    Algorithmic flops per call: 2 N' j^2 for the quadratic forms on the
+    matrix cores plus 2 N' j for the covariances."""
+    import workloads
+
+    Nc, p, d, g = 60000, 2, 0.1, 1e-4
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    out = {"Nc": Nc, "p": p, "d": d, "g": g, "reps": reps, "j": {}}
+    for j in (16, 32, 48, 64, 96, 128):
+        Xj, Xc, x = workloads.scores_case(j, Nc, p, 0)
+        D = ((Xj[:, None, :] - Xj[None, :, :]) ** 2).sum(-1)
+        Kinv = np.linalg.inv(np.exp(-D / d) + g * np.eye(j))
+        h = np.exp(-((Xj - x) ** 2).sum(-1) / d)
+        args = [dev(a) for a in (Xj, Kinv, Xc, x, h)]
+        delta = torch.empty(Nc, dtype=torch.float64, device="cuda")
+        flops = 2.0 * Nc * j * j + 2.0 * Nc * j
+        rec = {}
+        for prec, peak in (("fp64", PEAK["fp64_mfma"]), ("mixed", PEAK["fp32_mfma"])):
+            fn = lambda: lagp.alc_scores(*args, d, g, prec, out=delta)  # noqa: E731
+            fn()
+            ms = timer.run(fn, reps)
+            rec[prec] = {"us_per_call": ms * 1e3, "evals_per_s": Nc / (ms * 1e-3),
+                         "tflops": flops / (ms * 1e-3) / 1e12, "mfma_frac": flops / (ms * 1e-3) / peak}
+        out["j"][j] = rec
+        print(f"[bench] scores j={j}: fp64 {rec['fp64']['us_per_call']:.1f} us "
+              f"({rec['fp64']['evals_per_s']:.3g} evals/s, {rec['fp64']['mfma_frac'] * 100:.1f} % of MFMA peak), "
+              f"mixed {rec['mixed']['us_per_call']:.1f} us", file=sys.stderr, flush=True)
+    return out
+
+
 class Timer:
     """HIP events on the stream the library launches on (torch's current one)."""
 
@@ -96,6 +130,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--only", choices=["mixed", "fp64", "fp64_reform", "both"], default="both")
+    ap.add_argument("--no-scores", action="store_true", help="skip the batch-scores microbenchmark")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -269,6 +304,8 @@ def main() -> int:
                           f"locations ({dt:.1f} s wall)")
         print(f"[bench] cpu oracle: {S / dt:.1f} loc/s on {threads} threads", file=sys.stderr, flush=True)
 
+    scores = scores_microbench(lagp, torch, timer) if cfg == 2 and not args.no_scores else None
+
     # mixed-precision error report: every result of the mixed path against the float64 path
     # (whose designs and outputs are parity-tested against the float64 oracle)
     mixed_report = None
@@ -322,6 +359,8 @@ def main() -> int:
         "roofline": {"kernel": kname, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": unit, "frac": achieved / peak, "traffic": traffic, "per_unit": per_unit},
         "cpu_baseline": cpu,
+        # batch scores of one location's candidates (lagp_alc_scores), N' = 60,000
+        "scores_microbench": scores,
     }
     print(json.dumps(line), flush=True)
     return 0

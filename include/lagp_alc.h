@@ -141,6 +141,32 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
                                double *alc32, int32_t *status, int32_t *guard, void *stream);
 
 /*
+ * lagp_alc_scores -- the scores of a batch of candidates against one design,
+ * given K_j^{-1}: the per-step computation of the paper's GPU kernel (Fig. 3
+ * steps 2-6, with the sign of eq. piedef), over all candidates in one launch.
+ *
+ *   Xj [j x p]     design X_j             Kinv [j x j]  K_j^{-1}, K_j =
+ *                                                       K(X_j, X_j) + g I
+ *                                                       (symmetric: read by
+ *                                                       rows or by columns)
+ *   Xc [Nc x p]    candidates             x [p], h [j]  location and K(X_j, x)
+ *   d, g           lengthscale and nugget (finite, > 0)
+ *   precision      LAGP_FP64: float64 throughout; LAGP_MIXED: kernel values,
+ *                  the products with K_j^{-1} and the scores in float32 with
+ *                  float32 accumulation (K_j^{-1} and w = K_j^{-1} h are formed
+ *                  or rounded from the float64 inputs)
+ *   delta [Nc]     out: v_j(x) - v_{j+1}(x) for each candidate (eq. dxy),
+ *                  computed as (K(c,x) - k_c^T K_j^{-1} h)^2 / s_c with
+ *                  s_c = 1 + g - k_c^T K_j^{-1} k_c; -INFINITY where s_c <= 0
+ * The quadratic forms k_c^T K_j^{-1} k_c of 64-candidate tiles are products on
+ * the matrix cores (16x16x4 MFMA).  Supported: 1 <= j <= 128, p <= 16;
+ * Nc = 0 is a no-op.
+ */
+lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double *Kinv, const double *Xc,
+                            int64_t Nc, const double *x, const double *h, double d, double g,
+                            int32_t precision, double *delta, void *stream);
+
+/*
  * lagp_alc_predict -- the whole hot path: lagp_nn_pool into `pool`
  * (caller-allocated M x Np int32, left holding the pools), then
  * lagp_alc_from_pool.  Arguments as above.

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_FP64_REFORM, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
+__all__ = ["nn_pool", "alc_scores", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED, "fp64_reform": LAGP_FP64_REFORM}
@@ -66,6 +66,26 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
     _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
                                  workspace.data_ptr(), workspace.numel(), _stream(X.device)))
+    return out
+
+
+def alc_scores(Xj, Kinv, Xc, x, h, d: float, g: float, precision="fp64",
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Scores v_j(x) - v_{j+1}(x) (eq. dxy) of every candidate row of Xc against
+    the design Xj (j x p) at x, given K_j^{-1} (j x j) and h = K(X_j, x) (j):
+    the paper's per-step kernel over all candidates in one launch."""
+    L = _lib.load()
+    Xj, Kinv, Xc, x, h = (_f64(t, nme) for t, nme in ((Xj, "Xj"), (Kinv, "Kinv"), (Xc, "Xc"), (x, "x"), (h, "h")))
+    j, p = Xj.shape
+    if Kinv.shape != (j, j) or Xc.dim() != 2 or Xc.shape[1] != p or x.numel() != p or h.numel() != j:
+        raise ValueError("need Xj j x p, Kinv j x j, Xc Nc x p, x of p and h of j entries")
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
+    if out is None:
+        out = torch.empty(Xc.shape[0], dtype=torch.float64, device=Xc.device)
+    _lib.check(L.lagp_alc_scores(Xj.data_ptr(), j, p, Kinv.data_ptr(), Xc.data_ptr(), Xc.shape[0], x.data_ptr(),
+                                 h.data_ptr(), float(d), float(g), _prec(precision), out.data_ptr(),
+                                 _stream(Xc.device)))
     return out
 
 

@@ -114,6 +114,28 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
     return ok();
 }
 
+lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double *Kinv, const double *Xc,
+                            int64_t Nc, const double *x, const double *h, double d, double g,
+                            int32_t precision, double *delta, void *stream)
+{
+    if (precision != LAGP_FP64 && precision != LAGP_MIXED)
+        return fail(LAGP_EINVAL, "precision = %d is not LAGP_FP64 or LAGP_MIXED", precision);
+    if (j < 1) return fail(LAGP_EINVAL, "j = %d < 1", j);
+    if (j > lagp::kScoresJmax) return fail(LAGP_EUNSUPPORTED, "j = %d > %d", j, lagp::kScoresJmax);
+    if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
+    if (p > lagp::kMaxP) return fail(LAGP_EUNSUPPORTED, "p = %d > %d", p, lagp::kMaxP);
+    if (Nc < 0) return fail(LAGP_EINVAL, "Nc = %lld < 0", (long long)Nc);
+    if (!(d > 0.0) || !isfinite(d)) return fail(LAGP_EINVAL, "lengthscale d must be finite and > 0");
+    if (!(g > 0.0) || !isfinite(g)) return fail(LAGP_EINVAL, "nugget g must be finite and > 0");
+    if (Nc == 0) return ok();
+    if (!Xj || !Kinv || !Xc || !x || !h || !delta)
+        return fail(LAGP_EINVAL, "Xj, Kinv, Xc, x, h and delta must be non-NULL");
+    hipError_t e = lagp::launch_alc_scores(Xj, j, p, Kinv, Xc, Nc, x, h, d, g, precision == LAGP_MIXED, delta,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "alc_scores launch");
+    return ok();
+}
+
 lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                const double *XX, int64_t M, const int32_t *pool, int32_t Np,
                                int32_t n0, int32_t n, double d, double g, int32_t precision,

@@ -10,6 +10,7 @@ namespace lagp {
 int set_error(int code, const char *fmt, ...);
 
 constexpr int kMaxP = 16;  // largest input dimension any kernel accepts
+constexpr int kScoresJmax = 128;  // largest design of the batch-scores kernel
 
 // Per-location status codes (the LAGP_LOC_* values of the public header).
 constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4,
@@ -96,5 +97,11 @@ enum GpMode { kGpNll = 0, kGpBackward = 1, kGpMle = 2, kGpPredict = 3 };
 bool local_gp_supported(int n, int p);
 size_t local_gp_lds(int n, int p);
 hipError_t launch_local_gp(const GpArgs &a, int mode, hipStream_t st);
+
+// Batch scores of Nc candidates against one design of j points given K_j^{-1}
+// and h (lagp_alc_scores); float32 arithmetic when `mixed`.
+hipError_t launch_alc_scores(const double *Xj, int j, int p, const double *Kinv, const double *Xc, int64_t Nc,
+                             const double *x, const double *h, double d, double g, bool mixed, double *delta,
+                             hipStream_t st);
 
 }  // namespace lagp

@@ -179,3 +179,19 @@ def test_nn_pool_ws_validation(L):
     assert ws(FAKE, 100, 3, FAKE, 0, 10, FAKE, None, 0) == 0     # M = 0: no-op
     assert L.lagp_plan_workspace(100, 2, 10, 50, 20, None) == -1
     assert L.lagp_plan_workspace(100, 17, 10, 50, 20, ctypes.byref(nb)) == -4
+
+
+def test_scores_validation(L):
+    P = FAKE
+    sc = lambda j=4, p=2, Nc=10, d=0.5, g=1e-3, prec=0, delta=P: L.lagp_alc_scores(  # noqa: E731
+        P, j, p, P, P, Nc, P, P, d, g, prec, delta, None)
+    assert sc(j=0) == -1
+    assert sc(j=129) == -4
+    assert sc(p=0) == -1
+    assert sc(p=17) == -4
+    assert sc(Nc=-1) == -1
+    assert sc(d=0.0) == -1
+    assert sc(g=float("nan")) == -1
+    assert sc(prec=2) == -1
+    assert sc(delta=None) == -1
+    assert sc(Nc=0, delta=None) == 0     # no-op before any pointer is needed

@@ -131,3 +131,15 @@ def uniform(seed: int, N: int, p: int, M: int, *, resp=response_sines, noise: fl
     if noise > 0:
         Y = Y + r.normal(0.0, math.sqrt(noise), N)
     return np.ascontiguousarray(X), np.ascontiguousarray(Y), np.ascontiguousarray(XX)
+
+
+def scores_case(j: int, Nc: int, p: int, seed: int = 0, spread: float = 0.25) -> tuple:
+    """One location with a design of j points and Nc candidates (the shape of
+    the paper's ALC-in-isolation experiment, Sec. 4): x uniform on the unit
+    cube, the design uniform in the cube of half-width `spread` around x, the
+    candidates uniform on the unit cube.  Returns (Xj, Xc, x), float64."""
+    r = np.random.default_rng([SEED_ROOT, 100 + p, j, seed])
+    x = r.random(p)
+    Xj = x + spread * (2.0 * r.random((j, p)) - 1.0)
+    Xc = r.random((Nc, p))
+    return Xj, Xc, x
