@@ -31,8 +31,14 @@ namespace lagp {
 
 namespace {
 
-constexpr int kScBlock = 256;  // four waves, 16 candidates each per tile
-constexpr int kScTile = 64;    // candidates per workgroup tile
+// Threads per workgroup: 256 (four waves), or 512 where the LDS of K_j^{-1}
+// holds one workgroup per CU (float64, J >= 112), so that two waves per SIMD
+// share it.  Each wave scores 16 candidates per tile.
+template <typename T, int J>
+constexpr int sc_block()
+{
+    return sizeof(T) == 8 && J >= 112 ? 512 : 256;
+}
 
 template <typename T>
 struct ScMma;
@@ -112,8 +118,9 @@ __host__ __device__ constexpr size_t sc_lds(int J, int p)
 }
 
 template <typename T, int J>
-__global__ __launch_bounds__(kScBlock) void alc_scores_kernel(ScArgs a)
+__global__ __launch_bounds__((sc_block<T, J>())) void alc_scores_kernel(ScArgs a)
 {
+    constexpr int TB = sc_block<T, J>(), TILE = TB / 4;  // 16 candidates per wave
     constexpr int KK = J / 4, RT = J / 16;
     typedef typename ScMma<T>::acc acc_t;
     extern __shared__ double sc_dyn[];
@@ -124,7 +131,7 @@ __global__ __launch_bounds__(kScBlock) void alc_scores_kernel(ScArgs a)
     T *frag = w + J;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int t = tid; t < J * p; t += kScBlock) xj[t] = t < j * p ? a.Xj[t] : 0.0;
+    for (int t = tid; t < J * p; t += TB) xj[t] = t < j * p ? a.Xj[t] : 0.0;
     if (tid < p) xs[tid] = a.x[tid];
     // the loads below are unrolled so that many are in flight; indices outside
     // the j x j input are clamped to entry 0 and their values discarded
@@ -139,10 +146,11 @@ __global__ __launch_bounds__(kScBlock) void alc_scores_kernel(ScArgs a)
         }
         w[t] = (T)s;
     }
-    static_assert(J * J % kScBlock == 0 && J <= kScBlock, "staging shape");
+    static_assert(J <= TB, "one row of w per thread");
 #pragma unroll 8
-    for (int i = 0; i < J * J / kScBlock; i++) {
-        const int t = tid + i * kScBlock;
+    for (int i = 0; i < (J * J + TB - 1) / TB; i++) {
+        const int t = tid + i * TB;
+        if (t >= J * J) break;  // the last round only: J * J is a multiple of 64
         const int l = t & 63, blk = t >> 6;  // blk = rt * KK + kk
         const int rt = blk / KK, kk = blk - rt * KK;
         const int row = 16 * rt + (l & 15), col = perm<T>(kk, l >> 4);
@@ -154,9 +162,9 @@ __global__ __launch_bounds__(kScBlock) void alc_scores_kernel(ScArgs a)
 
     const T kappa = (T)(1.0 + a.g), nid = (T)(-1.0 / a.d);
     const int c16 = lane & 15, o = lane >> 4;
-    const int64_t ntiles = (a.Nc + kScTile - 1) / kScTile;
+    const int64_t ntiles = (a.Nc + TILE - 1) / TILE;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t cand = tile * kScTile + wv * 16 + c16;
+        const int64_t cand = tile * TILE + wv * 16 + c16;
         const bool valid = cand < a.Nc;
         double xc[kMaxP];
 #pragma unroll
@@ -249,25 +257,31 @@ hipError_t scores_setup()
     return hipSuccess;
 }
 
+template <typename T, int J>
+hipError_t launch_j(const ScArgs &a, hipStream_t st)
+{
+    constexpr int TB = sc_block<T, J>();
+    const size_t lds = sc_lds<T>(J, a.p);
+    int nb = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_of<T, J>(), TB, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t ntiles = (a.Nc + TB / 4 - 1) / (TB / 4);
+    const int64_t resident = (int64_t)cus * (nb > 0 ? nb : 1);
+    const dim3 grid((unsigned)(ntiles < resident ? ntiles : resident));
+    hipLaunchKernelGGL((alc_scores_kernel<T, J>), grid, dim3(TB), lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_t(const ScArgs &a, hipStream_t st)
 {
     const int J = (a.j + 15) & ~15;
-    const size_t lds = sc_lds<T>(J, a.p);
-    const void *k = scores_kernel<T>(J);
-    int nb = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kScBlock, lds);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const int64_t ntiles = (a.Nc + kScTile - 1) / kScTile;
-    const int64_t resident = (int64_t)cus * (nb > 0 ? nb : 1);
-    const dim3 grid((unsigned)(ntiles < resident ? ntiles : resident));
     switch (J) {
-#define LAGP_SC_CASE(JJ)                                                                   \
-    case JJ:                                                                               \
-        hipLaunchKernelGGL((alc_scores_kernel<T, JJ>), grid, dim3(kScBlock), lds, st, a); \
-        break;
+#define LAGP_SC_CASE(JJ)              \
+    case JJ:                          \
+        return launch_j<T, JJ>(a, st);
         LAGP_SC_CASE(16)
         LAGP_SC_CASE(32)
         LAGP_SC_CASE(48)
