@@ -16,6 +16,7 @@ precision; the other precision is timed beside it.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -226,11 +227,15 @@ def main() -> int:
     # ---- per-kernel timing with HIP events, same launches as in the step
     o = paths[precs[0]][1]
     pool = o["pool"]
-    # the NN variant the step runs: plans may stream a float32 copy of X
-    nn32 = plan_info is not None and ("chosen" not in plan_info or " x32" in plan_info.split("chosen")[-1])
-    nnws = torch.empty(W.N * W.p * 4 + 256, dtype=torch.uint8, device=dev) if nn32 else None
-    kms = {"nn_pool": timer.run(lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, f32_copy=nn32,
-                                                     workspace=nnws), args.steps)}
+    # the NN variant the step runs: plans may use the grid-pruned pools
+    nngrid = plan_info is not None and ("chosen" not in plan_info or "nn grid" in plan_info.split("chosen")[-1])
+    nnws = None
+    if nngrid:
+        nbytes = ctypes.c_size_t(0)
+        lagp._lib.check(lagp._lib.load().lagp_nn_pool_workspace(W.N, W.p, ctypes.byref(nbytes)))
+        nnws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    kms = {"nn_pool" + ("_grid" if nngrid else ""): timer.run(
+        lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, grid=nngrid, workspace=nnws), args.steps)}
     if cfg == 3:
         kms["alc_fp64_uneven"] = timer.run(
             lambda: lagp.alc_uneven_from_pool(X, Y, XX, pool, n0, n, d, g, n_per=n_per, Np_per=Np_per,

@@ -85,12 +85,16 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
 
 /*
  * lagp_nn_pool_workspace -- bytes of device workspace that lagp_nn_pool_ws
- *   needs: a float32 copy of X (N p 4 bytes, rounded up to 256).
- * lagp_nn_pool_ws -- lagp_nn_pool, streaming a float32 copy of X that it
- *   first writes into `workspace` (half the bytes per pass over the design);
- *   the float64 row is read only for the rows that the float32 screen keeps,
- *   so the pools are identical to lagp_nn_pool's.  workspace: device memory
- *   of at least lagp_nn_pool_workspace(N, p) bytes, 16-byte aligned (else
+ *   needs (about N (4 p + 8) bytes plus the cells: 1024 boxes and counters).
+ * lagp_nn_pool_ws -- lagp_nn_pool with the design bucketed, once per call,
+ *   into up to 1024 cells of a regular grid over its bounding box (a float32
+ *   copy of the rows cell by cell, their indices, the exact float64 bounding
+ *   box of each cell's rows, all in `workspace`).  Each location visits the
+ *   cells in order of the distance from x to their boxes and stops at the
+ *   first cell that is farther than its current N'-th nearest row: the pools
+ *   are identical to lagp_nn_pool's (pools of locations with a non-finite
+ *   coordinate are unspecified in both).  workspace: device memory of at
+ *   least lagp_nn_pool_workspace(N, p) bytes, 16-byte aligned (else
  *   LAGP_EWORKSPACE); calls that overlap must not share it.
  */
 lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, size_t *bytes);
@@ -227,11 +231,12 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  *   pool [M x Np_max] it fills; the workspace (16-byte aligned) must hold
  *   lagp_plan_workspace bytes.  Unless flags has LAGP_PLAN_NO_TUNE, the
  *   plan first times the variants of each tunable launch on these inputs,
- *   on at most their first 65,536 locations (locations per NN workgroup;
- *   whether the NN kernel streams the float32 copy of X; for each pool-size
+ *   on at most their first 65,536 locations (the NN variant: the grid-pruned
+ *   pools of lagp_nn_pool_ws, one, two or four locations per workgroup over
+ *   the whole design, or one over a float32 copy of it; for each pool-size
  *   schedule of the ALC kernel, how the chosen factor row reaches the
- *   lanes), and keeps the fastest; the chosen launches are then captured
- *   into a graph.  Creation
+ *   lanes), and keeps the fastest (the grid without tuning); the chosen
+ *   launches are then captured into a graph.  Creation
  *   runs the path on `stream` (several times when tuning), synchronises it,
  *   and finally enqueues one graph launch, whose results the outputs hold
  *   once `stream` has been synchronised.  M >= 1.  The buffers must stay

@@ -44,11 +44,13 @@ def version() -> str:
 
 
 def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None = None,
-            f32_copy: bool = False, workspace: torch.Tensor | None = None) -> torch.Tensor:
+            grid: bool = False, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """M x Np int32 pools: the Np nearest design rows of each location, sorted by (distance, index).
 
-    f32_copy: stream a float32 copy of X (lagp_nn_pool_ws; same pools) kept in
-    `workspace` (a uint8 device tensor, allocated here if None or too small)."""
+    grid: bucket the design into grid cells and stream, nearest cell first, only
+    the cells that can hold a pool member (lagp_nn_pool_ws; the same pools),
+    with the cells kept in `workspace` (a uint8 device tensor, allocated here if
+    None or too small)."""
     L = _lib.load()
     X, XX = _f64(X, "X"), _f64(XX, "XX")
     M, p = XX.shape
@@ -56,7 +58,7 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
         raise ValueError("X must be N x p with the p of XX")
     if out is None:
         out = torch.empty((M, Np), dtype=torch.int32, device=X.device)
-    if not f32_copy:
+    if not grid:
         _lib.check(L.lagp_nn_pool(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
                                   _stream(X.device)))
         return out

@@ -109,7 +109,7 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
     if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < lagp::nn_pool_workspace(N, p))
         return fail(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes",
                     lagp::nn_pool_workspace(N, p));
-    hipError_t e = lagp::launch_nn_pool(X, N, p, XX, M, Np, pool, (hipStream_t)stream, -1, (float *)workspace);
+    hipError_t e = lagp::launch_nn_grid(X, N, p, XX, M, Np, pool, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
     return ok();
 }

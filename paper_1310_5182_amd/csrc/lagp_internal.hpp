@@ -44,9 +44,13 @@ int nn_pool_cap(int Np);
 // Number of location groupings (2^g locations per workgroup) for pools of Np;
 // grouping < 0 picks the default.
 int nn_pool_groupings(int Np);
-// x32 (nullable): workspace of nn_pool_workspace(N, p) bytes for a float32
-// copy of X, which the stream then reads instead of X.
+// Workspace of the pool kernels that take one (nn_pool_workspace(N, p)
+// bytes): x32 below uses its first N p floats for a float32 copy of X, which
+// the stream then reads instead of X; launch_nn_grid uses all of it for the
+// grid of the design (cells, their boxes, the rows cell by cell) and prunes.
 size_t nn_pool_workspace(int64_t N, int p);
+hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
+                          void *ws, hipStream_t st);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
                           int32_t *pool, hipStream_t st, int grouping = -1, float *x32 = nullptr);
 

@@ -28,6 +28,19 @@
 // With a float32 copy of X (made once per call into caller workspace), the
 // stream reads half the bytes and the float64 row is fetched only for the rows
 // that pass the float32 test.
+//
+// Grid-pruned pools (with caller workspace).  The design is bucketed once per
+// call into C <= 1024 cells of a regular grid over its bounding box (the bits
+// of the cell index spread over the first dimensions) by a counting sort,
+// which leaves a float32 copy of the rows cell by cell, their design indices,
+// and the exact float64 bounding box of each cell's rows.  Each location
+// sorts the cells by the squared distance from x to their boxes and streams
+// the rows nearest cell first; a cell whose box is farther than the running
+// threshold (with a relative margin of 2^-20, far above the rounding of
+// either side) holds no row below it, and since the cells come in order of
+// that distance, the first such chunk ends the stream.  Every row that is
+// streamed goes through the same screen and exact key as above, so the pools
+// are identical to the unpruned ones.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -213,6 +226,31 @@ __device__ void bitonic_sort(uint64_t *keys, int32_t *idx)
     for (int k = 2; k <= SORTN; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < SORTN; i += kNnBlock) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t ka = keys[i], kb = keys[ixj];
+                    const int32_t ia = idx[i], ib = idx[ixj];
+                    const bool up = (i & k) == 0;
+                    const bool swap = up ? key_less(kb, ib, ka, ia) : key_less(ka, ia, kb, ib);
+                    if (swap) {
+                        keys[i] = kb;
+                        keys[ixj] = ka;
+                        idx[i] = ib;
+                        idx[ixj] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Ascending sort of n (a power of two <= the buffers) composite keys.
+__device__ void bitonic_sort_n(uint64_t *keys, int32_t *idx, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += kNnBlock) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const uint64_t ka = keys[i], kb = keys[ixj];
@@ -434,6 +472,472 @@ static hipError_t launch_cap(const double *X, const float *X32, int64_t N, int p
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ grid pruning
+constexpr int kGridCmax = 1024;  // cells
+constexpr int kGridParts = 256;  // workgroups of the bounding-box pass
+
+struct NnGrid {
+    float *x32;      // [N x p] float32 rows, cell by cell
+    int32_t *perm;   // [N] design index of each of those rows
+    int32_t *cid;    // [N] cell of each design row
+    int32_t *cnt;    // [C] rows per cell
+    int32_t *cur;    // [C] scatter cursors
+    int32_t *off;    // [C + 1] first row of each cell
+    double *box;     // [C][p][2] smallest and largest coordinate of each cell's rows
+    double *part;    // [kGridParts + 1][p][2] partial bounds, then the design's bounds
+    int C;
+    int bits[kMaxP];  // cell-index bits of each dimension
+};
+
+// Cells of 512 rows or more, so that a chunk of the stream spans few of them.
+static int grid_cells(int64_t N)
+{
+    int C = 1;
+    while (C < kGridCmax && (int64_t)C * 2 * 512 <= N) C *= 2;
+    return C;
+}
+
+static size_t align256(size_t v)
+{
+    return (v + 255) & ~(size_t)255;
+}
+
+size_t nn_pool_workspace(int64_t N, int p)
+{
+    return align256((size_t)N * p * 4) + 2 * align256((size_t)N * 4) + 3 * align256((kGridCmax + 1) * 4) +
+           align256((size_t)kGridCmax * p * 16) + align256((size_t)(kGridParts + 1) * p * 16);
+}
+
+static NnGrid grid_layout(void *ws, int64_t N, int p)
+{
+    NnGrid g{};
+    char *b = (char *)ws;
+    g.x32 = (float *)b;
+    b += align256((size_t)N * p * 4);
+    g.perm = (int32_t *)b;
+    b += align256((size_t)N * 4);
+    g.cid = (int32_t *)b;
+    b += align256((size_t)N * 4);
+    g.cnt = (int32_t *)b;
+    b += align256((kGridCmax + 1) * 4);
+    g.cur = (int32_t *)b;
+    b += align256((kGridCmax + 1) * 4);
+    g.off = (int32_t *)b;
+    b += align256((kGridCmax + 1) * 4);
+    g.box = (double *)b;
+    b += align256((size_t)kGridCmax * p * 16);
+    g.part = (double *)b;
+    g.C = grid_cells(N);
+    int cb = 0;
+    while ((1 << cb) < g.C) cb++;
+    for (int k = 0; k < kMaxP; k++) g.bits[k] = k < p ? cb / p + (k < cb % p ? 1 : 0) : 0;
+    return g;
+}
+
+// Partial bounds of the design per workgroup; non-finite coordinates widen
+// the bounds to the whole line.
+__global__ __launch_bounds__(256) void grid_minmax(const double *__restrict__ X, int64_t N, int p, NnGrid g)
+{
+    __shared__ double slo[256], shi[256];
+    double lo[kMaxP], hi[kMaxP];
+#pragma unroll
+    for (int k = 0; k < kMaxP; k++) {
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int k = 0; k < kMaxP; k++)
+            if (k < p) {
+                const double v = X[i * p + k];
+                lo[k] = isfinite(v) ? fmin(lo[k], v) : -INFINITY;
+                hi[k] = isfinite(v) ? fmax(hi[k], v) : INFINITY;
+            }
+#pragma unroll
+    for (int k = 0; k < kMaxP; k++) {
+        if (k >= p) break;
+        slo[threadIdx.x] = lo[k];
+        shi[threadIdx.x] = hi[k];
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (threadIdx.x < s2) {
+                slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s2]);
+                shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s2]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            g.part[((size_t)blockIdx.x * p + k) * 2] = slo[0];
+            g.part[((size_t)blockIdx.x * p + k) * 2 + 1] = shi[0];
+        }
+        __syncthreads();
+    }
+}
+
+// The design's bounds from the partials; cell counters cleared.
+__global__ __launch_bounds__(256) void grid_final(int p, int parts, NnGrid g)
+{
+    if (threadIdx.x < p) {
+        const int k = threadIdx.x;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < parts; b++) {
+            lo = fmin(lo, g.part[((size_t)b * p + k) * 2]);
+            hi = fmax(hi, g.part[((size_t)b * p + k) * 2 + 1]);
+        }
+        g.part[((size_t)kGridParts * p + k) * 2] = lo;
+        g.part[((size_t)kGridParts * p + k) * 2 + 1] = hi;
+    }
+    for (int c = threadIdx.x; c < kGridCmax + 1; c += 256) g.cnt[c] = 0;
+}
+
+__device__ __forceinline__ int grid_cell_of(const double *__restrict__ X, int64_t i, int p, const NnGrid &g)
+{
+    int cell = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxP; k++) {
+        if (k >= p) break;
+        const int b = g.bits[k];
+        if (b == 0) continue;
+        const double lo = g.part[((size_t)kGridParts * p + k) * 2], hi = g.part[((size_t)kGridParts * p + k) * 2 + 1];
+        const int s = 1 << b;
+        int q = 0;
+        const double v = X[i * p + k];
+        if (hi > lo && isfinite(hi - lo) && isfinite(v)) {
+            const double t = floor((v - lo) / (hi - lo) * s);
+            q = t < 0.0 ? 0 : t >= (double)s ? s - 1 : (int)t;
+        }
+        cell = (cell << b) | q;
+    }
+    return cell;
+}
+
+__global__ __launch_bounds__(256) void grid_count(const double *__restrict__ X, int64_t N, int p, NnGrid g)
+{
+    __shared__ int32_t h[kGridCmax];
+    for (int c = threadIdx.x; c < g.C; c += 256) h[c] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const int c = grid_cell_of(X, i, p, g);
+        g.cid[i] = c;
+        atomicAdd(&h[c], 1);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < g.C; c += 256)
+        if (h[c]) atomicAdd(&g.cnt[c], h[c]);
+}
+
+// Exclusive scan of the counts (one workgroup, four cells per thread).
+__global__ __launch_bounds__(256) void grid_scan(int64_t N, NnGrid g)
+{
+    __shared__ int32_t part[256];
+    const int t = threadIdx.x;
+    int32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int c = 4 * t + q;
+        v[q] = c < g.C ? g.cnt[c] : 0;
+        sum += v[q];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t add = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int c = 4 * t + q;
+        if (c < g.C) {
+            g.off[c] = run;
+            g.cur[c] = run;
+        }
+        run += v[q];
+    }
+    if (t == 0) g.off[g.C] = (int32_t)N;
+}
+
+__global__ __launch_bounds__(256) void grid_scatter(const double *__restrict__ X, int64_t N, int p, NnGrid g)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const int pos = atomicAdd(&g.cur[g.cid[i]], 1);
+        g.perm[pos] = (int32_t)i;
+        for (int k = 0; k < p; k++) g.x32[(size_t)pos * p + k] = (float)X[i * p + k];
+    }
+}
+
+// Exact float64 bounds of each cell's rows (one workgroup per cell; an empty
+// cell gets +inf / -inf, which puts it out of reach).
+__global__ __launch_bounds__(256) void grid_box(const double *__restrict__ X, int p, NnGrid g)
+{
+    __shared__ double slo[256], shi[256];
+    const int c = blockIdx.x;
+    const int r0 = g.off[c], r1 = g.off[c + 1];
+    for (int k = 0; k < p; k++) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int r = r0 + threadIdx.x; r < r1; r += 256) {
+            const double v = X[(int64_t)g.perm[r] * p + k];
+            lo = isfinite(v) ? fmin(lo, v) : -INFINITY;
+            hi = isfinite(v) ? fmax(hi, v) : INFINITY;
+        }
+        slo[threadIdx.x] = lo;
+        shi[threadIdx.x] = hi;
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (threadIdx.x < s2) {
+                slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s2]);
+                shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s2]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            g.box[((size_t)c * p + k) * 2] = slo[0];
+            g.box[((size_t)c * p + k) * 2 + 1] = shi[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Largest rank r >= r0 with pre[r] <= v, for pre[r0] <= v < pre[C] (pre
+// ascending): a forward walk, short because cells hold 512 rows or more.
+__device__ __forceinline__ int rank_from(const int32_t *pre, int r0, int64_t v)
+{
+    while (pre[r0 + 1] <= v) r0++;
+    return r0;
+}
+
+// One location per workgroup, rows streamed cell by cell (nearest first).
+template <int CAP, int SORTN, int PF>
+__global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restrict__ X, int64_t N,
+                                                           const double *__restrict__ XX, int64_t M, int Np,
+                                                           int32_t *__restrict__ pool, NnGrid gr)
+{
+    static_assert(CAP >= SORTN + kNnChunk && CAP >= kGridCmax, "room for one chunk above the kept set");
+    constexpr int p = PF;
+    constexpr float kU = 5.9604645e-8f;  // 2^-24
+    constexpr double kMargin = 1.0 - 1.0 / (1 << 20);
+    __shared__ uint64_t keys[CAP];
+    __shared__ int32_t idxs[CAP];
+    __shared__ double xs[PF];
+    __shared__ NnGroup grp;
+    __shared__ NnShared S;
+    __shared__ int32_t pre[kGridCmax + 1];  // rows in the cells of rank < r
+    __shared__ int16_t cellr[kGridCmax];    // cell of rank r (nearest first)
+    __shared__ float mindr[kGridCmax];      // <= squared distance from x to the box of that cell
+
+    const int tid = threadIdx.x, C = gr.C;
+    const int64_t m = blockIdx.x;
+    if (tid < PF) xs[tid] = XX[m * p + tid];
+    if (tid == 0) {
+        grp.count = 0;
+        grp.thr_k = ~0ull;
+        grp.thr_i = INT32_MAX;
+    }
+    __syncthreads();
+    float xf[PF], lmax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+        xf[k] = (float)xs[k];
+        lmax = fmaxf(lmax, fabsf(xf[k]));
+    }
+    constexpr float kSlope = 1.0f - 2.0f * PF * kU;
+    constexpr float kConst = 40.0f * PF * kU;
+
+    // ---- cells in order of the squared distance from x to their boxes
+    for (int c = tid; c < C; c += kNnBlock) {
+        double sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < PF; k++) {
+            const double lo = gr.box[((size_t)c * p + k) * 2], hi = gr.box[((size_t)c * p + k) * 2 + 1];
+            const double gap = fmax(fmax(lo - xs[k], xs[k] - hi), 0.0);
+            sd = fma(gap, gap, sd);
+        }
+        keys[c] = __builtin_bit_cast(uint64_t, sd);  // >= 0 (or NaN for a NaN location: last)
+        idxs[c] = c;
+    }
+    __syncthreads();
+    bitonic_sort_n(keys, idxs, C);
+    int32_t csum[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int r = 4 * tid + q;
+        csum[q] = 0;
+        if (r < C) {
+            const int c = idxs[r];
+            cellr[r] = (int16_t)c;
+            const double md = __builtin_bit_cast(double, keys[r]);
+            float f = (float)md;  // rounded down to a float below md
+            if (!(md >= 0.0)) f = INFINITY;
+            else if ((double)f > md) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) - 1u);
+            mindr[r] = f;
+            csum[q] = gr.off[c + 1] - gr.off[c];
+        }
+        tot += csum[q];
+    }
+    // exclusive scan of the cell sizes in rank order: pre[r]
+    S.hist[tid] = (uint32_t)tot;
+    __syncthreads();
+    for (int o = 1; o < kNnBlock; o <<= 1) {
+        const uint32_t add = tid >= o ? S.hist[tid - o] : 0u;
+        __syncthreads();
+        S.hist[tid] += add;
+        __syncthreads();
+    }
+    int32_t run = (int32_t)S.hist[tid] - tot;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int r = 4 * tid + q;
+        if (r < C) pre[r] = run;
+        run += csum[q];
+    }
+    if (tid == 0) pre[C] = (int32_t)N;
+    __syncthreads();
+
+    // ---- the rows, nearest cell first
+    int rc = 0;  // rank of the cell that holds row vb
+    for (int64_t vb = 0; vb < N; vb += kNnChunk) {
+        const uint64_t tk = grp.thr_k;
+        const int32_t ti = grp.thr_i;
+        const double td = tk == ~0ull ? INFINITY : __builtin_bit_cast(double, tk);
+        float tf;
+        {
+            const float f = (float)td;
+            tf = (double)f < td ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
+        }
+        // every remaining cell is at least as far as the one holding row vb
+        rc = rank_from(pre, rc, vb);
+        if ((double)mindr[rc] * kMargin > td) break;
+        int r = rc;  // the items' rows come in increasing order
+        uint32_t pend = 0;
+#pragma unroll
+        for (int it = 0; it < kNnItems; it++) {
+            const int64_t v = vb + it * kNnBlock + tid;
+            if (v < N) {
+                r = rank_from(pre, r, v);
+                if ((double)mindr[r] * kMargin <= td) {
+                    const int64_t row = gr.off[cellr[r]] + (v - pre[r]);
+                    float xrf[PF], rmax = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < PF; k++) {
+                        xrf[k] = gr.x32[row * PF + k];
+                        rmax = fmaxf(rmax, fabsf(xrf[k]));
+                    }
+                    float d32 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < PF; k++) {
+                        const float t = xrf[k] - xf[k];
+                        d32 = fmaf(t, t, d32);
+                    }
+                    const float B = fmaxf(rmax, lmax);
+                    if (d32 * kSlope - kConst * B * B < tf) {
+                        const int32_t i = gr.perm[row];
+                        const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
+                        const uint64_t key = __builtin_bit_cast(uint64_t, sd);
+                        if (key_less(key, i, tk, ti)) {
+                            const int pos = atomicAdd(&grp.count, 1);
+                            if (pos < CAP) {
+                                keys[pos] = key;
+                                idxs[pos] = i;
+                            } else {
+                                pend |= 1u << it;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // a full buffer: as in nn_pool_kernel (the count changes only after a barrier)
+        if (grp.count > CAP) {
+            select_keep(keys, idxs, S, grp, CAP, Np);
+            const uint64_t nk = grp.thr_k;
+            const int32_t ni = grp.thr_i;
+#pragma unroll
+            for (int it = 0; it < kNnItems; it++) {
+                if ((pend >> it) & 1u) {
+                    const int64_t v = vb + it * kNnBlock + tid;
+                    const int rr = rank_from(pre, rc, v);
+                    const int32_t i = gr.perm[gr.off[cellr[rr]] + (v - pre[rr])];
+                    const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
+                    const uint64_t key = __builtin_bit_cast(uint64_t, sd);
+                    if (key_less(key, i, nk, ni)) {
+                        const int pos = atomicAdd(&grp.count, 1);
+                        keys[pos] = key;
+                        idxs[pos] = i;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (grp.count > Np) select_keep(keys, idxs, S, grp, grp.count, Np);
+    for (int i = Np + tid; i < SORTN; i += kNnBlock) {
+        keys[i] = ~0ull;
+        idxs[i] = INT32_MAX;
+    }
+    __syncthreads();
+    bitonic_sort<SORTN>(keys, idxs);
+    for (int r = tid; r < Np; r += kNnBlock) pool[m * Np + r] = idxs[r];
+}
+
+template <int CAP, int SORTN>
+static hipError_t launch_grid_cap(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
+                                  int32_t *pool, const NnGrid &g, hipStream_t st)
+{
+    switch (p) {
+#define LAGP_NG_CASE(P)                                                                                       \
+    case P:                                                                                                   \
+        hipLaunchKernelGGL((nn_grid_kernel<CAP, SORTN, P>), dim3((unsigned)M), dim3(kNnBlock), 0, st, X, N, XX, \
+                           M, Np, pool, g);                                                                   \
+        break;
+        LAGP_NG_CASE(1)
+        LAGP_NG_CASE(2)
+        LAGP_NG_CASE(3)
+        LAGP_NG_CASE(4)
+        LAGP_NG_CASE(5)
+        LAGP_NG_CASE(6)
+        LAGP_NG_CASE(7)
+        LAGP_NG_CASE(8)
+        LAGP_NG_CASE(9)
+        LAGP_NG_CASE(10)
+        LAGP_NG_CASE(11)
+        LAGP_NG_CASE(12)
+        LAGP_NG_CASE(13)
+        LAGP_NG_CASE(14)
+        LAGP_NG_CASE(15)
+        LAGP_NG_CASE(16)
+#undef LAGP_NG_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
+                          void *ws, hipStream_t st)
+{
+    if (M == 0) return hipSuccess;
+    if (p < 1 || p > kMaxP || !ws) return hipErrorInvalidValue;
+    const NnGrid g = grid_layout(ws, N, p);
+    const int64_t nb = (N + 255) / 256;
+    const unsigned rows_grid = (unsigned)(nb < 4096 ? nb : 4096);
+    const unsigned parts = (unsigned)(nb < kGridParts ? nb : kGridParts);
+    hipLaunchKernelGGL(grid_minmax, dim3(parts), dim3(256), 0, st, X, N, p, g);
+    hipLaunchKernelGGL(grid_final, dim3(1), dim3(256), 0, st, p, (int)parts, g);
+    hipLaunchKernelGGL(grid_count, dim3(rows_grid), dim3(256), 0, st, X, N, p, g);
+    hipLaunchKernelGGL(grid_scan, dim3(1), dim3(256), 0, st, N, g);
+    hipLaunchKernelGGL(grid_scatter, dim3(rows_grid), dim3(256), 0, st, X, N, p, g);
+    hipLaunchKernelGGL(grid_box, dim3((unsigned)g.C), dim3(256), 0, st, X, p, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (Np <= 512) return launch_grid_cap<2048, 512>(X, N, p, XX, M, Np, pool, g, st);
+    if (Np <= 1024) return launch_grid_cap<2048, 1024>(X, N, p, XX, M, Np, pool, g, st);
+    if (Np <= kNnMaxNp) return launch_grid_cap<3072, 2048>(X, N, p, XX, M, Np, pool, g, st);
+    return hipErrorInvalidValue;
+}
+
 int nn_pool_cap(int Np)
 {
     if (Np <= 512) return 2048;
@@ -457,11 +961,6 @@ __global__ void nn_to_f32(const double *__restrict__ X, float *__restrict__ X32,
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         X32[i] = (float)X[i];
-}
-
-size_t nn_pool_workspace(int64_t N, int p)
-{
-    return ((size_t)N * p * sizeof(float) + 255) & ~(size_t)255;
 }
 
 int nn_pool_groupings(int Np)

@@ -1,10 +1,10 @@
 // Graph-captured, autotuned runs of the whole path (lagp_plan_* of lagp_alc.h).
 //
 // A plan binds one problem's buffers, picks the fastest variant of each
-// tunable launch by timing it on those very inputs (locations per NN
-// workgroup and whether the NN kernel streams a float32 copy of X; for every
-// pool-size schedule of the ALC kernel, how the chosen factor row is
-// broadcast), and captures the chosen launches - NN pools,
+// tunable launch by timing it on those very inputs (the NN variant: locations
+// per workgroup over the whole design, the stream of a float32 copy of it, or
+// the grid-pruned stream; for every pool-size schedule of the ALC kernel, how
+// the chosen factor row is broadcast), and captures the chosen launches - NN pools,
 // queue planning, persistent ALC workgroups - into one HIP graph.  Replaying
 // the graph costs one launch call; every node is a kernel (no memset nodes).
 #include <hip/hip_runtime.h>
@@ -23,9 +23,9 @@ struct lagp_plan_s {
     int32_t *pool;
     void *ws;         // the ALC kernels' part of the workspace
     size_t ws_bytes;
-    float *x32;       // then the float32 copy of X that the NN kernel may stream
-    int grouping = -1;  // NN locations per workgroup: 2^grouping
-    bool use32 = true;  // the NN kernel streams x32
+    void *nnws;       // then the NN kernels' workspace
+    int grouping = -1;  // NN variant: 2^grouping locations per workgroup, kNnF32 or kNnGrid
+
     int bcast = -1;     // ALC broadcast mask
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -35,17 +35,32 @@ struct lagp_plan_s {
 namespace lagp {
 
 // Enqueue the whole path with the given variants.
-static hipError_t run_path(const lagp_plan_s &P, int grouping, bool use32, int bcast, hipStream_t st)
+// NN variants beyond the location groupings 0 .. nn_pool_groupings(Np) - 1
+constexpr int kNnF32 = 100, kNnGrid = 101;
+
+static const char *nn_name(int v, char *buf, size_t n)
 {
-    hipError_t e = launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, grouping,
-                                  use32 ? P.x32 : nullptr);
+    if (v == kNnGrid)
+        snprintf(buf, n, "grid");
+    else if (v == kNnF32)
+        snprintf(buf, n, "g=1 x32");
+    else
+        snprintf(buf, n, "g=%d", 1 << v);
+    return buf;
+}
+
+static hipError_t run_path(const lagp_plan_s &P, int nnv, int bcast, hipStream_t st)
+{
+    hipError_t e = nnv == kNnGrid ? launch_nn_grid(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, P.nnws, st)
+                   : nnv == kNnF32
+                       ? launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, 0, (float *)P.nnws)
+                       : launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, nnv, nullptr);
     if (e != hipSuccess) return e;
     return launch_alc_uneven(P.a, P.n_per, P.Np_per, P.sel_off, P.ws, P.ws_bytes, st, bcast);
 }
 
 // Milliseconds of one run (the best of `reps`, after one untimed run).
-static hipError_t time_path(const lagp_plan_s &P, int grouping, bool use32, int bcast, hipStream_t st, int reps,
-                            float *ms)
+static hipError_t time_path(const lagp_plan_s &P, int nnv, int bcast, hipStream_t st, int reps, float *ms)
 {
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -55,10 +70,10 @@ static hipError_t time_path(const lagp_plan_s &P, int grouping, bool use32, int 
         return e;
     }
     float best = 1e30f;
-    e = run_path(P, grouping, use32, bcast, st);
+    e = run_path(P, nnv, bcast, st);
     for (int r = 0; e == hipSuccess && r < reps; r++) {
         if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        if ((e = run_path(P, grouping, use32, bcast, st)) != hipSuccess) break;
+        if ((e = run_path(P, nnv, bcast, st)) != hipSuccess) break;
         if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float t = 0.0f;
@@ -71,8 +86,7 @@ static hipError_t time_path(const lagp_plan_s &P, int grouping, bool use32, int 
     return e;
 }
 
-// Coordinate search: the NN variant (grouping, float32 copy) first, then each
-// schedule's broadcast bit.
+// Coordinate search: the NN variant first, then each schedule's broadcast bit.
 // The timing runs use at most the first kTuneLocations locations (their
 // outputs are overwritten later), so that tuning stays short for large M.
 constexpr int64_t kTuneLocations = 65536;
@@ -81,33 +95,31 @@ static hipError_t tune(lagp_plan_s &Pfull, hipStream_t st)
 {
     lagp_plan_s P = Pfull;
     if (P.a.M > kTuneLocations) P.a.M = kTuneLocations;
-    char line[160];
+    char line[160], nm[32];
     float best = 0.0f;
-    int g_best = 0, mask = 0x7;
-    bool u_best = true;
-    hipError_t e = time_path(P, 0, true, mask, st, 2, &best);
+    int v_best = kNnGrid, mask = 0x7;
+    hipError_t e = time_path(P, kNnGrid, mask, st, 2, &best);
     if (e != hipSuccess) return e;
-    snprintf(line, sizeof line, "nn g=1 x32 alc mask=%x: %.3f ms", mask, best);
+    snprintf(line, sizeof line, "nn grid alc mask=%x: %.3f ms", mask, best);
     P.info += line;
-    for (int g = 0; g < nn_pool_groupings(P.a.Np); g++) {
-        for (int u = 1; u >= 0; u--) {
-            if (g == 0 && u == 1) continue;  // timed above
-            float t = 0.0f;
-            if ((e = time_path(P, g, u == 1, mask, st, 2, &t)) != hipSuccess) return e;
-            snprintf(line, sizeof line, "; nn g=%d%s: %.3f ms", 1 << g, u ? " x32" : "", t);
-            P.info += line;
-            if (t < best) {
-                best = t;
-                g_best = g;
-                u_best = u == 1;
-            }
+    int variants[8], nv = 0;
+    for (int g = 0; g < nn_pool_groupings(P.a.Np); g++) variants[nv++] = g;
+    variants[nv++] = kNnF32;
+    for (int q = 0; q < nv; q++) {
+        float t = 0.0f;
+        if ((e = time_path(P, variants[q], mask, st, 2, &t)) != hipSuccess) return e;
+        snprintf(line, sizeof line, "; nn %s: %.3f ms", nn_name(variants[q], nm, sizeof nm), t);
+        P.info += line;
+        if (t < best) {
+            best = t;
+            v_best = variants[q];
         }
     }
     const int top = alc_inc_schedule(P.a.Np);
     for (int b = 0; b <= top; b++) {
         const int m2 = mask ^ (1 << b);
         float t = 0.0f;
-        if ((e = time_path(P, g_best, u_best, m2, st, 2, &t)) != hipSuccess) return e;
+        if ((e = time_path(P, v_best, m2, st, 2, &t)) != hipSuccess) return e;
         snprintf(line, sizeof line, "; alc mask=%x: %.3f ms", m2, t);
         P.info += line;
         if (t < best) {
@@ -115,11 +127,10 @@ static hipError_t tune(lagp_plan_s &Pfull, hipStream_t st)
             mask = m2;
         }
     }
-    Pfull.grouping = g_best;
-    Pfull.use32 = u_best;
+    Pfull.grouping = v_best;
     Pfull.bcast = mask;
-    snprintf(line, sizeof line, "; chosen nn g=%d%s alc mask=%x (%.3f ms on %lld locations)", 1 << g_best,
-             u_best ? " x32" : "", mask, best, (long long)P.a.M);
+    snprintf(line, sizeof line, "; chosen nn %s alc mask=%x (%.3f ms on %lld locations)",
+             nn_name(v_best, nm, sizeof nm), mask, best, (long long)P.a.M);
     Pfull.info = P.info + line;
     return hipSuccess;
 }
@@ -182,10 +193,11 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     P->pool = pool;
     P->ws = workspace;
     P->ws_bytes = need_alc;
-    P->x32 = (float *)((char *)workspace + need_alc);
+    P->nnws = (char *)workspace + need_alc;
     hipStream_t st = (hipStream_t)stream;
+    P->grouping = lagp::kNnGrid;  // the default NN variant
     if (flags & LAGP_PLAN_NO_TUNE) {
-        P->info = "defaults (not tuned)";
+        P->info = "defaults (not tuned: nn grid)";
     } else if ((e = lagp::tune(*P, st)) != hipSuccess) {
         delete P;
         return plan_fail(LAGP_EHIP, "autotuning run", e);
@@ -198,7 +210,7 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     }
     if ((e = hipStreamSynchronize(st)) == hipSuccess &&
         (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
-        hipError_t run = lagp::run_path(*P, P->grouping, P->use32, P->bcast, cs);
+        hipError_t run = lagp::run_path(*P, P->grouping, P->bcast, cs);
         e = hipStreamEndCapture(cs, &P->graph);
         if (run != hipSuccess) e = run;
     }

@@ -168,13 +168,15 @@ def test_nn_pool_ws_validation(L):
     assert L.lagp_nn_pool_workspace(100, 17, ctypes.byref(nb)) == -4
     assert L.lagp_nn_pool_workspace(0, 2, ctypes.byref(nb)) == -1
     assert L.lagp_nn_pool_workspace(100, 3, ctypes.byref(nb)) == 0
-    assert nb.value == 1280                                       # 100 * 3 * 4 bytes, rounded up to 256
+    need = nb.value
+    assert need >= 100 * (3 * 4 + 8)                              # rows cell by cell, indices, cells
+    assert L.lagp_nn_pool_workspace(200, 3, ctypes.byref(nb)) == 0 and nb.value > need
     ws = lambda *a: L.lagp_nn_pool_ws(*a, None)                   # noqa: E731
-    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE, 1279) == -2  # too small
-    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE + 4, 4096) == -2  # not 16-byte aligned
-    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, None, 4096) == -2
-    assert ws(FAKE, 100, 3, FAKE, 3, 101, FAKE, FAKE, 4096) == -1
-    assert ws(FAKE, 100, 3, FAKE, 3, 10, None, FAKE, 4096) == -1
+    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE, need - 1) == -2  # too small
+    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE + 4, need) == -2  # not 16-byte aligned
+    assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, None, need) == -2
+    assert ws(FAKE, 100, 3, FAKE, 3, 101, FAKE, FAKE, need) == -1
+    assert ws(FAKE, 100, 3, FAKE, 3, 10, None, FAKE, need) == -1
     assert ws(FAKE, 10**6, 3, FAKE, 3, 5000, FAKE, FAKE, 1 << 30) == -4
     assert ws(FAKE, 100, 3, FAKE, 0, 10, FAKE, None, 0) == 0     # M = 0: no-op
     assert L.lagp_plan_workspace(100, 2, 10, 50, 20, None) == -1

@@ -88,11 +88,11 @@ def test_nn_pool_bit_exact(lagp, orc, case):
         import torch
 
         got = lagp.nn_pool(dev(W.X), dev(W.XX), npl)
-        got32 = lagp.nn_pool(dev(W.X), dev(W.XX), npl, f32_copy=True)  # streams a float32 copy of X
+        got32 = lagp.nn_pool(dev(W.X), dev(W.XX), npl, grid=True)  # grid-pruned stream
         torch.cuda.synchronize()
         want = orc.nn_pool(W.X, W.XX, npl)
         assert np.array_equal(got.cpu().numpy(), want), (case, npl)
-        assert np.array_equal(got32.cpu().numpy(), want), (case, npl, "f32_copy")
+        assert np.array_equal(got32.cpu().numpy(), want), (case, npl, "grid")
 
 
 # ---------------------------------------------------------------- ALC designs
