@@ -232,7 +232,7 @@ def main() -> int:
     nnws = None
     if nngrid:
         nbytes = ctypes.c_size_t(0)
-        lagp._lib.check(lagp._lib.load().lagp_nn_pool_workspace(W.N, W.p, ctypes.byref(nbytes)))
+        lagp._lib.check(lagp._lib.load().lagp_nn_pool_workspace(W.N, W.p, M, ctypes.byref(nbytes)))
         nnws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     kms = {"nn_pool" + ("_grid" if nngrid else ""): timer.run(
         lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, grid=nngrid, workspace=nnws), args.steps)}

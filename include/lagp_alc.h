@@ -85,11 +85,14 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
 
 /*
  * lagp_nn_pool_workspace -- bytes of device workspace that lagp_nn_pool_ws
- *   needs (about N (4 p + 8) bytes plus the cells: 1024 boxes and counters).
+ *   needs for N design rows and M locations (about N (4 p + 8) + 8 M bytes
+ *   plus the cells: 1024 boxes and counters).
  * lagp_nn_pool_ws -- lagp_nn_pool with the design bucketed, once per call,
  *   into up to 1024 cells of a regular grid over its bounding box (a float32
  *   copy of the rows cell by cell, their indices, the exact float64 bounding
- *   box of each cell's rows, all in `workspace`).  Each location visits the
+ *   box of each cell's rows, all in `workspace`; the locations are taken in
+ *   cell order, each XCD of the GPU a contiguous run of them, so that the
+ *   workgroups sharing an L2 read mostly the same cells).  Each location visits the
  *   cells in order of the distance from x to their boxes and stops at the
  *   first cell that is farther than its current N'-th nearest row: the pools
  *   are identical to lagp_nn_pool's (pools of locations with a non-finite
@@ -97,7 +100,7 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
  *   least lagp_nn_pool_workspace(N, p) bytes, 16-byte aligned (else
  *   LAGP_EWORKSPACE); calls that overlap must not share it.
  */
-lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, size_t *bytes);
+lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, int64_t M, size_t *bytes);
 lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
                             int32_t Np, int32_t *pool, void *workspace, size_t workspace_bytes,
                             void *stream);

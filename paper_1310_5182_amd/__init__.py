@@ -63,7 +63,7 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
                                   _stream(X.device)))
         return out
     nbytes = ctypes.c_size_t(0)
-    _lib.check(L.lagp_nn_pool_workspace(X.shape[0], p, ctypes.byref(nbytes)))
+    _lib.check(L.lagp_nn_pool_workspace(X.shape[0], p, M, ctypes.byref(nbytes)))
     if workspace is None or workspace.numel() < nbytes.value:
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
     _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),

@@ -63,7 +63,7 @@ def load():
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.lagp_nn_pool.argtypes = [P, i64, i32, P, i64, i32, P, P]
     L.lagp_nn_pool.restype = i32
-    L.lagp_nn_pool_workspace.argtypes = [i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_nn_pool_workspace.argtypes = [i64, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_nn_pool_workspace.restype = i32
     L.lagp_nn_pool_ws.argtypes = [P, i64, i32, P, i64, i32, P, P, ctypes.c_size_t, P]
     L.lagp_nn_pool_ws.restype = i32

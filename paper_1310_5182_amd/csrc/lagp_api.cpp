@@ -87,13 +87,14 @@ lagp_status lagp_nn_pool(const double *X, int64_t N, int32_t p, const double *XX
     return ok();
 }
 
-lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, size_t *bytes)
+lagp_status lagp_nn_pool_workspace(int64_t N, int32_t p, int64_t M, size_t *bytes)
 {
     if (!bytes) return fail(LAGP_EINVAL, "bytes must be non-NULL");
+    if (M < 0) return fail(LAGP_EINVAL, "M = %lld < 0", (long long)M);
     if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
     if (p > lagp::kMaxP) return fail(LAGP_EUNSUPPORTED, "p = %d > %d", p, lagp::kMaxP);
     if (N < 1 || N >= (int64_t)1 << 31) return fail(LAGP_EINVAL, "N = %lld outside [1, 2^31)", (long long)N);
-    *bytes = lagp::nn_pool_workspace(N, p);
+    *bytes = lagp::nn_pool_workspace(N, p, M);
     return ok();
 }
 
@@ -106,9 +107,9 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
     if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
     if (lagp::nn_pool_cap(Np) == 0) return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", Np);
     if (M == 0) return ok();
-    if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < lagp::nn_pool_workspace(N, p))
+    if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < lagp::nn_pool_workspace(N, p, M))
         return fail(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes",
-                    lagp::nn_pool_workspace(N, p));
+                    lagp::nn_pool_workspace(N, p, M));
     hipError_t e = lagp::launch_nn_grid(X, N, p, XX, M, Np, pool, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
     return ok();

@@ -48,7 +48,7 @@ int nn_pool_groupings(int Np);
 // bytes): x32 below uses its first N p floats for a float32 copy of X, which
 // the stream then reads instead of X; launch_nn_grid uses all of it for the
 // grid of the design (cells, their boxes, the rows cell by cell) and prunes.
-size_t nn_pool_workspace(int64_t N, int p);
+size_t nn_pool_workspace(int64_t N, int p, int64_t M);
 hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
                           void *ws, hipStream_t st);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,

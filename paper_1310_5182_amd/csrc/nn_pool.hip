@@ -40,7 +40,11 @@
 // either side) holds no row below it, and since the cells come in order of
 // that distance, the first such chunk ends the stream.  Every row that is
 // streamed goes through the same screen and exact key as above, so the pools
-// are identical to the unpruned ones.
+// are identical to the unpruned ones.  The locations are bucketed into the
+// same cells, and the workgroups of each XCD (the dispatcher hands out
+// consecutive workgroups to the XCDs in turn) take a contiguous run of them in
+// cell order, so that the workgroups resident on one XCD read mostly the same
+// cells through its L2.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -485,6 +489,9 @@ struct NnGrid {
     int32_t *off;    // [C + 1] first row of each cell
     double *box;     // [C][p][2] smallest and largest coordinate of each cell's rows
     double *part;    // [kGridParts + 1][p][2] partial bounds, then the design's bounds
+    int32_t *lcid;   // [M] cell of each location
+    int32_t *lcnt, *lcur, *loff;  // [C], [C], [C + 1] as above, for the locations
+    int32_t *lperm;  // [M] locations in cell order
     int C;
     int bits[kMaxP];  // cell-index bits of each dimension
 };
@@ -502,13 +509,14 @@ static size_t align256(size_t v)
     return (v + 255) & ~(size_t)255;
 }
 
-size_t nn_pool_workspace(int64_t N, int p)
+size_t nn_pool_workspace(int64_t N, int p, int64_t M)
 {
     return align256((size_t)N * p * 4) + 2 * align256((size_t)N * 4) + 3 * align256((kGridCmax + 1) * 4) +
-           align256((size_t)kGridCmax * p * 16) + align256((size_t)(kGridParts + 1) * p * 16);
+           align256((size_t)kGridCmax * p * 16) + align256((size_t)(kGridParts + 1) * p * 16) +
+           2 * align256((size_t)M * 4) + 3 * align256((kGridCmax + 1) * 4);
 }
 
-static NnGrid grid_layout(void *ws, int64_t N, int p)
+static NnGrid grid_layout(void *ws, int64_t N, int p, int64_t M)
 {
     NnGrid g{};
     char *b = (char *)ws;
@@ -527,6 +535,16 @@ static NnGrid grid_layout(void *ws, int64_t N, int p)
     g.box = (double *)b;
     b += align256((size_t)kGridCmax * p * 16);
     g.part = (double *)b;
+    b += align256((size_t)(kGridParts + 1) * p * 16);
+    g.lcid = (int32_t *)b;
+    b += align256((size_t)M * 4);
+    g.lperm = (int32_t *)b;
+    b += align256((size_t)M * 4);
+    g.lcnt = (int32_t *)b;
+    b += align256((kGridCmax + 1) * 4);
+    g.lcur = (int32_t *)b;
+    b += align256((kGridCmax + 1) * 4);
+    g.loff = (int32_t *)b;
     g.C = grid_cells(N);
     int cb = 0;
     while ((1 << cb) < g.C) cb++;
@@ -587,7 +605,10 @@ __global__ __launch_bounds__(256) void grid_final(int p, int parts, NnGrid g)
         g.part[((size_t)kGridParts * p + k) * 2] = lo;
         g.part[((size_t)kGridParts * p + k) * 2 + 1] = hi;
     }
-    for (int c = threadIdx.x; c < kGridCmax + 1; c += 256) g.cnt[c] = 0;
+    for (int c = threadIdx.x; c < kGridCmax + 1; c += 256) {
+        g.cnt[c] = 0;
+        g.lcnt[c] = 0;
+    }
 }
 
 __device__ __forceinline__ int grid_cell_of(const double *__restrict__ X, int64_t i, int p, const NnGrid &g)
@@ -611,23 +632,26 @@ __device__ __forceinline__ int grid_cell_of(const double *__restrict__ X, int64_
     return cell;
 }
 
-__global__ __launch_bounds__(256) void grid_count(const double *__restrict__ X, int64_t N, int p, NnGrid g)
+// Cell of each of the n points P (the design rows, or the locations) and the
+// points per cell.
+__global__ __launch_bounds__(256) void grid_count(const double *__restrict__ P, int64_t n, int p, NnGrid g,
+                                                  int32_t *cid, int32_t *cnt)
 {
     __shared__ int32_t h[kGridCmax];
     for (int c = threadIdx.x; c < g.C; c += 256) h[c] = 0;
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-        const int c = grid_cell_of(X, i, p, g);
-        g.cid[i] = c;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int c = grid_cell_of(P, i, p, g);
+        cid[i] = c;
         atomicAdd(&h[c], 1);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < g.C; c += 256)
-        if (h[c]) atomicAdd(&g.cnt[c], h[c]);
+        if (h[c]) atomicAdd(&cnt[c], h[c]);
 }
 
 // Exclusive scan of the counts (one workgroup, four cells per thread).
-__global__ __launch_bounds__(256) void grid_scan(int64_t N, NnGrid g)
+__global__ __launch_bounds__(256) void grid_scan(int64_t n, int C, const int32_t *cnt, int32_t *off, int32_t *cur)
 {
     __shared__ int32_t part[256];
     const int t = threadIdx.x;
@@ -635,7 +659,7 @@ __global__ __launch_bounds__(256) void grid_scan(int64_t N, NnGrid g)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int c = 4 * t + q;
-        v[q] = c < g.C ? g.cnt[c] : 0;
+        v[q] = c < C ? cnt[c] : 0;
         sum += v[q];
     }
     part[t] = sum;
@@ -650,13 +674,20 @@ __global__ __launch_bounds__(256) void grid_scan(int64_t N, NnGrid g)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int c = 4 * t + q;
-        if (c < g.C) {
-            g.off[c] = run;
-            g.cur[c] = run;
+        if (c < C) {
+            off[c] = run;
+            cur[c] = run;
         }
         run += v[q];
     }
-    if (t == 0) g.off[g.C] = (int32_t)N;
+    if (t == 0) off[C] = (int32_t)n;
+}
+
+// The locations in cell order.
+__global__ __launch_bounds__(256) void grid_order(int64_t M, NnGrid g)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256)
+        g.lperm[atomicAdd(&g.lcur[g.lcid[i]], 1)] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void grid_scatter(const double *__restrict__ X, int64_t N, int p, NnGrid g)
@@ -728,7 +759,11 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
     __shared__ float mindr[kGridCmax];      // <= squared distance from x to the box of that cell
 
     const int tid = threadIdx.x, C = gr.C;
-    const int64_t m = blockIdx.x;
+    // the XCD of this workgroup (blockIdx.x mod 8) takes the slots
+    // [x q, (x + 1) q) of the locations in cell order; the grid is 8 q wide
+    const int64_t q = (M + 7) / 8, slot = (int64_t)(blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    if (slot >= M) return;  // the whole workgroup, before any barrier
+    const int64_t m = gr.lperm[slot];
     if (tid < PF) xs[tid] = XX[m * p + tid];
     if (tid == 0) {
         grp.count = 0;
@@ -889,8 +924,8 @@ static hipError_t launch_grid_cap(const double *X, int64_t N, int p, const doubl
     switch (p) {
 #define LAGP_NG_CASE(P)                                                                                       \
     case P:                                                                                                   \
-        hipLaunchKernelGGL((nn_grid_kernel<CAP, SORTN, P>), dim3((unsigned)M), dim3(kNnBlock), 0, st, X, N, XX, \
-                           M, Np, pool, g);                                                                   \
+        hipLaunchKernelGGL((nn_grid_kernel<CAP, SORTN, P>), dim3((unsigned)(8 * ((M + 7) / 8))), dim3(kNnBlock), 0, \
+                           st, X, N, XX, M, Np, pool, g);                                                     \
         break;
         LAGP_NG_CASE(1)
         LAGP_NG_CASE(2)
@@ -920,15 +955,18 @@ hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, i
 {
     if (M == 0) return hipSuccess;
     if (p < 1 || p > kMaxP || !ws) return hipErrorInvalidValue;
-    const NnGrid g = grid_layout(ws, N, p);
-    const int64_t nb = (N + 255) / 256;
-    const unsigned rows_grid = (unsigned)(nb < 4096 ? nb : 4096);
+    const NnGrid g = grid_layout(ws, N, p, M);
+    const int64_t nb = (N + 255) / 256, mb = (M + 255) / 256;
+    const unsigned rows_grid = (unsigned)(nb < 4096 ? nb : 4096), locs_grid = (unsigned)(mb < 4096 ? mb : 4096);
     const unsigned parts = (unsigned)(nb < kGridParts ? nb : kGridParts);
     hipLaunchKernelGGL(grid_minmax, dim3(parts), dim3(256), 0, st, X, N, p, g);
     hipLaunchKernelGGL(grid_final, dim3(1), dim3(256), 0, st, p, (int)parts, g);
-    hipLaunchKernelGGL(grid_count, dim3(rows_grid), dim3(256), 0, st, X, N, p, g);
-    hipLaunchKernelGGL(grid_scan, dim3(1), dim3(256), 0, st, N, g);
+    hipLaunchKernelGGL(grid_count, dim3(rows_grid), dim3(256), 0, st, X, N, p, g, g.cid, g.cnt);
+    hipLaunchKernelGGL(grid_count, dim3(locs_grid), dim3(256), 0, st, XX, M, p, g, g.lcid, g.lcnt);
+    hipLaunchKernelGGL(grid_scan, dim3(1), dim3(256), 0, st, N, g.C, g.cnt, g.off, g.cur);
+    hipLaunchKernelGGL(grid_scan, dim3(1), dim3(256), 0, st, M, g.C, g.lcnt, g.loff, g.lcur);
     hipLaunchKernelGGL(grid_scatter, dim3(rows_grid), dim3(256), 0, st, X, N, p, g);
+    hipLaunchKernelGGL(grid_order, dim3(locs_grid), dim3(256), 0, st, M, g);
     hipLaunchKernelGGL(grid_box, dim3((unsigned)g.C), dim3(256), 0, st, X, p, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

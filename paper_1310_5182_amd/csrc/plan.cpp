@@ -150,7 +150,7 @@ extern "C" {
 lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes)
 {
     size_t nn = 0;
-    lagp_status s = lagp_nn_pool_workspace(N, p, &nn);
+    lagp_status s = lagp_nn_pool_workspace(N, p, M, &nn);
     if (s != LAGP_OK) return s;
     s = lagp_alc_uneven_workspace(p, M, Np_max, n_max, bytes);
     if (s != LAGP_OK) return s;
@@ -179,7 +179,7 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     hipError_t e = lagp::alc_uneven_workspace(p, M, Np_max, n_max, &need_alc);
     if (e != hipSuccess) return plan_fail(LAGP_EHIP, "workspace query", e);
     need_alc = (need_alc + 255) & ~(size_t)255;
-    need = need_alc + lagp::nn_pool_workspace(N, p);
+    need = need_alc + lagp::nn_pool_workspace(N, p, M);
     if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < need)
         return lagp::set_error(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes", need);
     if (!X || !Y || !XX || !sel) return plan_fail(LAGP_EINVAL, "X, Y, XX and sel must be non-NULL");

@@ -164,13 +164,15 @@ def test_plan_validation(L):
 
 def test_nn_pool_ws_validation(L):
     nb = ctypes.c_size_t(0)
-    assert L.lagp_nn_pool_workspace(100, 2, None) == -1
-    assert L.lagp_nn_pool_workspace(100, 17, ctypes.byref(nb)) == -4
-    assert L.lagp_nn_pool_workspace(0, 2, ctypes.byref(nb)) == -1
-    assert L.lagp_nn_pool_workspace(100, 3, ctypes.byref(nb)) == 0
+    assert L.lagp_nn_pool_workspace(100, 2, 3, None) == -1
+    assert L.lagp_nn_pool_workspace(100, 17, 3, ctypes.byref(nb)) == -4
+    assert L.lagp_nn_pool_workspace(0, 2, 3, ctypes.byref(nb)) == -1
+    assert L.lagp_nn_pool_workspace(100, 2, -1, ctypes.byref(nb)) == -1
+    assert L.lagp_nn_pool_workspace(100, 3, 3, ctypes.byref(nb)) == 0
     need = nb.value
     assert need >= 100 * (3 * 4 + 8)                              # rows cell by cell, indices, cells
-    assert L.lagp_nn_pool_workspace(200, 3, ctypes.byref(nb)) == 0 and nb.value > need
+    assert L.lagp_nn_pool_workspace(200, 3, 3, ctypes.byref(nb)) == 0 and nb.value > need
+    assert L.lagp_nn_pool_workspace(100, 3, 3000, ctypes.byref(nb)) == 0 and nb.value > need
     ws = lambda *a: L.lagp_nn_pool_ws(*a, None)                   # noqa: E731
     assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE, need - 1) == -2  # too small
     assert ws(FAKE, 100, 3, FAKE, 3, 10, FAKE, FAKE + 4, need) == -2  # not 16-byte aligned

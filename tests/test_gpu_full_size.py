@@ -107,7 +107,10 @@ def test_uneven_full_size(lagp, orc):
     W = workloads.make(3)
     print(f"[full] config3 N={W.N} M={W.M}", flush=True)
     X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
-    o = lagp.alc_uneven_predict(X, Y, XX, W.n0, 100, 2000, W.d, W.g, n_per=dev(W.n_per), Np_per=dev(W.Np_per))
+    # as timed: one tuned, graph-captured plan (launched again after creation)
+    plan = lagp.Plan(X, Y, XX, W.n0, 100, 2000, W.d, W.g, n_per=dev(W.n_per), Np_per=dev(W.Np_per))
+    print(f"[full] plan: {plan.describe()}", flush=True)
+    o = plan.launch()
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in o.items() if k != "workspace"}
     del o
