@@ -223,3 +223,37 @@ def test_bad_pool_and_nonfinite_location(lagp):
         assert np.isnan(g["mean"][m]) and np.isnan(g["s2"][m])
         assert np.all(g["sel"][m] == -1)
     assert np.all(np.isfinite(g["mean"][[0, 1, 3]]))
+
+
+@pytest.mark.parametrize("case", ["clusters_p3", "p1_duplicates", "p16", "constant_coordinate"])
+def test_nn_pool_grid_nonuniform(lagp, orc, case):
+    """Grid-pruned pools on designs far from uniform: clusters with empty cells
+    between them, locations outside the design's bounding box, duplicates, a
+    coordinate that never varies, and p = 1 and p = 16 cell layouts."""
+    import torch
+
+    r = np.random.default_rng(17)
+    if case == "clusters_p3":
+        centres = r.random((5, 3))
+        X = np.vstack([c + 0.02 * r.standard_normal((7000, 3)) for c in centres] + [r.random((2000, 3))])
+        XX = np.vstack([centres + 0.01, r.random((10, 3)), np.array([[1.5, 1.5, 1.5], [-0.4, 0.5, 2.0]])])
+        sizes = [1, 50, 1000, 2000]
+    elif case == "p1_duplicates":
+        X = np.round(r.random((20000, 1)) * 300) / 300  # about 67 copies of each value
+        XX = np.vstack([X[:5], r.random((5, 1)), [[1.7]], [[-2.0]]])
+        sizes = [1, 777, 2048]
+    elif case == "p16":
+        X = r.random((20000, 16))
+        XX = np.vstack([X[:3] + 1e-3, r.random((5, 16))])
+        sizes = [10, 500, 1024]
+    else:
+        X = r.random((30000, 4))
+        X[:, 2] = 0.25
+        XX = np.vstack([r.random((6, 4)), X[:2]])
+        sizes = [64, 1000]
+    for npl in sizes:
+        print(f"[parity] nn_pool grid {case} N={X.shape[0]} p={X.shape[1]} M={XX.shape[0]} Np={npl}", flush=True)
+        got = lagp.nn_pool(dev(X), dev(XX), npl, grid=True)
+        torch.cuda.synchronize()
+        want = orc.nn_pool(X, XX, npl)
+        assert np.array_equal(got.cpu().numpy(), want), (case, npl)
