@@ -67,8 +67,8 @@ typedef int32_t lagp_status;
 #define LAGP_LOC_NONFINITE 3    /* x not finite                                 */
 #define LAGP_LOC_BAD_POOL 4     /* a pool entry outside [0, N): the location is */
                                 /* skipped, no design row is read               */
-#define LAGP_LOC_BAD_SHAPE 5    /* per-location n or N' outside the bounds of   */
-                                /* lagp_alc_uneven_from_pool                    */
+#define LAGP_LOC_BAD_SHAPE 5    /* per-location n, N' or d outside the bounds   */
+                                /* of lagp_alc_uneven_from_pool                 */
 
 /*
  * lagp_nn_pool -- nearest-neighbour candidate pools (Sec. 2.2, Sec. 3.1).
@@ -205,6 +205,12 @@ lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int3
  *                           [sel_off[m], sel_off[m] + n_m)); NULL: row m
  *                           starts at m * n_max and entries n_m .. n_max - 1
  *                           are set to -1 (alc NaN)
+ *   d_per [M]               per-location lengthscale (device float64; NULL
+ *                           means d everywhere), e.g. the d_hat of
+ *                           lagp_local_mle_d for a second design stage with
+ *                           each location's own estimate (Fig. 1 step 4);
+ *                           each must be finite and > 0, else status[m] =
+ *                           LAGP_LOC_BAD_SHAPE
  *   workspace               device memory of at least the size reported by
  *                           lagp_alc_uneven_workspace (else LAGP_EWORKSPACE);
  *                           holds the location queue and the factor-row
@@ -218,10 +224,10 @@ lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int3
 lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                       const double *XX, int64_t M, const int32_t *pool, int32_t Np_max,
                                       int32_t n0, int32_t n_max, const int32_t *n_per,
-                                      const int32_t *Np_per, const int64_t *sel_off, double d, double g,
-                                      int32_t precision, double *mean, double *s2, double *var,
-                                      int32_t *sel, double *alc, int32_t *status, int32_t *guard,
-                                      void *workspace, size_t workspace_bytes, void *stream);
+                                      const int32_t *Np_per, const int64_t *sel_off, const double *d_per,
+                                      double d, double g, int32_t precision, double *mean, double *s2,
+                                      double *var, int32_t *sel, double *alc, int32_t *status,
+                                      int32_t *guard, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Plans: the whole float64 path with per-location sizes (lagp_nn_pool_ws
@@ -256,8 +262,8 @@ lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max,
 
 lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
                              int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,
-                             const int32_t *Np_per, const int64_t *sel_off, double d, double g,
-                             int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
+                             const int32_t *Np_per, const int64_t *sel_off, const double *d_per, double d,
+                             double g, int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
                              double *alc, int32_t *status, int32_t *guard, void *workspace,
                              size_t workspace_bytes, int32_t flags, void *stream, lagp_plan *out);
 lagp_status lagp_plan_launch(lagp_plan plan, void *stream);

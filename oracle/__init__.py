@@ -57,7 +57,7 @@ class Oracle:
         L.orc_nn_pool.restype = i32
         L.orc_gp_predict.argtypes = [P, P, i32, i32, P, f64, f64, P]
         L.orc_gp_predict.restype = i32
-        L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, f64,
+        L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, P, f64,
                               P, i32, i32, P, P, P, P, P, P, P, P, P]
         L.orc_alc.restype = i32
         L.orc_alc_scores.argtypes = [P, i32, i32, P, i64, P, f64, f64, i32, P, P, P]
@@ -90,8 +90,10 @@ class Oracle:
         return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
 
     def alc(self, X, Y, XX, pool, n0: int, n: int, d: float, g: float, *, Np: int | None = None,
-            n_per=None, Np_per=None, forced=None, mode_b: bool = False, threads: int = 0) -> dict:
-        """Greedy ALC local designs and local predictions for every location.
+            n_per=None, Np_per=None, forced=None, mode_b: bool = False, threads: int = 0,
+            d_per=None) -> dict:
+        """Greedy ALC local designs and local predictions for every location
+        (d_per: an own lengthscale per location, overriding d).
 
         Returns arrays: sel, dsel, dmax, amax, dsecond, nu (M x nmax), vtraj
         (M x (nmax + 1)), mean, s2, var, v, psi (M), status (M).
@@ -112,8 +114,9 @@ class Oracle:
         vtraj = np.full((M, nmax + 1), np.nan)
         pred = np.full((M, 5), np.nan)
         status = np.zeros(M, np.int32)
+        d_per = None if d_per is None else _f64(d_per)
         rc = self.L.orc_alc(_p(X), _p(Y), X.shape[0], X.shape[1], _p(XX), M, _p(pool), Np_stride,
-                            _p(Np_per), Np, _p(n_per), n, nmax, n0, d, g, _p(forced), int(mode_b),
+                            _p(Np_per), Np, _p(n_per), n, nmax, n0, d, _p(d_per), g, _p(forced), int(mode_b),
                             threads, _p(sel), _p(dsel), _p(dmax), _p(amax), _p(dsecond), _p(nu),
                             _p(vtraj), _p(pred), _p(status))
         if rc:

@@ -452,7 +452,7 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
  */
 int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX, int64_t M,
             const int32_t *pool, int Np_stride, const int32_t *Np_per, int Np,
-            const int32_t *n_per, int n, int n_stride, int n0, double d, double g,
+            const int32_t *n_per, int n, int n_stride, int n0, double d, const double *d_per, double g,
             const int32_t *forced, int mode_b, int nthreads,
             int32_t *sel, double *dsel, double *dmax, int32_t *amax, double *dsecond,
             double *nu, double *vtraj, double *pred, int32_t *status)
@@ -474,13 +474,15 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
         for (int64_t m = 0; m < M; m++) {
             int nm = n_per ? n_per[m] : n;
             int Npm = Np_per ? Np_per[m] : Np;
+            const double dm = d_per ? d_per[m] : d;  /* the location's own lengthscale */
             orc_trace tr = {t_sel, t_d, t_d + n_stride, t_amax, t_d + 2 * n_stride,
                             t_d + 3 * n_stride, t_v, {0}};
             int rc;
-            if (!ok || nm > n_stride || Npm > Np_stride || nm > Npm || n0 > nm || Npm > N)
+            if (!ok || nm > n_stride || Npm > Np_stride || nm > Npm || n0 > nm || Npm > N || !(dm > 0.0) ||
+                !isfinite(dm))
                 rc = ORC_BAD_ARGS;
             else
-                rc = alc_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np_stride, Npm, n0, nm, d, g,
+                rc = alc_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np_stride, Npm, n0, nm, dm, g,
                              forced ? forced + m * (int64_t)n_stride : NULL, mode_b, &tr, &w);
             if (rc == ORC_BAD_ARGS) {
                 for (int j = 0; j < n_stride; j++) { t_sel[j] = -1; t_amax[j] = -1; }

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_FP64_REFORM, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_scores", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
+__all__ = ["nn_pool", "alc_scores", "alc_multistage", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED, "fp64_reform": LAGP_FP64_REFORM}
@@ -146,11 +146,20 @@ def _i32(t, name: str, M: int) -> int:
     return t.data_ptr()
 
 
+def _d_per(t, M: int) -> int:
+    if t is None:
+        return 0
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda or t.numel() != M:
+        raise ValueError("d_per must be a contiguous float64 device tensor of length M")
+    return t.data_ptr()
+
+
 def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float, n_per=None,
-                         Np_per=None, sel_off=None, precision="fp64", out: dict | None = None) -> dict:
+                         Np_per=None, sel_off=None, precision="fp64", out: dict | None = None,
+                         d_per=None) -> dict:
     """Greedy ALC designs with a design size n_per[m] and a pool size Np_per[m]
     of each location's own (int32 device tensors, None = n_max / the pool
-    width).  pool: M x Np_max from nn_pool(X, XX, Np_max).  Without sel_off,
+    width) and optionally a lengthscale d_per[m] of its own (float64, None = d).  pool: M x Np_max from nn_pool(X, XX, Np_max).  Without sel_off,
     sel and alc are M x n_max with entries past n_per[m] set to -1 / NaN;
     with sel_off (int64, M + 1 offsets) they are flat rows, and `out` must
     supply sel and alc of length sel_off[M]."""
@@ -175,7 +184,7 @@ def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float
     _lib.check(L.lagp_alc_uneven_from_pool(
         X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np_max, n0, n_max,
         _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M),
-        sel_off.data_ptr() if sel_off is not None else 0, float(d), float(g), _prec(precision),
+        sel_off.data_ptr() if sel_off is not None else 0, _d_per(d_per, M), float(d), float(g), _prec(precision),
         o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
         o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), ws.data_ptr(), ws.numel(),
         _stream(dev)))
@@ -183,7 +192,7 @@ def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float
 
 
 def alc_uneven_predict(X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
-                       Np_per=None, precision="fp64", out: dict | None = None) -> dict:
+                       Np_per=None, precision="fp64", out: dict | None = None, d_per=None) -> dict:
     """The whole path with per-location n and N': one pool of the Np_max nearest
     neighbours per location (each location uses its own prefix), then
     alc_uneven_from_pool."""
@@ -191,7 +200,7 @@ def alc_uneven_predict(X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: 
     o = out if out is not None else {}
     o["pool"] = nn_pool(X, XX, Np_max, out=o.get("pool"))
     return alc_uneven_from_pool(X, Y, XX, o["pool"], n0, n_max, d, g, n_per=n_per, Np_per=Np_per,
-                                precision=precision, out=o)
+                                precision=precision, out=o, d_per=d_per)
 
 
 class Plan:
@@ -202,7 +211,7 @@ class Plan:
     current stream.  The input tensors must stay alive as long as the plan."""
 
     def __init__(self, X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
-                 Np_per=None, tune: bool = True):
+                 Np_per=None, tune: bool = True, d_per=None):
         L = _lib.load()
         X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
         M, p = XX.shape
@@ -212,11 +221,12 @@ class Plan:
         nbytes = ctypes.c_size_t(0)
         _lib.check(L.lagp_plan_workspace(X.shape[0], p, M, Np_max, n_max, ctypes.byref(nbytes)))
         o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
-        self._keep = (X, Y, XX, n_per, Np_per)
+        self._keep = (X, Y, XX, n_per, Np_per, d_per)
         self.out, self._dev, self._h = o, dev, ctypes.c_void_p()
         _lib.check(L.lagp_plan_create(
             X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, n0, n_max, Np_max,
-            _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M), 0, float(d), float(g), o["pool"].data_ptr(),
+            _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M), 0, _d_per(d_per, M), float(d), float(g),
+            o["pool"].data_ptr(),
             o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
             o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), o["workspace"].data_ptr(),
             o["workspace"].numel(), 0 if tune else 1, _stream(dev), ctypes.byref(self._h)))
@@ -337,3 +347,22 @@ def local_predict(X, Y, sel, XX, d, g: float) -> dict:
                                     out["s2"].data_ptr(), out["var"].data_ptr(), out["status"].data_ptr(),
                                     _stream(dev)))
     return out
+
+
+def alc_multistage(X, Y, XX, n0: int, n: int, Np: int, d0: float, g: float, stages: int = 2,
+                   dmin: float = 1e-3, dmax: float = 5.0, maxit: int = 100) -> dict:
+    """Local designs with a lengthscale of each location's own (Fig. 1 with
+    step 4): greedy ALC designs at d0 and the MLE of d on each design, then
+    `stages - 1` more rounds of designs at each location's estimate and its
+    MLE again; the prediction uses the last estimate on the last design.
+    Returns pool, sel (M x n), d (the estimates, M), mle (last round) and
+    mean, s2, var, status of the prediction."""
+    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
+    pool = nn_pool(X, XX, Np)
+    d_est = None
+    for _ in range(max(1, stages)):
+        o = alc_uneven_from_pool(X, Y, XX, pool, n0, n, d0, g, d_per=d_est)
+        mle = local_mle_d(X, Y, o["sel"], d0 if d_est is None else d_est, g, dmin, dmax, maxit)
+        d_est = mle["d"]
+    pred = local_predict(X, Y, o["sel"], XX, d_est, g)
+    return dict(pool=pool, sel=o["sel"], d=d_est, mle=mle, design_status=o["status"], **pred)

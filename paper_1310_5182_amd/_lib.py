@@ -77,13 +77,13 @@ def load():
     L.lagp_alc_predict.restype = i32
     L.lagp_alc_uneven_workspace.argtypes = [i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_alc_uneven_workspace.restype = i32
-    L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, f64, f64,
+    L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, P, f64, f64,
                                             i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
     L.lagp_alc_uneven_from_pool.restype = i32
     L.lagp_plan_workspace.argtypes = [i64, i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_plan_workspace.restype = i32
-    L.lagp_plan_create.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, P, P, P, f64, f64, P, P, P, P, P,
-                                   P, P, P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
+    L.lagp_plan_create.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, P, P, P, P, f64, f64, P, P, P, P,
+                                   P, P, P, P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
     L.lagp_plan_create.restype = i32
     L.lagp_plan_launch.argtypes = [P, P]
     L.lagp_plan_launch.restype = i32

@@ -52,6 +52,7 @@ struct IncArgs {
     const int32_t *n_per;     // [M] or NULL
     const int32_t *Np_per;    // [M] or NULL
     const int64_t *sel_off;   // [M + 1] or NULL: row m of sel / alc at m * a.n
+    const double *d_per;      // [M] lengthscale of each location, or NULL: a.d
     int pool_stride;          // row stride of the pool (N'_max)
     const int32_t *queue;     // location list, NULL: location = blockIdx.x
     const int32_t *qinfo;     // [2]: first queue entry and count of this schedule
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int p = a.p, n0 = a.n0;
-    const double kappa = 1.0 + a.g, nid = -1.0 / a.d;
+    const double kappa = 1.0 + a.g;
     const int G0 = ZR + x.zl_cols;  // first entry kept in global memory
     double *gz = x.gz ? x.gz + (size_t)blockIdx.x * x.gcols * CAP : nullptr;
 
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         const int n = x.n_per ? x.n_per[m] : a.n;
         const int Np = x.Np_per ? x.Np_per[m] : a.Np;
         const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
+        const double nid = -1.0 / (x.d_per ? x.d_per[m] : a.d);  // checked > 0 by the queue
 
         // ---- stage the location; every lane loads its own pool positions
         if (tid == 0) ctl_status = kLocOk;
@@ -579,7 +581,9 @@ __global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
     const int Np = x.Np_per ? x.Np_per[m] : a.Np;
     const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
     const int64_t rowlen = x.sel_off ? x.sel_off[m + 1] - x.sel_off[m] : a.n;
-    const bool ok = n >= a.n0 && n <= a.n && Np >= n && Np <= x.pool_stride && rowlen >= n;
+    const double dm = x.d_per ? x.d_per[m] : a.d;
+    const bool ok = n >= a.n0 && n <= a.n && Np >= n && Np <= x.pool_stride && rowlen >= n && dm > 0.0 &&
+                    isfinite(dm);
     const int b = ok ? sched_for(Np) : -1;
     if (b < 0) {
         w.key[m] = -1;
@@ -702,7 +706,8 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
 }
 
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
-                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st, int bcast)
+                             const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
+                             hipStream_t st, int bcast)
 {
     if (a.M == 0) return hipSuccess;
     DevInfo info;
@@ -729,6 +734,7 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
     x.n_per = n_per;
     x.Np_per = Np_per;
     x.sel_off = sel_off;
+    x.d_per = d_per;
     x.pool_stride = a.Np;
     x.queue = w.queue;
 

@@ -193,10 +193,10 @@ lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int3
 lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t N, int32_t p,
                                       const double *XX, int64_t M, const int32_t *pool, int32_t Np_max,
                                       int32_t n0, int32_t n_max, const int32_t *n_per,
-                                      const int32_t *Np_per, const int64_t *sel_off, double d, double g,
-                                      int32_t precision, double *mean, double *s2, double *var,
-                                      int32_t *sel, double *alc, int32_t *status, int32_t *guard,
-                                      void *workspace, size_t workspace_bytes, void *stream)
+                                      const int32_t *Np_per, const int64_t *sel_off, const double *d_per,
+                                      double d, double g, int32_t precision, double *mean, double *s2,
+                                      double *var, int32_t *sel, double *alc, int32_t *status,
+                                      int32_t *guard, void *workspace, size_t workspace_bytes, void *stream)
 {
     lagp_status s = check_common(X, N, p, XX, M, Np_max);
     if (s != LAGP_OK) return s;
@@ -215,7 +215,8 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
         return fail(LAGP_EWORKSPACE, "workspace of %zu bytes given, %zu needed", workspace_bytes, need);
     lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np_max, n0, n_max, d, g, mean, s2, var, sel, alc, nullptr, status,
                     guard};
-    e = lagp::launch_alc_uneven(a, n_per, Np_per, sel_off, workspace, workspace_bytes, (hipStream_t)stream);
+    e = lagp::launch_alc_uneven(a, n_per, Np_per, sel_off, d_per, workspace, workspace_bytes,
+                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "uneven alc launch");
     return ok();
 }

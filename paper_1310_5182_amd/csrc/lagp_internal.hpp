@@ -66,12 +66,13 @@ constexpr int kIncSchedules = 3;
 int alc_inc_schedule(int Np);  // schedule serving pools of Np (-1: none)
 bool alc_inc_supported(int p, int Np, int n);
 hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1);
-// Per-location n and N' (a.n, a.Np are the upper bounds; pool rows of a.Np).
+// Per-location n, N' (a.n, a.Np are the upper bounds; pool rows of a.Np) and,
+// when d_per is not NULL, lengthscale d.
 bool alc_uneven_supported(int p, int Np_max, int n_max);
 hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes);
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
-                             const int64_t *sel_off, void *ws, size_t ws_bytes, hipStream_t st,
-                             int bcast = -1);
+                             const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
+                             hipStream_t st, int bcast = -1);
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

@@ -20,6 +20,7 @@ struct lagp_plan_s {
     lagp::AlcArgs a;
     const int32_t *n_per, *Np_per;
     const int64_t *sel_off;
+    const double *d_per;
     int32_t *pool;
     void *ws;         // the ALC kernels' part of the workspace
     size_t ws_bytes;
@@ -56,7 +57,7 @@ static hipError_t run_path(const lagp_plan_s &P, int nnv, int bcast, hipStream_t
                        ? launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, 0, (float *)P.nnws)
                        : launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, nnv, nullptr);
     if (e != hipSuccess) return e;
-    return launch_alc_uneven(P.a, P.n_per, P.Np_per, P.sel_off, P.ws, P.ws_bytes, st, bcast);
+    return launch_alc_uneven(P.a, P.n_per, P.Np_per, P.sel_off, P.d_per, P.ws, P.ws_bytes, st, bcast);
 }
 
 // Milliseconds of one run (the best of `reps`, after one untimed run).
@@ -160,8 +161,8 @@ lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max,
 
 lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
                              int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,
-                             const int32_t *Np_per, const int64_t *sel_off, double d, double g,
-                             int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
+                             const int32_t *Np_per, const int64_t *sel_off, const double *d_per, double d,
+                             double g, int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
                              double *alc, int32_t *status, int32_t *guard, void *workspace,
                              size_t workspace_bytes, int32_t flags, void *stream, lagp_plan *out)
 {
@@ -170,7 +171,7 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     if (M < 1) return plan_fail(LAGP_EINVAL, "a plan needs M >= 1");
     // every argument check of the two calls it strings together, before any launch
     lagp_status s = lagp_alc_uneven_from_pool(X, Y, N, p, XX, 0, pool, Np_max, n0, n_max, n_per, Np_per,
-                                              sel_off, d, g, LAGP_FP64, mean, s2, var, sel, alc, status,
+                                              sel_off, d_per, d, g, LAGP_FP64, mean, s2, var, sel, alc, status,
                                               guard, workspace, workspace_bytes, stream);
     if (s != LAGP_OK) return s;  // its message stays in lagp_last_error()
     if (!pool) return plan_fail(LAGP_EINVAL, "pool must be non-NULL");
@@ -190,6 +191,7 @@ lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_
     P->n_per = n_per;
     P->Np_per = Np_per;
     P->sel_off = sel_off;
+    P->d_per = d_per;
     P->pool = pool;
     P->ws = workspace;
     P->ws_bytes = need_alc;

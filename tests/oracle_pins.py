@@ -32,6 +32,10 @@ What pins what:
                       h = K(X_j, x) from numpy; the one-point closed form
   scores_greedy     - the batch scores at a step of a greedy run reproduce that
                       step's best score and argmax
+  per_location_d    - a lengthscale of each location's own (the second design
+                      stage of Fig. 1 step 4) gives, location by location,
+                      the run with that scalar lengthscale; invalid entries
+                      fail only their own location
 """
 from __future__ import annotations
 
@@ -316,6 +320,27 @@ def scores_greedy(orc):
             assert arg == out["amax"][m, j], (m, j)
 
 
+def per_location_d(orc):
+    W = workloads.make(4, N=3000, M=5)
+    n0, n, Np = 6, 16, 90
+    pool = orc.nn_pool(W.X, W.XX, Np)
+    dp = np.array([0.05, 0.2, 0.7, 2.0, 0.2])
+    a = orc.alc(W.X, W.Y, W.XX, pool, n0, n, W.d, W.g, d_per=dp)
+    for m in range(W.M):
+        b = orc.alc(W.X, W.Y, W.XX[m:m + 1], pool[m:m + 1], n0, n, float(dp[m]), W.g)
+        for k in ("sel", "dsel", "mean", "s2", "var", "status"):
+            assert np.array_equal(a[k][m], b[k][0], equal_nan=True), (m, k)
+    c = orc.alc(W.X, W.Y, W.XX, pool, n0, n, W.d, W.g, d_per=np.full(W.M, W.d))
+    e = orc.alc(W.X, W.Y, W.XX, pool, n0, n, W.d, W.g)
+    for k in ("sel", "dsel", "mean", "s2", "var"):
+        assert np.array_equal(c[k], e[k], equal_nan=True), k
+    bad = dp.copy()
+    bad[1], bad[3] = 0.0, np.nan
+    f = orc.alc(W.X, W.Y, W.XX, pool, n0, n, W.d, W.g, d_per=bad)
+    assert list(f["status"] != 0) == [False, True, False, True, False]
+    assert np.array_equal(f["sel"][[0, 2, 4]], a["sel"][[0, 2, 4]])
+
+
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
        special_cases, design_point, predict_textbook, route_b, forced, nll_textbook,
-       nll_derivatives_fd, mle_optimality, scores_brute, scores_greedy]
+       nll_derivatives_fd, mle_optimality, scores_brute, scores_greedy, per_location_d]

@@ -45,9 +45,12 @@ def sequence_check(gpu_sel, pool, forced, n0, n_per=None, tau_floor=1e-12, nu_mu
 
 
 def cond_bounds(X, sel, d, g):
-    """kappa * eps * cond(K_n) per location (relative resolution of v)."""
+    """kappa * eps * cond(K_n) per location (relative resolution of v); d is a
+    scalar or one lengthscale per location."""
     out = np.empty(sel.shape[0])
+    dv = np.broadcast_to(np.asarray(d, dtype=float), (sel.shape[0],))
     for m in range(sel.shape[0]):
+        d = float(dv[m])
         D = X[sel[m]]
         r2 = np.zeros((len(D), len(D)))
         for k in range(D.shape[1]):

@@ -123,7 +123,7 @@ def test_local_validation(L):
 
 
 def uneven(L, N=5000, p=4, M=3, Np=2000, n0=6, n=100, prec=0, ws=FAKE, nbytes=1 << 30, sel=FAKE):
-    return L.lagp_alc_uneven_from_pool(FAKE, FAKE, N, p, FAKE, M, FAKE, Np, n0, n, None, None, None,
+    return L.lagp_alc_uneven_from_pool(FAKE, FAKE, N, p, FAKE, M, FAKE, Np, n0, n, None, None, None, None,
                                        0.3, 1e-5, prec, None, None, None, sel, None, None, None,
                                        ws, nbytes, None)
 
@@ -148,7 +148,7 @@ def test_uneven_validation(L):
 
 def test_plan_validation(L):
     h = ctypes.c_void_p()
-    args = [FAKE, FAKE, 5000, 4, FAKE, 3, 6, 100, 2000, None, None, None, 0.3, 1e-5, FAKE, None, None,
+    args = [FAKE, FAKE, 5000, 4, FAKE, 3, 6, 100, 2000, None, None, None, None, 0.3, 1e-5, FAKE, None, None,
             None, FAKE, None, None, None, FAKE, 1 << 30, 0, None]
     assert L.lagp_plan_create(*args, None) == -1                       # no handle
     bad = list(args); bad[5] = 0

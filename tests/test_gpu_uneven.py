@@ -44,21 +44,23 @@ def host(o):
     return {k: v.cpu().numpy() for k, v in o.items() if k != "workspace"}
 
 
-def run_uneven(lagp, W, n0, n_max, Np_max, n_per, Np_per):
+def run_uneven(lagp, W, n0, n_max, Np_max, n_per, Np_per, d_per=None):
     import torch
 
     o = lagp.alc_uneven_predict(dev(W.X), dev(W.Y), dev(W.XX), n0, n_max, Np_max, W.d, W.g,
                                 n_per=None if n_per is None else dev(n_per),
-                                Np_per=None if Np_per is None else dev(Np_per))
+                                Np_per=None if Np_per is None else dev(Np_per),
+                                d_per=None if d_per is None else dev(d_per))
     torch.cuda.synchronize()
     return host(o)
 
 
-def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-10):
+def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-10, d_per=None):
     M = W.M
     n_per = np.full(M, n_max, np.int32) if n_per is None else n_per
+    dv = np.full(M, W.d) if d_per is None else d_per
     forced = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per,
-                     forced=g["sel"], mode_b=True)
+                     forced=g["sel"], mode_b=True, d_per=d_per)
     assert np.all(g["status"] == 0), np.unique(g["status"], return_counts=True)
     assert np.all(forced["status"] == 0)
     for m in range(M):  # padding past each design
@@ -70,7 +72,7 @@ def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-1
         rel = np.empty(M)
         tol = np.empty(M)
         for m in range(M):
-            kc = parity.cond_bounds(W.X, g["sel"][m:m + 1, :n_per[m]], W.d, W.g)[0]
+            kc = parity.cond_bounds(W.X, g["sel"][m:m + 1, :n_per[m]], dv[m], W.g)[0]
             b = forced[k][m]
             floor = mean_floor if k == "mean" else 0.0
             rel[m] = abs(g[k][m] - b) / max(abs(b), floor)
@@ -78,7 +80,7 @@ def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-1
             tol[m] = max(tau_out, 10 * bound)
         rep[k] = dict(max_rel=float(rel.max()), n_cond_limited=int(np.sum(tol > tau_out)))
         worst = max(worst, float(np.max(rel / tol)))
-    free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per)
+    free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per, d_per=d_per)
     same = int(sum(np.array_equal(free["sel"][m, :n_per[m]], g["sel"][m, :n_per[m]]) for m in range(M)))
     rec = dict(M=M, N=W.N, p=W.p, n_range=[int(n_per.min()), int(n_per.max())],
                ties=seq["ties"], max_tie_r=seq["max_r"], fails=len(seq["fails"]), same_sequence=same,
@@ -163,3 +165,59 @@ def test_csr_rows_and_bad_shapes(lagp, orc):
     for i, m in enumerate(good):
         same = np.array_equal(ref["sel"][i, :n_per[m]], pad["sel"][m, :n_per[m]])
         assert same or abs(ref["mean"][i] - pad["mean"][m]) <= 1e-8 * max(1.0, abs(ref["mean"][i]))
+
+
+def test_per_location_lengthscale(lagp, orc):
+    """Each location with a lengthscale of its own (the second design stage of
+    Fig. 1 step 4), seeded log-uniform over a decade, with uneven n and N'."""
+    W = workloads.make(3, M=40)
+    dp = workloads.lengthscales(W.M, 0.05, 0.5)
+    print(f"[uneven] per-location d M={W.M}", flush=True)
+    g = run_uneven(lagp, W, W.n0, 100, 2000, W.n_per, W.Np_per, d_per=dp)
+    check_against_oracle(orc, W, g, W.n0, 100, W.n_per, W.Np_per, "uneven_per_location_d", d_per=dp)
+    # a constant d_per is the scalar d, bit for bit; invalid entries fail only their own location
+    a = run_uneven(lagp, W, W.n0, 100, 2000, W.n_per, W.Np_per)
+    b = run_uneven(lagp, W, W.n0, 100, 2000, W.n_per, W.Np_per, d_per=np.full(W.M, W.d))
+    for k in ("sel", "mean", "s2", "status"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    bad = dp.copy()
+    bad[[3, 17]] = [0.0, np.nan]
+    c = run_uneven(lagp, W, W.n0, 100, 2000, W.n_per, W.Np_per, d_per=bad)
+    assert list(np.nonzero(c["status"])[0]) == [3, 17] and np.all(c["status"][[3, 17]] == 5)
+    ok = np.setdiff1d(np.arange(W.M), [3, 17])
+    assert np.array_equal(c["sel"][ok], g["sel"][ok])
+
+
+def test_multistage(lagp, orc):
+    """Fig. 1 with step 4 end to end (config-4 shapes): designs at d0, MLE,
+    designs at each location's estimate, MLE, prediction; against the oracle
+    running the same stages on its own estimates.  The two sides' estimates
+    agree to the MLE's stopping tolerance, so designs are compared where they
+    coincide and the outputs there to 1e-6."""
+    import torch
+
+    W = workloads.make(4, N=20000, M=24)
+    n0, n, Np, d0 = W.n0, 30, 300, 0.2
+    print(f"[uneven] multistage M={W.M}", flush=True)
+    o = lagp.alc_multistage(dev(W.X), dev(W.Y), dev(W.XX), n0, n, Np, d0, W.g, stages=2)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in o.items() if isinstance(v, torch.Tensor)}
+    assert np.all(g["design_status"] == 0) and np.all(g["status"] == 0)
+    # the oracle, stage by stage on its own results
+    pool = orc.nn_pool(W.X, W.XX, Np)
+    assert np.array_equal(g["pool"], pool)
+    r1 = orc.alc(W.X, W.Y, W.XX, pool, n0, n, d0, W.g)
+    m1 = orc.local_mle(W.X, W.Y, r1["sel"], d0, W.g)
+    r2 = orc.alc(W.X, W.Y, W.XX, pool, n0, n, d0, W.g, d_per=m1["d"])
+    m2 = orc.local_mle(W.X, W.Y, r2["sel"], m1["d"], W.g)
+    same = np.all(g["sel"] == r2["sel"], axis=1)
+    rel_d = np.abs(g["d"] - m2["d"]) / m2["d"]
+    worst = 0.0
+    for m in np.nonzero(same)[0]:
+        ref = orc.gp_predict(W.X[r2["sel"][m]], W.Y[r2["sel"][m]], W.XX[m], float(m2["d"][m]), W.g)
+        for k in ("mean", "s2"):
+            worst = max(worst, abs(g[k][m] - ref[k]) / max(abs(ref[k]), 1e-6))
+    _log("multistage", dict(M=W.M, same_designs=int(same.sum()), d_max_rel=float(rel_d[same].max()),
+                            outputs_max_rel=worst, d_range=[float(g["d"].min()), float(g["d"].max())]))
+    assert same.mean() >= 0.8
+    assert worst <= 1e-6

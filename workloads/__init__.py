@@ -133,6 +133,13 @@ def uniform(seed: int, N: int, p: int, M: int, *, resp=response_sines, noise: fl
     return np.ascontiguousarray(X), np.ascontiguousarray(Y), np.ascontiguousarray(XX)
 
 
+def lengthscales(M: int, lo: float, hi: float, seed: int = 0) -> np.ndarray:
+    """A lengthscale per location, log-uniform on [lo, hi] (inputs for designs
+    with each location's own d)."""
+    r = np.random.default_rng([SEED_ROOT, 200, M, seed])
+    return np.exp(r.uniform(np.log(lo), np.log(hi), M))
+
+
 def scores_case(j: int, Nc: int, p: int, seed: int = 0, spread: float = 0.25) -> tuple:
     """One location with a design of j points and Nc candidates (the shape of
     the paper's ALC-in-isolation experiment, Sec. 4): x uniform on the unit
