@@ -22,7 +22,8 @@
 //               - (n/2) ((alpha^T Kdd alpha - 2 (Kd alpha)^T A (Kd alpha)) / psi
 //                        + (alpha^T Kd alpha)^2 / psi^2)
 // tr(A Kd) and tr(A Kdd) are element sums (A and Kd symmetric), and
-// tr(A Kd A Kd) = sum_ab B_ab B_ba with B = A Kd, formed pair by pair.
+// tr(A Kd A Kd) = sum_ab (A Kd)_ab (Kd A)_ab, both products formed on the
+// matrix cores.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -201,23 +202,39 @@ struct GpBlock {
             rowk[tid] = v;
         }
         __syncthreads();
-        // v^T A v, and tr(B B) over element pairs a <= b of B = A Kd
+        // v^T A v
         double s2[2] = {0.0, 0.0};
         if (tid < n) {
             double av = 0.0;
             for (int b = 0; b < n; b++) av = fma(M1[tid * S + b], rowk[b], av);
             s2[0] = rowk[tid] * av;
         }
-        for (int a = ta; a < n; a += 16)
-            for (int b = tb; b < n; b += 16) {
-                if (b < a) continue;
-                double bab = 0.0, bba = 0.0;
-                for (int c = 0; c < n; c++) {
-                    bab = fma(M1[a * S + c], M2[c * S + b], bab);
-                    bba = fma(M1[b * S + c], M2[c * S + a], bba);
-                }
-                s2[1] = fma(a == b ? 1.0 : 2.0, bab * bba, s2[1]);
+        // tr(B B) with B = A Kd: since A and Kd are symmetric, B^T = Kd A, so
+        // tr(B B) = sum_ab B_ab (Kd A)_ab, and tile (J, I) of that sum equals
+        // tile (I, J).  Each wave takes tiles I <= J (16 x 16, zero beyond n) in
+        // turn, forms both products on the 16x16x4 float64 MFMA and sums their
+        // elementwise product in registers.
+        const int T = (n + 15) >> 4;
+        const int r16 = lane & 15, k4 = lane >> 4;
+        for (int t = w; t < T * (T + 1) / 2; t += kGpWaves) {  // wave-uniform
+            int I = 0, J = t;
+            while (J >= T - I) J -= T - I++;
+            J += I;
+            const int a = 16 * I + r16, b = 16 * J + r16;
+            v4d pb = {0.0, 0.0, 0.0, 0.0}, pc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < 4 * T; kk++) {
+                const int c = 4 * kk + k4;
+                const bool ac = a < n && c < n, bc = b < n && c < n;
+                // A-operand lanes hold row a, column c; B-operand lanes row c, column b
+                pb = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? M1[a * S + c] : 0.0, bc ? M2[c * S + b] : 0.0,
+                                                          pb, 0, 0, 0);
+                pc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? M2[a * S + c] : 0.0, bc ? M1[c * S + b] : 0.0,
+                                                          pc, 0, 0, 0);
             }
+            const double wt = I == J ? 1.0 : 2.0;
+#pragma unroll
+            for (int r = 0; r < 4; r++) s2[1] = fma(wt * pb[r], pc[r], s2[1]);
+        }
         bsum(s2);
         e.d2 = 0.5 * (s1[1] - s2[1]) - 0.5 * n * ((s1[3] - 2.0 * s2[0]) / psi + aKda * aKda / (psi * psi));
         return e;
