@@ -110,7 +110,7 @@ __device__ __forceinline__ void dot_rowbcast(double (&acc)[S], const double (&lr
 // per-lane copy (no instruction of its own) instead of uniform-address LDS
 // reads (LDS return bandwidth).
 template <int TB, int S, int ZR, bool RL>
-__global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void alc_inc_kernel(IncArgs x)
 {
     constexpr int NW = TB / kWave;
     constexpr int CAP = TB * S;
@@ -128,7 +128,9 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
     double *zb = zl + (size_t)x.zl_cols * CAP;
     const int zrow = x.zrow;
 
-    __shared__ double pub[2][NW][3];  // s, cov, residual of each wave's best
+    // each wave's best: s, then 1 / lambda, w_h and t_j should it be chosen
+    // (lambda = sqrt(s)), worked out before the barrier by its own lane
+    __shared__ double pub[2][NW][4];
     __shared__ double red_s[2][NW];
     __shared__ int32_t red_i[2][NW], red_k[2][NW];
     __shared__ double alc_out[kIncNmax];
@@ -150,17 +152,19 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
         if (x.queue) {
             if (tid == 0) ctl_loc = atomicAdd(x.counter, 1);
             __syncthreads();
-            const int q = ctl_loc;
+            const int q = __builtin_amdgcn_readfirstlane(ctl_loc);
             if (q >= x.qinfo[1]) break;
-            m = x.queue[x.qinfo[0] + q];
+            m = __builtin_amdgcn_readfirstlane(x.queue[x.qinfo[0] + q]);
         } else {
             if (iter > 0) break;
             m = blockIdx.x;
         }
-        const int n = x.n_per ? x.n_per[m] : a.n;
-        const int Np = x.Np_per ? x.Np_per[m] : a.Np;
+        // per-location scalars: wave-uniform, so that the step loop and its
+        // bounds stay in scalar registers and scalar branches
+        const int n = __builtin_amdgcn_readfirstlane(x.n_per ? x.n_per[m] : a.n);
+        const int Np = __builtin_amdgcn_readfirstlane(x.Np_per ? x.Np_per[m] : a.Np);
         const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
-        const double nid = -1.0 / (x.d_per ? x.d_per[m] : a.d);  // checked > 0 by the queue
+        const double nid = uniform(-1.0 / (x.d_per ? x.d_per[m] : a.d));  // checked > 0 by the queue
 
         // ---- stage the location; every lane loads its own pool positions
         if (tid == 0) ctl_status = kLocOk;
@@ -193,9 +197,9 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
             for (int e = 0; e < ZR; e++) z[s][e] = 0.0;
         }
         __syncthreads();
-        int status = ctl_status;
+        int status = __builtin_amdgcn_readfirstlane(ctl_status);
         for (int k = 0; k < p; k++)
-            if (status == kLocOk && !isfinite(xs[k])) status = kLocNonfinite;
+            if (status == kLocOk && !isfinite(uniform(xs[k]))) status = kLocNonfinite;
         if (tid == 0) acc_pred[0] = acc_pred[1] = acc_pred[2] = 0.0;
 
         // the z row of slot s, entries [0, j), into dst (one lane)
@@ -206,8 +210,30 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 if (c * 8 < j)
 #pragma unroll
                     for (int u = 0; u < 8; u++) dst[c * 8 + u] = z[s][c * 8 + u];
-            for (int e = ZR; e < j; e++)
-                dst[e] = e < G0 ? zl[(e - ZR) * CAP + pos] : gz[(size_t)(e - G0) * CAP + pos];
+            // LDS and global columns in loops of their own (plain LDS and
+            // global accesses, several loads in flight)
+            const int jl = j < G0 ? j : G0;
+            int e = ZR;
+            for (; e + 4 <= jl; e += 4) {
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) v[u] = zl[(e + u - ZR) * CAP + pos];
+#pragma unroll
+                for (int u = 0; u < 4; u++) dst[e + u] = v[u];
+            }
+            for (; e < jl; e++) dst[e] = zl[(e - ZR) * CAP + pos];
+#pragma unroll 4
+            for (; e < j; e++) dst[e] = gz[(size_t)(e - G0) * CAP + pos];
+        };
+
+        // the step scalars of slot s, should it be chosen: s, 1 / lambda,
+        // w_h = cov / lambda, t_j = r / lambda with lambda = sqrt(s)
+        auto publish = [&](int s, double *dst) {
+            const double lam = sqrt(sv[s]);
+            dst[0] = sv[s];
+            dst[1] = 1.0 / lam;
+            dst[2] = cv[s] / lam;
+            dst[3] = ty[s] / lam;
         };
 
         int j = 0;
@@ -243,16 +269,12 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                     for (int s = 0; s < S; s++)
                         if (s == sb) {
                             put_row(s, j, zbp + w * zrow);
-                            pub[par][w][0] = sv[s];
-                            pub[par][w][1] = cv[s];
-                            pub[par][w][2] = ty[s];
+                            publish(s, pub[par][w]);
                         }
                 }
             } else if (tid == j) {  // pool position j: slot 0 of thread j
                 put_row(0, j, zbp + w * zrow);
-                pub[par][w][0] = sv[0];
-                pub[par][w][1] = cv[0];
-                pub[par][w][2] = ty[0];
+                publish(0, pub[par][w]);
                 red_i[par][w] = di[0];
             }
             __syncthreads();
@@ -264,8 +286,8 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 int32_t vi = lane < NW ? red_i[par][lane] : INT32_MAX;
                 int vk = lane < NW ? red_k[par][lane] : -1;
                 wave_argmax_ballot(v, vi, vk);
-                vbest = v;
-                wpos = vk;
+                vbest = uniform(v);
+                wpos = __builtin_amdgcn_readfirstlane(vk);
                 if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
                     status = kLocStepFail;
                     break;
@@ -273,7 +295,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
             }
             const int wt = wpos % TB, ws = wpos / TB;
             const int vw = wt >> 6;  // the winner's wave
-            const double sstar = pub[par][vw][0];
+            const double sstar = uniform(pub[par][vw][0]);
             if (!(sstar > 0.0) || !isfinite(sstar)) {
                 status = j < n0 ? kLocInitNotPd : kLocStepFail;
                 break;
@@ -284,13 +306,12 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                     if (s == ws) sv[s] = -1.0;  // retire the chosen slot
             }
             // step scalars, wave-uniform (scalar registers)
-            const double lam = uniform(sqrt(sstar));
-            const double ilam = uniform(1.0 / lam);
+            const double ilam = uniform(pub[par][vw][1]);
             const double *el = zbp + vw * zrow;
 
             // ===== (3) z_h and t = L^{-1} Y gain their entry j
-            const double wh = uniform(pub[par][vw][1] / lam);
-            const double tn = uniform(pub[par][vw][2] / lam);
+            const double wh = uniform(pub[par][vw][2]);
+            const double tn = uniform(pub[par][vw][3]);
             if (tid == 0) {
                 seldi[j] = red_i[par][vw];
                 alc_out[j] = vbest;
@@ -329,6 +350,7 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 }
             }
             const int jl = j < G0 ? j : G0;
+#pragma unroll 4
             for (int q = ZR; q < jl; q++) {
                 const double e = el[q];
 #pragma unroll
@@ -342,41 +364,59 @@ __global__ __launch_bounds__(TB) void alc_inc_kernel(IncArgs x)
                 for (int s = 0; s < S; s++) acc[s] = fma(col[s * TB], e, acc[s]);
             }
             // K(c, x*) from centred coordinates: |c - x*|^2 = |c'|^2 + |x*'|^2 - 2 c'.x*'
+            // (rows k >= p read row 0 and weigh it by zero, so that every load is
+            // unconditional and all of them are in flight together)
             double xw[kIncPmax];  // wave-uniform: held in scalar registers
 #pragma unroll
-            for (int k = 0; k < kIncPmax; k++) xw[k] = uniform(k < p ? cx[k * CAP + wpos] : 0.0);
+            for (int k = 0; k < kIncPmax; k++) {
+                const double v = uniform(cx[(k < p ? k : 0) * CAP + wpos]);
+                xw[k] = k < p ? v : 0.0;
+            }
             const double qw = uniform(cq[wpos]);
             // the entry index, as a scalar: the write below is a scalar branch, not
             // a select over every register column
             const int jc = __builtin_amdgcn_readfirstlane(j >> 3), ju = __builtin_amdgcn_readfirstlane(j & 7);
+            double wcs[S];
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 const int pos = tid + s * TB;
                 double dt = 0.0;
+                if (p > 4) {
 #pragma unroll
-                for (int k = 0; k < kIncPmax; k++)
-                    if (k < p) dt = fma(cx[k * CAP + pos], xw[k], dt);
+                    for (int k = 0; k < 8; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                } else if (p > 2) {
+#pragma unroll
+                    for (int k = 0; k < 4; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 2; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                }
                 const double r2 = fma(-2.0, dt, cq[pos] + qw);
                 const double kc = exp(r2 * nid);
                 const double wc = (kc - acc[s]) * ilam;
-                if (j < ZR) {
-#pragma unroll
-                    for (int c = 0; c < NCH; c++)
-                        if (c == jc)
-#pragma unroll
-                            for (int u = 0; u < 8; u++)
-                                if (u == ju) {
-                                    asm volatile("");  // keeps this a scalar branch, not a select per column
-                                    z[s][c * 8 + u] = wc;
-                                }
-                } else if (j < G0) {
-                    zl[(j - ZR) * CAP + pos] = wc;
-                } else {
-                    gz[(size_t)(j - G0) * CAP + pos] = wc;
+                wcs[s] = wc;
+                if (j >= ZR) {
+                    if (j < G0)
+                        zl[(j - ZR) * CAP + pos] = wc;
+                    else
+                        gz[(size_t)(j - G0) * CAP + pos] = wc;
                 }
                 sv[s] = fma(-wc, wc, sv[s]);
                 cv[s] = fma(-wc, wh, cv[s]);
                 ty[s] = fma(-wc, tn, ty[s]);
+            }
+            // register column j of every slot, behind one scalar branch tree
+            if (j < ZR) {
+#pragma unroll
+                for (int c = 0; c < NCH; c++)
+                    if (c == jc)
+#pragma unroll
+                        for (int u = 0; u < 8; u++)
+                            if (u == ju) {
+                                asm volatile("");  // keeps this a scalar branch, not a select per column
+#pragma unroll
+                                for (int s = 0; s < S; s++) z[s][c * 8 + u] = wcs[s];
+                            }
             }
         }
         __syncthreads();
