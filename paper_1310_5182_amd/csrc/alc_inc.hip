@@ -24,10 +24,12 @@
 // (q < ZR), in LDS columns (q < ZR + zl_cols) or in a per-workgroup global
 // workspace column (beyond), laid out [entry][position] so that every access
 // is a coalesced, lane-private one.  A step: each wave reduces the argmax of
-// its candidates and its best lane publishes that candidate's z row and
-// scalars in LDS (double-buffered by step parity); after one barrier every
-// wave combines the per-wave winners and every lane extends its own rows.
-// One barrier per step.
+// its candidates and its best lane publishes that candidate's step scalars in
+// LDS (double-buffered by step parity); after a barrier every wave combines
+// the per-wave winners, the winning lane writes its z row to LDS and, after a
+// second barrier, every lane extends its own rows.  (A row leaves its lane one
+// LDS instruction per two entries; writing only the winner's saves the LDS
+// pipe the rows of the other waves' proposals.)
 //
 // Locations come either one per workgroup (uniform n and N', grid = M) or
 // from a queue that persistent workgroups drain with an atomic counter
@@ -119,8 +121,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
     const AlcArgs &a = x.a;
 
     // Dynamic LDS: centred candidate coordinates [k][pos], their squared
-    // norms, z entries ZR.. [entry - ZR][pos], and each wave's best z row
-    // [parity][wave][entry].
+    // norms, z entries ZR.. [entry - ZR][pos], and the chosen point's z row
+    // [parity][entry].
     extern __shared__ double dyn[];
     double *cx = dyn;
     double *cq = cx + a.p * CAP;
@@ -239,9 +241,9 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
         int j = 0;
         for (; status == kLocOk && j < n; j++) {
             const int par = j & 1;
-            double *zbp = zb + (size_t)par * NW * zrow;
+            double *zbp = zb + (size_t)par * zrow;
             // ===== (1) every wave proposes its best candidate (forced pool order
-            // for the initial design) with its z row; one barrier
+            // for the initial design) and that candidate's step scalars; one barrier
             if (j >= n0) {
                 double bs = -1.0;
                 int32_t bi = INT32_MAX;
@@ -267,13 +269,9 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                     const int sb = bk / TB;
 #pragma unroll
                     for (int s = 0; s < S; s++)
-                        if (s == sb) {
-                            put_row(s, j, zbp + w * zrow);
-                            publish(s, pub[par][w]);
-                        }
+                        if (s == sb) publish(s, pub[par][w]);
                 }
             } else if (tid == j) {  // pool position j: slot 0 of thread j
-                put_row(0, j, zbp + w * zrow);
                 publish(0, pub[par][w]);
                 red_i[par][w] = di[0];
             }
@@ -300,14 +298,21 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 status = j < n0 ? kLocInitNotPd : kLocStepFail;
                 break;
             }
+            // only the chosen point's z row goes through LDS (each row is written
+            // by one lane, one LDS instruction per two entries): a second barrier
+            // instead of every wave writing its proposal's row
             if (tid == wt) {
 #pragma unroll
                 for (int s = 0; s < S; s++)
-                    if (s == ws) sv[s] = -1.0;  // retire the chosen slot
+                    if (s == ws) {
+                        if (j + 1 < n) put_row(s, j, zbp);
+                        sv[s] = -1.0;  // retire the chosen slot
+                    }
             }
+            if (j + 1 < n) __syncthreads();
             // step scalars, wave-uniform (scalar registers)
             const double ilam = uniform(pub[par][vw][1]);
-            const double *el = zbp + vw * zrow;
+            const double *el = zbp;
 
             // ===== (3) z_h and t = L^{-1} Y gain their entry j
             const double wh = uniform(pub[par][vw][2]);
@@ -468,10 +473,10 @@ struct Sched {
     // row slot holds n_max rounded up to a multiple of 8
     static int zrow(int n_max) { return (n_max + 7) & ~7; }
     // dynamic LDS bytes: p coordinates and a norm per position, zl LDS
-    // columns, and the double-buffered proposed rows of the waves
+    // columns, and the double-buffered row of the chosen point
     size_t lds(int p, int zl, int n_max) const
     {
-        return (size_t)cap() * 8 * ((size_t)p + 1 + (size_t)zl) + (size_t)2 * (tb / kWave) * zrow(n_max) * 8;
+        return (size_t)cap() * 8 * ((size_t)p + 1 + (size_t)zl) + (size_t)2 * zrow(n_max) * 8;
     }
     // LDS columns that fit, capped at the n_max - 1 - ZR that are needed; -1
     // if not even the coordinates fit
