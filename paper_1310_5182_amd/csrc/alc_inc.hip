@@ -229,13 +229,24 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
         };
 
         // the step scalars of slot s, should it be chosen: s, 1 / lambda,
-        // w_h = cov / lambda, t_j = r / lambda with lambda = sqrt(s)
+        // w_h = cov / lambda, t_j = r / lambda with lambda = sqrt(s).  1 / lambda
+        // is the hardware reciprocal square root refined by two Newton steps
+        // (h -> 1 / (2 lambda) and g -> lambda together), within an ulp or so;
+        // a NaN for s <= 0, which the chooser rejects by s itself.
         auto publish = [&](int s, double *dst) {
-            const double lam = sqrt(sv[s]);
-            dst[0] = sv[s];
-            dst[1] = 1.0 / lam;
-            dst[2] = cv[s] / lam;
-            dst[3] = ty[s] / lam;
+            const double sq = sv[s];
+            const double r0 = __builtin_amdgcn_rsq(sq);
+            double g = sq * r0, h = 0.5 * r0;
+            double e = fma(-g, h, 0.5);
+            g = fma(g, e, g);
+            h = fma(h, e, h);
+            e = fma(-g, h, 0.5);
+            h = fma(h, e, h);
+            const double il = 2.0 * h;
+            dst[0] = sq;
+            dst[1] = il;
+            dst[2] = cv[s] * il;
+            dst[3] = ty[s] * il;
         };
 
         int j = 0;
@@ -283,9 +294,14 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 double v = lane < NW ? red_s[par][lane] : -1.0;
                 int32_t vi = lane < NW ? red_i[par][lane] : INT32_MAX;
                 int vk = lane < NW ? red_k[par][lane] : -1;
-                wave_argmax_ballot(v, vi, vk);
-                vbest = uniform(v);
-                wpos = __builtin_amdgcn_readfirstlane(vk);
+                // NW <= 8 proposals: three exchange stages within each group of
+                // eight lanes leave lane 0 with the argmax (ties: smaller index)
+                static_assert(NW <= 8, "one group of eight lanes");
+                argmax_stage<0>(v, vi, vk);
+                argmax_stage<1>(v, vi, vk);
+                argmax_stage<2>(v, vi, vk);
+                vbest = readlane(v, 0);
+                wpos = __builtin_amdgcn_readlane(vk, 0);
                 if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
                     status = kLocStepFail;
                     break;
