@@ -138,7 +138,6 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
     __shared__ double alc_out[kIncNmax];
     __shared__ int32_t seldi[kIncNmax];
     __shared__ double xs[kIncPmax];
-    __shared__ double acc_pred[3];  // z_h.t, t.t, z_h.z_h so far (thread 0)
     __shared__ int ctl_status, ctl_loc;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -202,30 +201,17 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
         int status = __builtin_amdgcn_readfirstlane(ctl_status);
         for (int k = 0; k < p; k++)
             if (status == kLocOk && !isfinite(uniform(xs[k]))) status = kLocNonfinite;
-        if (tid == 0) acc_pred[0] = acc_pred[1] = acc_pred[2] = 0.0;
+        double ap0 = 0.0, ap1 = 0.0, ap2 = 0.0;  // z_h.t, t.t, z_h.z_h so far (wave 0)
 
-        // the z row of slot s, entries [0, j), into dst (one lane)
+        // the register entries of slot s's z row, [0, min(j, ZR)), into dst (one lane)
         auto put_row = [&](int s, int j, double *dst) {
-            const int pos = tid + s * TB;
 #pragma unroll
             for (int c = 0; c < NCH; c++)
                 if (c * 8 < j)
 #pragma unroll
                     for (int u = 0; u < 8; u++) dst[c * 8 + u] = z[s][c * 8 + u];
-            // LDS and global columns in loops of their own (plain LDS and
-            // global accesses, several loads in flight)
-            const int jl = j < G0 ? j : G0;
-            int e = ZR;
-            for (; e + 4 <= jl; e += 4) {
-                double v[4];
-#pragma unroll
-                for (int u = 0; u < 4; u++) v[u] = zl[(e + u - ZR) * CAP + pos];
-#pragma unroll
-                for (int u = 0; u < 4; u++) dst[e + u] = v[u];
-            }
-            for (; e < jl; e++) dst[e] = zl[(e - ZR) * CAP + pos];
-#pragma unroll 4
-            for (; e < j; e++) dst[e] = gz[(size_t)(e - G0) * CAP + pos];
+            // (entries from ZR on are read where they are kept, at the chosen
+            // position)
         };
 
         // the step scalars of slot s, should it be chosen: s, 1 / lambda,
@@ -289,6 +275,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             __syncthreads();
             // ===== (2) the winner: argmax of Delta, ties to the smaller design index
             int wpos = j;
+            int32_t wdi = -1;  // the chosen point's design index (from n0 on)
             double vbest = NAN;
             if (j >= n0) {
                 double v = lane < NW ? red_s[par][lane] : -1.0;
@@ -302,6 +289,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 argmax_stage<2>(v, vi, vk);
                 vbest = readlane(v, 0);
                 wpos = __builtin_amdgcn_readlane(vk, 0);
+                wdi = __builtin_amdgcn_readlane(vi, 0);
                 if (!(vbest >= 0.0) || wpos < 0) {  // no candidate with positive variance left
                     status = kLocStepFail;
                     break;
@@ -325,6 +313,16 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                         sv[s] = -1.0;  // retire the chosen slot
                     }
             }
+            // the chosen point's centred coordinates and squared norm, read while
+            // the winning lane writes its row (rows k >= p read row 0 and weigh
+            // it by zero, so that every load is unconditional)
+            double xw[kIncPmax];  // wave-uniform: held in scalar registers
+#pragma unroll
+            for (int k = 0; k < kIncPmax; k++) {
+                const double v = uniform(cx[(k < p ? k : 0) * CAP + wpos]);
+                xw[k] = k < p ? v : 0.0;
+            }
+            const double qw = uniform(cq[wpos]);
             if (j + 1 < n) __syncthreads();
             // step scalars, wave-uniform (scalar registers)
             const double ilam = uniform(pub[par][vw][1]);
@@ -334,11 +332,13 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             const double wh = uniform(pub[par][vw][2]);
             const double tn = uniform(pub[par][vw][3]);
             if (tid == 0) {
-                seldi[j] = red_i[par][vw];
+                seldi[j] = j >= n0 ? wdi : red_i[par][vw];
                 alc_out[j] = vbest;
-                acc_pred[0] = fma(wh, tn, acc_pred[0]);
-                acc_pred[1] = fma(tn, tn, acc_pred[1]);
-                acc_pred[2] = fma(wh, wh, acc_pred[2]);
+            }
+            if (w == 0) {
+                ap0 = fma(wh, tn, ap0);
+                ap1 = fma(tn, tn, ap1);
+                ap2 = fma(wh, wh, ap2);
             }
             if (j + 1 == n) continue;  // the design is complete: no more scoring
 
@@ -373,27 +373,18 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             const int jl = j < G0 ? j : G0;
 #pragma unroll 4
             for (int q = ZR; q < jl; q++) {
-                const double e = el[q];
+                const double e = zl[(q - ZR) * CAP + wpos];
 #pragma unroll
                 for (int s = 0; s < S; s++) acc[s] = fma(zl[(q - ZR) * CAP + tid + s * TB], e, acc[s]);
             }
 #pragma unroll 4
             for (int q = G0; q < j; q++) {
-                const double e = el[q];
+                const double e = gz[(size_t)(q - G0) * CAP + wpos];
                 const double *col = gz + (size_t)(q - G0) * CAP + tid;
 #pragma unroll
                 for (int s = 0; s < S; s++) acc[s] = fma(col[s * TB], e, acc[s]);
             }
             // K(c, x*) from centred coordinates: |c - x*|^2 = |c'|^2 + |x*'|^2 - 2 c'.x*'
-            // (rows k >= p read row 0 and weigh it by zero, so that every load is
-            // unconditional and all of them are in flight together)
-            double xw[kIncPmax];  // wave-uniform: held in scalar registers
-#pragma unroll
-            for (int k = 0; k < kIncPmax; k++) {
-                const double v = uniform(cx[(k < p ? k : 0) * CAP + wpos]);
-                xw[k] = k < p ? v : 0.0;
-            }
-            const double qw = uniform(cq[wpos]);
             // the entry index, as a scalar: the write below is a scalar branch, not
             // a select over every register column
             const int jc = __builtin_amdgcn_readfirstlane(j >> 3), ju = __builtin_amdgcn_readfirstlane(j & 7);
@@ -452,7 +443,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
         if (w == 0) {
             const bool ok = status == kLocOk;
             if (lane == 0) {
-                const double mu = acc_pred[0], psi = acc_pred[1], zz = acc_pred[2];
+                const double mu = ap0, psi = ap1, zz = ap2;
                 const double s2 = psi * (kappa - zz) / n;
                 if (a.mean) a.mean[m] = ok ? mu : NAN;
                 if (a.s2) a.s2[m] = ok ? s2 : NAN;
