@@ -209,6 +209,14 @@ def main() -> int:
                 lagp.alc_predict(X, Y, XX, n0, n, Np, d, g, prec, out=o)
 
             paths[prec] = (step, o)
+        if "fp64" in precs:
+            # the same float64 path as one tuned, graph-captured plan (NN variant
+            # and broadcast chosen by timing, before the timed region)
+            plan = lagp.Plan(X, Y, XX, n0, n, Np, d, g)
+            plan_info = plan.describe()
+            print(f"[bench] plan: {plan_info}", file=sys.stderr, flush=True)
+            paths["fp64_plan"] = (plan.launch, plan.out)
+            precs = precs + ["fp64_plan"]
 
     res = {}
     for prec in precs:
@@ -242,6 +250,8 @@ def main() -> int:
                                               out=o), args.steps)
     else:
         for prec in precs:
+            if prec == "fp64_plan":
+                continue  # the float64 kernel, timed as alc_fp64
             op = paths[prec][1]
             kms[f"alc_{prec}"] = timer.run(
                 lambda op=op, prec=prec: lagp.alc_from_pool(X, Y, XX, pool, n0, n, d, g, prec, out=op),
@@ -354,7 +364,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "mixed" else "f64",
         # every path timed, with the roofline figures of its own kernel
-        "paths": {k: dict(loc_per_s=v["loc_per_s"], alc_ms=kms.get(f"alc_{k}")) for k, v in res.items()},
+        "paths": {k: dict(loc_per_s=v["loc_per_s"], alc_ms=kms.get("alc_fp64" if k == "fp64_plan" else f"alc_{k}"))
+                  for k, v in res.items()},
         "data": "synthetic",
         "config": {"workload": f"config{cfg}: N={W.N} p={W.p} uniform design, M={M} locations, n0={n0}, "
                                + (f"n=U[20,100], N'=U[200,2000] per location" if cfg == 3 else

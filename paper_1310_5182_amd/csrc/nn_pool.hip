@@ -54,6 +54,9 @@ constexpr int kNnBlock = 256;
 constexpr int kNnWaves = kNnBlock / kWave;
 constexpr int kNnItems = 4;
 constexpr int kNnChunk = kNnBlock * kNnItems;
+// items whose row loads are in flight together (p <= 8; one at a time above,
+// where the registers of a second row would spill)
+constexpr int kNnBatchPmax = 8;
 constexpr int kNnMaxNp = 2048;
 
 __device__ __forceinline__ bool key_less(uint64_t k1, int32_t i1, uint64_t k2, int32_t i2)
@@ -344,8 +347,28 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
         // bit g * kNnItems + it: the row of item `it` passed for location g but
         // found the buffer full; it is tried again after the next selection
         uint32_t pend = 0;
+        // rows are loaded kNnBatch items at a time, all loads in flight together
+        // (a row index past the design reads the last row and is not used)
+        constexpr int kNnBatch = PF <= kNnBatchPmax ? 2 : 1;
 #pragma unroll
-        for (int it = 0; it < kNnItems; it++) {
+        for (int it0 = 0; it0 < kNnItems; it0 += kNnBatch) {
+        double xb[kNnBatch][F32 ? 1 : PF];
+        float xbf[kNnBatch][F32 ? PF : 1];
+#pragma unroll
+        for (int b = 0; b < kNnBatch; b++) {
+            const int64_t i = base + (it0 + b) * kNnBlock + threadIdx.x;
+            const int64_t ic = i < N ? i : N - 1;
+#pragma unroll
+            for (int k = 0; k < PF; k++) {
+                if constexpr (F32)
+                    xbf[b][k] = X32[ic * PF + k];
+                else
+                    xb[b][k] = X[ic * PF + k];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kNnBatch; b++) {
+            const int it = it0 + b;
             const int64_t i = base + it * kNnBlock + threadIdx.x;
             if (i < N) {
                 double xr[PF];
@@ -353,11 +376,11 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
                 float rmax = 0.0f;
                 if constexpr (F32) {
 #pragma unroll
-                    for (int k = 0; k < PF; k++) xrf[k] = X32[i * PF + k];
+                    for (int k = 0; k < PF; k++) xrf[k] = xbf[b][k];
                 } else {
 #pragma unroll
                     for (int k = 0; k < PF; k++) {
-                        xr[k] = X[i * PF + k];
+                        xr[k] = xb[b][k];
                         xrf[k] = (float)xr[k];
                     }
                 }
@@ -393,6 +416,7 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
                     }
                 }
             }
+        }
         }
         __syncthreads();
         // A full buffer: keep the Np smallest of its CAP keys, then insert the
@@ -846,17 +870,39 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
         if ((double)mindr[rc] * kMargin > td) break;
         int r = rc;  // the items' rows come in increasing order
         uint32_t pend = 0;
+        // two items at a time: both cell offsets, then both rows, in flight
+        // together (an item past the design or in a pruned cell reads row 0
+        // and is not used)
+        constexpr int kB = PF <= kNnBatchPmax ? 4 : 1;
 #pragma unroll
-        for (int it = 0; it < kNnItems; it++) {
-            const int64_t v = vb + it * kNnBlock + tid;
-            if (v < N) {
-                r = rank_from(pre, r, v);
-                if ((double)mindr[r] * kMargin <= td) {
-                    const int64_t row = gr.off[cellr[r]] + (v - pre[r]);
+        for (int it0 = 0; it0 < kNnItems; it0 += kB) {
+        bool use[kB];
+        int64_t rowb[kB];
+#pragma unroll
+        for (int b = 0; b < kB; b++) {
+            const int64_t v = vb + (it0 + b) * kNnBlock + tid;
+            const int64_t vc = v < N ? v : N - 1;
+            r = rank_from(pre, r, vc);
+            use[b] = v < N && (double)mindr[r] * kMargin <= td;
+            rowb[b] = gr.off[cellr[r]] + (vc - pre[r]);
+        }
+        float xb[kB][PF];
+#pragma unroll
+        for (int b = 0; b < kB; b++) {
+            const int64_t row = use[b] ? rowb[b] : 0;
+#pragma unroll
+            for (int k = 0; k < PF; k++) xb[b][k] = gr.x32[row * PF + k];
+        }
+#pragma unroll
+        for (int b = 0; b < kB; b++) {
+            const int it = it0 + b;
+            {
+                if (use[b]) {
+                    const int64_t row = rowb[b];
                     float xrf[PF], rmax = 0.0f;
 #pragma unroll
                     for (int k = 0; k < PF; k++) {
-                        xrf[k] = gr.x32[row * PF + k];
+                        xrf[k] = xb[b][k];
                         rmax = fmaxf(rmax, fabsf(xrf[k]));
                     }
                     float d32 = 0.0f;
@@ -882,6 +928,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
                     }
                 }
             }
+        }
         }
         __syncthreads();
         // a full buffer: as in nn_pool_kernel (the count changes only after a barrier)
