@@ -803,6 +803,21 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
     }
     constexpr float kSlope = 1.0f - 2.0f * PF * kU;
     constexpr float kConst = 40.0f * PF * kU;
+    // The screen's bound B on the magnitude of every coordinate, the row's and
+    // x's, from the design's bounding box (rounded up to float32, so that it is
+    // at least every float32 row coordinate) instead of each row's own maximum:
+    // a larger B only lets more rows through to the exact test.
+    float bd = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+        const double lo = gr.part[((size_t)kGridParts * p + k) * 2], hi = gr.part[((size_t)kGridParts * p + k) * 2 + 1];
+        const double mk = fmax(fabs(lo), fabs(hi));
+        float f = (float)mk;
+        if ((double)f < mk) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u);
+        bd = fmaxf(bd, f);
+    }
+    const float bB = fmaxf(bd, lmax);
+    const float cB = kConst * bB * bB;
 
     // ---- cells in order of the squared distance from x to their boxes
     for (int c = tid; c < C; c += kNnBlock) {
@@ -899,20 +914,16 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
             {
                 if (use[b]) {
                     const int64_t row = rowb[b];
-                    float xrf[PF], rmax = 0.0f;
+                    float xrf[PF];
 #pragma unroll
-                    for (int k = 0; k < PF; k++) {
-                        xrf[k] = xb[b][k];
-                        rmax = fmaxf(rmax, fabsf(xrf[k]));
-                    }
+                    for (int k = 0; k < PF; k++) xrf[k] = xb[b][k];
                     float d32 = 0.0f;
 #pragma unroll
                     for (int k = 0; k < PF; k++) {
                         const float t = xrf[k] - xf[k];
                         d32 = fmaf(t, t, d32);
                     }
-                    const float B = fmaxf(rmax, lmax);
-                    if (d32 * kSlope - kConst * B * B < tf) {
+                    if (d32 * kSlope - cB < tf) {
                         const int32_t i = gr.perm[row];
                         const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
                         const uint64_t key = __builtin_bit_cast(uint64_t, sd);
