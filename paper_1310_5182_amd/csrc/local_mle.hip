@@ -45,7 +45,7 @@ struct GpEval {
 // Per-location LDS workspace and the workgroup's view of it.
 struct GpBlock {
     double *M1;    // K, then A = K^{-1} (row stride S)
-    double *M2;    // Kd
+    double *M2;    // squared distances, then Kd
     double *xs;    // design rows [n][p]
     double *ys;    // responses [n]
     double *colk;  // sweep: pivot row (even pivots), then alpha
@@ -98,10 +98,11 @@ struct GpBlock {
             }
         for (int k = 0; k < n; k++) {
             double *v = (k & 1) ? rowk : colk;  // double-buffered pivot row
-            if (ta == (k & 15)) {
+            const int k0 = k >> 4, kr = k & 15;  // slot and thread row/column of pivot k
+            if (ta == kr) {
 #pragma unroll
                 for (int i = 0; i < 4; i++)
-                    if (ta + 16 * i == k)
+                    if (i == k0)  // uniform
 #pragma unroll
                         for (int j = 0; j < 4; j++)
                             if (tb + 16 * j < n) v[tb + 16 * j] = e[i][j];
@@ -117,21 +118,27 @@ struct GpBlock {
                 va[i] = ta + 16 * i < n ? v[ta + 16 * i] : 0.0;
                 vb[i] = tb + 16 * i < n ? v[tb + 16 * i] : 0.0;
             }
+            // every element takes A_ab - v_a v_b / p; row and column k are then
+            // overwritten (v / p, and -1/p on the diagonal) by the threads that
+            // hold them, behind a scalar branch on the slot and a lane mask
+            double sa[4];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int a = ta + 16 * i;
-                const double sa = va[i] * ip;
+            for (int i = 0; i < 4; i++) sa[i] = va[i] * ip;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int b = tb + 16 * j;
-                    if (a == k)
-                        e[i][j] = b == k ? -ip : vb[j] * ip;
-                    else if (b == k)
-                        e[i][j] = sa;
-                    else
-                        e[i][j] = fma(-sa, vb[j], e[i][j]);
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) e[i][j] = fma(-sa[i], vb[j], e[i][j]);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                if (i == k0) {  // uniform
+                    if (ta == kr)
+#pragma unroll
+                        for (int j = 0; j < 4; j++) e[i][j] = vb[j] * ip;
+                    if (tb == kr)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) e[r][i] = sa[r];
+                    if (ta == kr && tb == kr) e[i][i] = -ip;
                 }
-            }
         }
         // A = K^{-1} = minus the swept matrix
 #pragma unroll
@@ -151,8 +158,13 @@ struct GpBlock {
         GpEval e{NAN, NAN, NAN, NAN, false};
         const int ta = tid >> 4 & 15, tb = tid & 15;
         const double nid = -1.0 / d;
+        // K into M1; the squared distances are kept in M2 for the derivative pass
         for (int a = ta; a < n; a += 16)
-            for (int b = tb; b < n; b += 16) M1[a * S + b] = exp(r2(a, b) * nid) + (a == b ? g : 0.0);
+            for (int b = tb; b < n; b += 16) {
+                const double q = r2(a, b);
+                M2[a * S + b] = q;
+                M1[a * S + b] = exp(q * nid) + (a == b ? g : 0.0);
+            }
         __syncthreads();
         if (!invert()) return e;
         // alpha = A Y (in colk), psi, log|K|
@@ -168,13 +180,14 @@ struct GpBlock {
         e.ok = isfinite(e.nll);
         if (order == 0 || !e.ok) return e;
 
-        // Kd into M2; traces and quadratic forms in one pass over the elements
+        // Kd into M2 (over the squared distances); traces and quadratic forms in
+        // one pass over the elements
         const double d2i = 1.0 / (d * d), d3i = d2i / d;
         double s1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // tr(A Kd), tr(A Kdd), aKda, aKdda, tr A, a.a
         for (int a = ta; a < n; a += 16) {
             const double aa_ = colk[a];
             for (int b = tb; b < n; b += 16) {
-                const double q = r2(a, b);
+                const double q = M2[a * S + b];  // this thread's own element, from the K pass
                 const double c = exp(q * nid);
                 const double kd = c * q * d2i;
                 const double kdd = c * (q * q * d2i * d2i - 2.0 * q * d3i);
@@ -221,15 +234,17 @@ struct GpBlock {
             while (J >= T - I) J -= T - I++;
             J += I;
             const int a = 16 * I + r16, b = 16 * J + r16;
+            // indices past the design are clamped into it for the (unconditional)
+            // loads and their values replaced by zero
+            const int ah = a < n ? a : n - 1, bh = b < n ? b : n - 1;
             v4d pb = {0.0, 0.0, 0.0, 0.0}, pc = {0.0, 0.0, 0.0, 0.0};
             for (int kk = 0; kk < 4 * T; kk++) {
-                const int c = 4 * kk + k4;
+                const int c = 4 * kk + k4, ch = c < n ? c : n - 1;
                 const bool ac = a < n && c < n, bc = b < n && c < n;
                 // A-operand lanes hold row a, column c; B-operand lanes row c, column b
-                pb = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? M1[a * S + c] : 0.0, bc ? M2[c * S + b] : 0.0,
-                                                          pb, 0, 0, 0);
-                pc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? M2[a * S + c] : 0.0, bc ? M1[c * S + b] : 0.0,
-                                                          pc, 0, 0, 0);
+                const double a1 = M1[ah * S + ch], b2 = M2[ch * S + bh], a2 = M2[ah * S + ch], b1 = M1[ch * S + bh];
+                pb = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? a1 : 0.0, bc ? b2 : 0.0, pb, 0, 0, 0);
+                pc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac ? a2 : 0.0, bc ? b1 : 0.0, pc, 0, 0, 0);
             }
             const double wt = I == J ? 1.0 : 2.0;
 #pragma unroll
