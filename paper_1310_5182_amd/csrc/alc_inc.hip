@@ -62,7 +62,7 @@ struct IncArgs {
     double *gz;               // global z columns, gcols * CAP doubles per workgroup
     int gcols;
     int zl_cols;
-    int zrow;                 // LDS row length of a proposed z row (a.n rounded up to 8)
+    int zrow;                 // LDS row length of the chosen point's z row (a.n rounded up to 8)
 };
 
 // acc + z_0 l_0 + ... + z_7 l_7 in that order, fused multiply-adds, where l_u
@@ -476,7 +476,7 @@ constexpr size_t kDynLds = kLdsLimit - kStaticReserve;
 struct Sched {
     int tb, s, zr;
     constexpr int cap() const { return tb * s; }
-    // the proposed rows are copied in whole chunks of 8 register entries, so a
+    // the chosen row's register entries are copied in whole chunks of 8, so a
     // row slot holds n_max rounded up to a multiple of 8
     static int zrow(int n_max) { return (n_max + 7) & ~7; }
     // dynamic LDS bytes: p coordinates and a norm per position, zl LDS
