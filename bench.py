@@ -200,6 +200,21 @@ def main() -> int:
 
         paths["fp64"] = (step_mle, o4)
         precs = ["fp64"]
+        if args.only in ("both", "fp64"):
+            # the designs from a tuned, graph-captured plan, then the same MLE and prediction
+            plan = lagp.Plan(X, Y, XX, n0, n, Np, d, g)
+            plan_info = plan.describe()
+            print(f"[bench] plan: {plan_info}", file=sys.stderr, flush=True)
+            o4p = {}
+
+            def step_mle_plan():
+                op = plan.launch()
+                o4p.update(op)
+                o4p["mle"] = lagp.local_mle_d(X, Y, op["sel"], d0, g, 1e-3, 5.0, 100)
+                o4p["pred"] = lagp.local_predict(X, Y, op["sel"], XX, o4p["mle"]["d"], g)
+
+            paths["fp64_plan"] = (step_mle_plan, o4p)
+            precs = precs + ["fp64_plan"]
     else:
         precs = ["mixed", "fp64", "fp64_reform"] if args.only == "both" else [args.only]
         for prec in precs:
