@@ -57,6 +57,10 @@ static hipError_t run_path(const lagp_plan_s &P, int nnv, int bcast, hipStream_t
                        ? launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, 0, (float *)P.nnws)
                        : launch_nn_pool(P.a.X, P.a.N, P.a.p, P.a.XX, P.a.M, P.a.Np, P.pool, st, nnv, nullptr);
     if (e != hipSuccess) return e;
+    // uniform n, N' and d with every factor column on chip: one workgroup per
+    // location, no queue to classify and order
+    if (!P.n_per && !P.Np_per && !P.sel_off && !P.d_per && alc_inc_supported(P.a.p, P.a.Np, P.a.n))
+        return launch_alc_inc(P.a, st, bcast);
     return launch_alc_uneven(P.a, P.n_per, P.Np_per, P.sel_off, P.d_per, P.ws, P.ws_bytes, st, bcast);
 }
 
