@@ -232,7 +232,10 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
 /*
  * Plans: the whole float64 path with per-location sizes (lagp_nn_pool_ws
  * with Np_max into `pool`, then lagp_alc_uneven_from_pool) bound to fixed
- * buffers, autotuned and captured into one HIP graph.
+ * buffers, autotuned and captured into one HIP graph.  Without n_per,
+ * Np_per, sel_off and d_per, and when every factor column fits on chip, the
+ * designs run one workgroup per location instead of through the location
+ * queue (the same kernel and results).
  *
  * lagp_plan_workspace -- bytes of device workspace that lagp_plan_create
  *   needs: lagp_alc_uneven_workspace's, then lagp_nn_pool_workspace's.
