@@ -57,8 +57,10 @@ class Oracle:
         L.orc_nn_pool.restype = i32
         L.orc_gp_predict.argtypes = [P, P, i32, i32, P, f64, f64, P]
         L.orc_gp_predict.restype = i32
+        L.orc_gp_predict_b.argtypes = [P, P, i32, i32, P, f64, f64, P]
+        L.orc_gp_predict_b.restype = i32
         L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, P, f64,
-                              P, i32, i32, P, P, P, P, P, P, P, P, P]
+                              P, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_alc.restype = i32
         L.orc_alc_scores.argtypes = [P, i32, i32, P, i64, P, f64, f64, i32, P, P, P]
         L.orc_alc_scores.restype = i32
@@ -89,14 +91,24 @@ class Oracle:
         rc = self.L.orc_gp_predict(_p(D), _p(Yd), D.shape[0], D.shape[1], _p(x), d, g, _p(out))
         return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
 
+    def gp_predict_b(self, D, Yd, x, d: float, g: float) -> dict:
+        """gp_predict through K^{-1} grown row by row by the partitioned inverse
+        (eq. piedef): the paper's route, for the output route noise."""
+        D, Yd, x = _f64(np.atleast_2d(D)), _f64(Yd), _f64(x)
+        out = np.empty(5)
+        rc = self.L.orc_gp_predict_b(_p(D), _p(Yd), D.shape[0], D.shape[1], _p(x), d, g, _p(out))
+        return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
+
     def alc(self, X, Y, XX, pool, n0: int, n: int, d: float, g: float, *, Np: int | None = None,
             n_per=None, Np_per=None, forced=None, mode_b: bool = False, threads: int = 0,
             d_per=None) -> dict:
         """Greedy ALC local designs and local predictions for every location
         (d_per: an own lengthscale per location, overriding d).
 
-        Returns arrays: sel, dsel, dmax, amax, dsecond, nu (M x nmax), vtraj
-        (M x (nmax + 1)), mean, s2, var, v, psi (M), status (M).
+        Returns arrays: sel, dsel, dmax, amax, dsecond, nu, psitraj (M x nmax),
+        vtraj (M x (nmax + 1)), mean, s2, var, v, psi (M), status (M); with
+        mode_b also mean_b, s2_b, var_b, v_b, psi_b (M): the prediction on the
+        same design through the partitioned-inverse K_n^{-1} (eq. piedef).
         """
         X, Y, XX = _f64(X), _f64(Y), _f64(np.atleast_2d(XX))
         pool = _i32(np.atleast_2d(pool))
@@ -110,20 +122,25 @@ class Oracle:
             assert forced.shape == (M, nmax)
         sel = np.full((M, nmax), -1, np.int32)
         amax = np.full((M, nmax), -1, np.int32)
-        dsel, dmax, dsecond, nu = (np.full((M, nmax), np.nan) for _ in range(4))
+        dsel, dmax, dsecond, nu, psitraj = (np.full((M, nmax), np.nan) for _ in range(5))
         vtraj = np.full((M, nmax + 1), np.nan)
         pred = np.full((M, 5), np.nan)
+        pred_b = np.full((M, 5), np.nan)
         status = np.zeros(M, np.int32)
         d_per = None if d_per is None else _f64(d_per)
         rc = self.L.orc_alc(_p(X), _p(Y), X.shape[0], X.shape[1], _p(XX), M, _p(pool), Np_stride,
                             _p(Np_per), Np, _p(n_per), n, nmax, n0, d, _p(d_per), g, _p(forced), int(mode_b),
                             threads, _p(sel), _p(dsel), _p(dmax), _p(amax), _p(dsecond), _p(nu),
-                            _p(vtraj), _p(pred), _p(status))
+                            _p(vtraj), _p(pred), _p(status), _p(psitraj), _p(pred_b))
         if rc:
             raise ValueError(f"orc_alc: {STATUS.get(rc, rc)}")
-        return dict(sel=sel, dsel=dsel, dmax=dmax, amax=amax, dsecond=dsecond, nu=nu,
-                    vtraj=vtraj, mean=pred[:, 0], s2=pred[:, 1], var=pred[:, 2], v=pred[:, 3],
-                    psi=pred[:, 4], status=status)
+        out = dict(sel=sel, dsel=dsel, dmax=dmax, amax=amax, dsecond=dsecond, nu=nu, psitraj=psitraj,
+                   vtraj=vtraj, mean=pred[:, 0], s2=pred[:, 1], var=pred[:, 2], v=pred[:, 3],
+                   psi=pred[:, 4], status=status)
+        if mode_b:
+            for q, k in enumerate(("mean_b", "s2_b", "var_b", "v_b", "psi_b")):
+                out[k] = pred_b[:, q]
+        return out
 
     def lagp(self, X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, **kw) -> dict:
         """Nearest-neighbour pool, greedy ALC design and prediction for every location."""
@@ -193,6 +210,10 @@ def nn_pool(*a, **k):
 
 def gp_predict(*a, **k):
     return default().gp_predict(*a, **k)
+
+
+def gp_predict_b(*a, **k):
+    return default().gp_predict_b(*a, **k)
 
 
 def alc(*a, **k):

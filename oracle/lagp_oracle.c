@@ -239,11 +239,13 @@ typedef struct {
     double *dsecond;  /* runner-up score (NaN if none)                       */
     double *nu;       /* route noise max|dA - dB| / dmax (NaN if mode B off) */
     double *vtraj;    /* v_j(x) before step j, and v_n at index n (n + 1)   */
+    double *psitraj;  /* psi_j = Y_j^T K_j^{-1} Y_j before step j (0 at j=0) */
     double pred[5];   /* mean, s2, V, v, psi on the final design             */
+    double pred_b[5]; /* the same from the mode-B inverse (NaN if mode B off) */
 } orc_trace;
 
 typedef struct {
-    double *K, *L, *h, *zh, *kc, *zc, *Kinv, *Kinv2, *u, *gv, *Dn, *Yn;
+    double *K, *L, *h, *zh, *kc, *zc, *Kinv, *Kinv2, *u, *gv, *Dn, *Yn, *yj, *ty;
     uint8_t *chosen;
 } orc_work;
 
@@ -262,16 +264,18 @@ static int work_alloc(orc_work *w, int n, int Np, int p)
     w->gv = (double *)malloc(sizeof(double) * n);
     w->Dn = (double *)malloc(sizeof(double) * (size_t)n * p);
     w->Yn = (double *)malloc(sizeof(double) * n);
+    w->yj = (double *)malloc(sizeof(double) * n);
+    w->ty = (double *)malloc(sizeof(double) * n);
     w->chosen = (uint8_t *)malloc((size_t)Np);
     return w->K && w->L && w->Kinv && w->Kinv2 && w->h && w->zh && w->kc && w->zc && w->u &&
-           w->gv && w->Dn && w->Yn && w->chosen;
+           w->gv && w->Dn && w->Yn && w->yj && w->ty && w->chosen;
 }
 
 static void work_free(orc_work *w)
 {
     free(w->K); free(w->L); free(w->Kinv); free(w->Kinv2); free(w->h); free(w->zh);
     free(w->kc); free(w->zc); free(w->u); free(w->gv); free(w->Dn); free(w->Yn);
-    free(w->chosen);
+    free(w->yj); free(w->ty); free(w->chosen);
 }
 
 /* Mode B: grow K^{-1} (j x j, row-major, stride j) to (j+1) x (j+1) with the
@@ -294,6 +298,49 @@ static int piedef_grow(const double *Kinv, double *Kout, const double *kp, doubl
     }
     Kout[j * J + j] = m;
     return 0;
+}
+
+/* Mode B prediction on a fixed design (eqs. predgp, preds2): K_n^{-1} grown
+ * row by row over the design in the given order by the partitioned inverse
+ * (eq. piedef), then mu = h^T K^{-1} Y, psi = Y^T K^{-1} Y, v = kappa -
+ * h^T K^{-1} h.  out as for orc_gp_predict.  Returns 0, or 1 if a Schur
+ * complement is not positive. */
+int orc_gp_predict_b(const double *D, const double *Yd, int n, int p, const double *x,
+                     double d, double g, double *out)
+{
+    const double kappa = 1.0 + g;
+    double *A = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *B = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *kp = (double *)malloc(sizeof(double) * (size_t)n);
+    double *u = (double *)malloc(sizeof(double) * (size_t)n);
+    double *gv = (double *)malloc(sizeof(double) * (size_t)n);
+    double *h = (double *)malloc(sizeof(double) * (size_t)n);
+    int rc = 0;
+    for (int j = 0; j < n && rc == 0; j++) {
+        for (int a = 0; a < j; a++) kp[a] = kern(D + (size_t)a * p, D + (size_t)j * p, p, d);
+        if (piedef_grow(A, B, kp, kappa, u, gv, j)) rc = 1;
+        double *t = A; A = B; B = t;
+    }
+    if (rc) {
+        for (int q = 0; q < 5; q++) out[q] = NAN;
+    } else {
+        double mu = 0.0, psi = 0.0, hwh = 0.0;
+        for (int a = 0; a < n; a++) h[a] = kern(D + (size_t)a * p, x, p, d);
+        for (int a = 0; a < n; a++) {
+            double alpha_a = dot(A + (size_t)a * n, Yd, n);
+            mu += h[a] * alpha_a;
+            psi += Yd[a] * alpha_a;
+            hwh += h[a] * dot(A + (size_t)a * n, h, n);
+        }
+        double v = kappa - hwh, s2 = psi * v / n;
+        out[0] = mu;
+        out[1] = s2;
+        out[2] = n > 2 ? s2 * n / (n - 2) : NAN;
+        out[3] = v;
+        out[4] = psi;
+    }
+    free(A); free(B); free(kp); free(u); free(gv); free(h);
+    return rc;
 }
 
 /* Mode B score, eq. dxy term by term:
@@ -324,12 +371,12 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
     for (int k = 0; k < p; k++)
         if (!isfinite(x[k])) return ORC_NONFINITE;
     memset(w->chosen, 0, (size_t)Np);
-    for (int q = 0; q < 5; q++) tr->pred[q] = NAN;
+    for (int q = 0; q < 5; q++) tr->pred[q] = tr->pred_b[q] = NAN;
     int32_t *slot_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)n); /* pool slot of X_j rows */
     int rc = ORC_OK;
 
     for (int j = 0; j < n; j++) {
-        tr->dsel[j] = tr->dmax[j] = tr->dsecond[j] = tr->nu[j] = tr->vtraj[j] = NAN;
+        tr->dsel[j] = tr->dmax[j] = tr->dsecond[j] = tr->nu[j] = tr->vtraj[j] = tr->psitraj[j] = NAN;
         tr->amax[j] = -1;
         tr->sel[j] = -1;
     }
@@ -347,12 +394,16 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
                     w->K[a * j + b] = kern(xa, X + (int64_t)pool[slot_of[b]] * p, p, d);
                 w->K[a * j + a] += g;
                 w->h[a] = kern(xa, x, p, d);
+                w->yj[a] = Y[pool[slot_of[a]]];
             }
             if (cholesky(w->K, w->L, j)) { rc = j <= n0 ? ORC_INIT_NOT_PD : ORC_STEP_FAIL; break; }
             forward_solve(w->L, w->h, w->zh, j);
+            /* psi_j = Y_j^T K_j^{-1} Y_j = |L_j^{-1} Y_j|^2 (Sec. 2.1 eq. preds2) */
+            forward_solve(w->L, w->yj, w->ty, j);
         }
         double vj = kappa - (j > 0 ? dot(w->zh, w->zh, j) : 0.0);
         tr->vtraj[j] = vj;
+        tr->psitraj[j] = j > 0 ? dot(w->ty, w->ty, j) : 0.0;
 
         int take_slot = -1;
         if (j < n0) {
@@ -435,6 +486,25 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
         }
         if (orc_gp_predict(w->Dn, w->Yn, n, p, x, d, g, tr->pred)) rc = ORC_STEP_FAIL;
         else tr->vtraj[n] = tr->pred[3];
+        /* Mode B: the same prediction from K_n^{-1} as grown by eq. piedef
+         * (eqs. predgp, preds2 with the explicit inverse): the output route noise. */
+        if (rc == ORC_OK && mode_b) {
+            double mu = 0.0, psi = 0.0, hwh = 0.0;
+            for (int a = 0; a < n; a++) w->h[a] = kern(w->Dn + (size_t)a * p, x, p, d);
+            for (int a = 0; a < n; a++) {
+                double alpha_a = dot(Kinv + (size_t)a * n, w->Yn, n);
+                double wa = dot(Kinv + (size_t)a * n, w->h, n);
+                mu += w->h[a] * alpha_a;
+                psi += w->Yn[a] * alpha_a;
+                hwh += w->h[a] * wa;
+            }
+            const double v = kappa - hwh, scale = psi * v / n;
+            tr->pred_b[0] = mu;
+            tr->pred_b[1] = scale;
+            tr->pred_b[2] = n > 2 ? scale * n / (n - 2) : NAN;
+            tr->pred_b[3] = v;
+            tr->pred_b[4] = psi;
+        }
     }
     free(slot_of);
     return rc;
@@ -449,13 +519,19 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
  * forced: NULL, or M x n_stride sequences to evaluate instead of choosing.
  * Per-step outputs are M x n_stride (row m holds n_m entries); vtraj is
  * M x (n_stride + 1); pred is M x 5.  Any per-step output may be NULL.
+ * psitraj (M x n_stride): psi_j = Y_j^T K_j^{-1} Y_j before step j, the
+ * global variance estimate of the normalisation of Sec. 3.1 (Fig. 3 step 9).
+ * pred_b (M x 5): with mode_b, pred recomputed from the K_n^{-1} that the
+ * partitioned-inverse update (eq. piedef) built along the design, i.e. the
+ * output of the paper's route; its gap to pred measures the output route
+ * noise.  NaN without mode_b.
  */
 int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX, int64_t M,
             const int32_t *pool, int Np_stride, const int32_t *Np_per, int Np,
             const int32_t *n_per, int n, int n_stride, int n0, double d, const double *d_per, double g,
             const int32_t *forced, int mode_b, int nthreads,
             int32_t *sel, double *dsel, double *dmax, int32_t *amax, double *dsecond,
-            double *nu, double *vtraj, double *pred, int32_t *status)
+            double *nu, double *vtraj, double *pred, int32_t *status, double *psitraj, double *pred_b)
 {
     if (!(d > 0.0) || !(g > 0.0) || !isfinite(d) || !isfinite(g) || p < 1 || n0 < 1)
         return ORC_BAD_ARGS;
@@ -468,7 +544,7 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
         int ok = work_alloc(&w, n_stride, Np_stride, p);
         int32_t *t_sel = (int32_t *)malloc(sizeof(int32_t) * n_stride);
         int32_t *t_amax = (int32_t *)malloc(sizeof(int32_t) * n_stride);
-        double *t_d = (double *)malloc(sizeof(double) * n_stride * 4);
+        double *t_d = (double *)malloc(sizeof(double) * n_stride * 5);
         double *t_v = (double *)malloc(sizeof(double) * (n_stride + 1));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t m = 0; m < M; m++) {
@@ -476,7 +552,7 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
             int Npm = Np_per ? Np_per[m] : Np;
             const double dm = d_per ? d_per[m] : d;  /* the location's own lengthscale */
             orc_trace tr = {t_sel, t_d, t_d + n_stride, t_amax, t_d + 2 * n_stride,
-                            t_d + 3 * n_stride, t_v, {0}};
+                            t_d + 3 * n_stride, t_v, t_d + 4 * n_stride, {0}, {0}};
             int rc;
             if (!ok || nm > n_stride || Npm > Np_stride || nm > Npm || n0 > nm || Npm > N || !(dm > 0.0) ||
                 !isfinite(dm))
@@ -486,13 +562,13 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
                              forced ? forced + m * (int64_t)n_stride : NULL, mode_b, &tr, &w);
             if (rc == ORC_BAD_ARGS) {
                 for (int j = 0; j < n_stride; j++) { t_sel[j] = -1; t_amax[j] = -1; }
-                for (int j = 0; j < 4 * n_stride; j++) t_d[j] = NAN;
+                for (int j = 0; j < 5 * n_stride; j++) t_d[j] = NAN;
                 for (int j = 0; j <= n_stride; j++) t_v[j] = NAN;
-                for (int q = 0; q < 5; q++) tr.pred[q] = NAN;
+                for (int q = 0; q < 5; q++) tr.pred[q] = tr.pred_b[q] = NAN;
                 nm = n_stride;
             }
             if (rc != ORC_OK)
-                for (int q = 0; q < 5; q++) tr.pred[q] = NAN;
+                for (int q = 0; q < 5; q++) tr.pred[q] = tr.pred_b[q] = NAN;
             int64_t o = m * (int64_t)n_stride;
             for (int j = 0; j < nm; j++) {
                 if (sel) sel[o + j] = t_sel[j];
@@ -501,11 +577,14 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
                 if (amax) amax[o + j] = t_amax[j];
                 if (dsecond) dsecond[o + j] = t_d[2 * n_stride + j];
                 if (nu) nu[o + j] = t_d[3 * n_stride + j];
+                if (psitraj) psitraj[o + j] = t_d[4 * n_stride + j];
             }
             if (vtraj)
                 for (int j = 0; j <= nm; j++) vtraj[m * (int64_t)(n_stride + 1) + j] = t_v[j];
             if (pred)
                 for (int q = 0; q < 5; q++) pred[m * 5 + q] = tr.pred[q];
+            if (pred_b)
+                for (int q = 0; q < 5; q++) pred_b[m * 5 + q] = tr.pred_b[q];
             if (status) status[m] = rc;
         }
         if (ok) work_free(&w);

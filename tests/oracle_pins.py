@@ -19,7 +19,15 @@ What pins what:
   design_point      - at a design point v = 2g - g^2 (K^{-1})_ii -> 0 with g
   predict_textbook  - local prediction = eqs. predgp/preds2 via numpy.solve
   route_b           - the paper's partitioned-inverse route (eq. piedef) and the
-                      literal three-term eq. dxy agree with mode A
+                      literal three-term eq. dxy agree with mode A; the
+                      prediction from its K_n^{-1} (mean_b, s2_b, ...) agrees
+                      with mode A and with numpy.solve where K_n is well
+                      conditioned (the output route noise is then ~ eps)
+  predict_b         - the fixed-design prediction through the partitioned
+                      inverse = numpy.solve (eqs. predgp, preds2, piedef)
+  psi_trajectory    - psi_j = Y_j^T K_j^{-1} Y_j at every step (the global
+                      variance estimate of the normalised score, Sec. 3.1)
+                      = numpy.solve on the step's design
   forced            - evaluating a given sequence reproduces the free run
   nll_textbook      - negative log of eq. gpk = slogdet/solve form, and = the
                       marginal over the scale computed by quadrature (pins
@@ -27,6 +35,12 @@ What pins what:
   nll_derivatives_fd- d/dd, d/dg and d2/dd2 = central finite differences
   mle_optimality    - the Newton MLE is a stationary point (or a bound with
                       the gradient pointing out) and beats a fine local grid
+  mle_global        - the Newton MLE equals the global minimiser of the NLL
+                      over [1e-3, 5] found by a 2000-point log grid refined by
+                      golden-section search (or, where the likelihood has
+                      several local minima, is reported as a local one)
+  local_mle_batched - the batched MLE over many designs = the single-design
+                      MLE of each gathered design
   scores_brute      - batch scores of many candidates against one design (both
                       routes) = brute force v_j - v_{j+1}; K_j^{-1} K_j = I and
                       h = K(X_j, x) from numpy; the one-point closed form
@@ -114,9 +128,14 @@ def tie_rule(orc):
         # twins are adjacent in the pool, smaller index first
         for s in range(0, Np - 1, 2):
             assert P[s] + 60 == P[s + 1] or P[s] == P[s + 1] - 60
-        chosen = out["sel"][m, n0:]
-        # the first greedy pick is the smaller twin of a tied pair
-        assert chosen[0] < 60
+        # twins score exactly alike while both are candidates (identical
+        # coordinates give bit-identical kernel values), so the larger twin can
+        # only be picked once the smaller one is in the design
+        sel = list(out["sel"][m])
+        for j in range(n0, n):
+            if sel[j] >= 60:
+                assert sel[j] - 60 in sel[:j], (m, j, sel)
+        assert out["sel"][m, n0] < 60
 
 
 def invariants(orc):
@@ -216,6 +235,45 @@ def route_b(orc):
     nu = out["nu"][:, 6:]
     assert np.all(np.isfinite(nu))
     assert np.max(nu) < 1e-9, np.max(nu)
+    # the prediction through the partitioned-inverse K_n^{-1}: equal to mode A
+    # and to numpy.solve at this conditioning (cond(K_n) ~ 1e3)
+    for m in range(W.M):
+        ref = brute.predict(W.X[out["sel"][m]], W.Y[out["sel"][m]], W.XX[m], W.d, W.g)
+        for k in ("mean", "s2", "var", "v", "psi"):
+            assert _rel(out[k + "_b"][m], out[k][m]) < 1e-10, (m, k)
+            assert _rel(out[k + "_b"][m], ref[k]) < 1e-9, (m, k)
+    plain = orc.lagp(W.X, W.Y, W.XX, 6, 30, 300, W.d, W.g)
+    assert "mean_b" not in plain
+
+
+def predict_b(orc):
+    r = np.random.default_rng(19)
+    for n, p, d, g in ((1, 2, 0.3, 1e-2), (5, 1, 0.3, 1e-3), (17, 3, 0.7, 1e-4), (40, 4, 0.25, 1e-5)):
+        D = r.random((n, p))
+        Yd = np.cos(3 * D).sum(axis=1) + r.normal(0, 0.1, n)
+        x = r.random(p)
+        got = orc.gp_predict_b(D, Yd, x, d, g)
+        ref = brute.predict(D, Yd, x, d, g)
+        assert got["status"] == 0
+        for k in ("mean", "s2", "v", "psi"):
+            assert _rel(got[k], ref[k]) < 1e-7, (n, k)
+        if n > 2:
+            assert _rel(got["var"], ref["var"]) < 1e-7
+
+
+def psi_trajectory(orc):
+    W = workloads.make(2, N=3000, M=3)
+    n0, n = 6, 20
+    out = orc.lagp(W.X, W.Y, W.XX, n0, n, 200, W.d, W.g)
+    for m in range(W.M):
+        assert out["psitraj"][m, 0] == 0.0
+        for j in (1, n0, 13, n - 1):
+            D, Yd = W.X[out["sel"][m, :j]], W.Y[out["sel"][m, :j]]
+            K = brute.corr(D, D, W.d) + W.g * np.eye(j)
+            want = Yd @ np.linalg.solve(K, Yd)
+            assert _rel(out["psitraj"][m, j], want) < 1e-9, (m, j)
+        # psi of the last step's design grows by one term into the prediction's psi
+        assert out["psi"][m] >= out["psitraj"][m, n - 1]
 
 
 def forced(orc):
@@ -277,6 +335,71 @@ def mle_optimality(orc):
         # no point of a fine grid around the optimum does better
         for t in np.geomspace(max(dmin, dh / 1.5), min(dmax, dh * 1.5), 61):
             assert orc.nll(D, Yd, t, W.g)["nll"] >= f["nll"] - 1e-9 * abs(f["nll"])
+
+
+def _golden(f, a, b, tol=1e-13):
+    """Golden-section minimum of a unimodal f on [a, b] (log-d coordinates)."""
+    phi = (math.sqrt(5.0) - 1.0) / 2.0
+    c, e = b - phi * (b - a), a + phi * (b - a)
+    fc, fe = f(c), f(e)
+    while b - a > tol * max(1.0, abs(a) + abs(b)):
+        if fc <= fe:
+            b, e, fe = e, c, fc
+            c = b - phi * (b - a)
+            fc = f(c)
+        else:
+            a, c, fc = c, e, fe
+            e = a + phi * (b - a)
+            fe = f(e)
+    return (a + b) / 2.0
+
+
+def mle_global(orc):
+    W = workloads.make(4, N=4000, M=6)
+    out = orc.lagp(W.X, W.Y, W.XX, 6, 30, 300, 0.2, W.g)
+    dmin, dmax = 1e-3, 5.0
+    grid = np.geomspace(dmin, dmax, 2000)
+    local = 0
+    for m in range(W.M):
+        D, Yd = W.X[out["sel"][m]], W.Y[out["sel"][m]]
+        res = orc.mle_d(D, Yd, 0.2, W.g, dmin, dmax)
+        assert res["status"] == 0, res
+        f = np.array([brute.nll(D, Yd, t, W.g) for t in grid])
+        i = int(np.argmin(f))
+        if i == 0 or i == len(grid) - 1:
+            d_glob = grid[i]
+        else:
+            u = _golden(lambda lu: brute.nll(D, Yd, math.exp(lu), W.g), math.log(grid[i - 1]),
+                        math.log(grid[i + 1]))
+            d_glob = math.exp(u)
+        f_glob = brute.nll(D, Yd, d_glob, W.g)
+        f_newton = brute.nll(D, Yd, res["d"], W.g)
+        if f_newton <= f_glob + 1e-10 * max(1.0, abs(f_glob)):
+            # the Newton optimum is the global one; interior optima agree in d
+            if dmin < d_glob < dmax:
+                assert abs(res["d"] - d_glob) <= 1e-6 * d_glob, (m, res["d"], d_glob)
+            else:
+                assert res["d"] == d_glob, (m, res["d"], d_glob)
+        else:
+            # a local minimum: it must still be one (a grid neighbourhood cannot improve it)
+            local += 1
+            for t in np.geomspace(res["d"] / 1.01, res["d"] * 1.01, 21):
+                if dmin <= t <= dmax:
+                    assert brute.nll(D, Yd, t, W.g) >= f_newton - 1e-10 * abs(f_newton)
+    # the greedy designs of this workload have a single minimum in d
+    assert local == 0, local
+
+
+def local_mle_batched(orc):
+    W = workloads.make(4, N=3000, M=5)
+    out = orc.lagp(W.X, W.Y, W.XX, 6, 20, 200, 0.2, W.g)
+    d0 = np.array([0.2, 0.05, 1.0, 3.0, 0.2])
+    b = orc.local_mle(W.X, W.Y, out["sel"], d0, W.g, 1e-3, 5.0, 100, threads=2)
+    for m in range(W.M):
+        s = out["sel"][m]
+        one = orc.mle_d(W.X[s], W.Y[s], float(d0[m]), W.g, 1e-3, 5.0, 100)
+        for k in ("d", "nll", "iters", "status"):
+            assert one[k] == b[k][m], (m, k, one[k], b[k][m])
 
 
 def scores_brute(orc):
@@ -342,5 +465,6 @@ def per_location_d(orc):
 
 
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
-       special_cases, design_point, predict_textbook, route_b, forced, nll_textbook,
-       nll_derivatives_fd, mle_optimality, scores_brute, scores_greedy, per_location_d]
+       special_cases, design_point, predict_textbook, route_b, predict_b, psi_trajectory, forced,
+       nll_textbook, nll_derivatives_fd, mle_optimality, mle_global, local_mle_batched, scores_brute,
+       scores_greedy, per_location_d]

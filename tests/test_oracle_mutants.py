@@ -54,6 +54,18 @@ MUTANTS = {
     "dg_form": ("out[2] = 0.5 * trA - 0.5 * n * aa / psi;", "out[2] = 0.5 * trA - 0.5 * n * aKda / psi;"),
     # second derivative missing the psi^2 term
     "d2_missing_term": ("+ aKda * aKda / (psi * psi));", ");"),
+    # mode-B prediction: mean from Y instead of K(X_n, x)
+    "pred_b_mean": ("                mu += w->h[a] * alpha_a;", "                mu += w->Yn[a] * alpha_a;"),
+    # fixed-design mode-B prediction: variance term with the wrong vector
+    "predict_b_hwh": ("hwh += h[a] * dot(A + (size_t)a * n, h, n);", "hwh += h[a] * dot(A + (size_t)a * n, Yd, n);"),
+    # psi trajectory from Y_j^T Y_j
+    "psitraj_plain": ("tr->psitraj[j] = j > 0 ? dot(w->ty, w->ty, j) : 0.0;",
+                      "tr->psitraj[j] = j > 0 ? dot(w->yj, w->yj, j) : 0.0;"),
+    # batched MLE gathering the first location's responses for every design
+    "local_mle_gather": ("Yn[a] = Y[sel[m * n + a]];", "Yn[a] = Y[sel[a]];"),
+    # Newton iteration stopping on the first backtracking success without moving on
+    "mle_one_step": ("        if (moved <= 1e-10 * d) { status = 0; it++; break; }",
+                     "        status = 0; it++; break;"),
 }
 
 
