@@ -174,15 +174,96 @@ lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double
                             int32_t precision, double *delta, void *stream);
 
 /*
- * lagp_alc_predict -- the whole hot path: lagp_nn_pool into `pool`
- * (caller-allocated M x Np int32, left holding the pools), then
- * lagp_alc_from_pool.  Arguments as above.
+ * ---------------------------------------------------------------------------
+ * The whole hot path in one call: problem and outputs as structs.
+ *
+ * Every struct begins with struct_size, which the caller sets to
+ * sizeof(struct) as compiled against this header: the library rejects any
+ * other value with LAGP_EINVAL (an ABI guard: a caller built against another
+ * layout of the structs fails loudly instead of passing shifted fields).
+ * lagp_abi_version() returns LAGP_ABI_VERSION of the library.
  */
-lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_t p,
-                             const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
-                             double d, double g, int32_t precision, int32_t *pool,
-                             double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                             double *alc32, int32_t *status, int32_t *guard, void *stream);
+#define LAGP_ABI_VERSION 2
+
+/* lagp_problem.flags */
+#define LAGP_NORMALIZE_ALC 1u  /* report each selected point's score multiplied */
+                               /* by psi_j / (j - 2), psi_j = Y_j^T K_j^{-1} Y_j */
+                               /* of the design it was chosen for: the          */
+                               /* normalisation by the global variance estimate  */
+                               /* of Sec. 3.1 (Fig. 3 step 9).  The choices are  */
+                               /* unchanged (the factor is positive and common   */
+                               /* to all candidates of a step).  Needs n0 >= 3.  */
+#define LAGP_NN_BRUTE 2u       /* pools by streaming the whole design for every */
+                               /* location (lagp_nn_pool) instead of the grid of */
+                               /* lagp_nn_pool_ws; the pools are identical       */
+
+typedef struct lagp_problem {
+    uint32_t struct_size;      /* = sizeof(lagp_problem)                          */
+    uint32_t flags;            /* LAGP_NORMALIZE_ALC | LAGP_NN_BRUTE              */
+    const double *X;           /* [N x p] design                                   */
+    const double *Y;           /* [N] responses (used raw: zero-mean GP)           */
+    const double *XX;          /* [M x p] predictive locations                     */
+    int64_t N, M;              /* 1 <= N < 2^31; M >= 0 (M = 0: nothing to do)     */
+    int32_t p;                 /* 1 <= p <= 8                                       */
+    int32_t n0;                /* start size: the n0 nearest (Fig. 1 step 2a)      */
+    int32_t n;                 /* final design size, or the largest n_per[m]       */
+    int32_t Np;                /* candidate pool size N', or the largest Np_per[m] */
+    const int32_t *n_per;      /* [M] per-location n, or NULL (n everywhere)       */
+    const int32_t *Np_per;     /* [M] per-location N', or NULL (Np everywhere)     */
+    const double *d_per;       /* [M] per-location lengthscale, or NULL (d)        */
+    double d, g;               /* lengthscale and nugget, finite and > 0           */
+    int32_t precision;         /* LAGP_FP64, LAGP_MIXED or LAGP_FP64_REFORM        */
+    int32_t reserved;          /* 0                                                */
+} lagp_problem;
+
+typedef struct lagp_outputs {
+    uint32_t struct_size;      /* = sizeof(lagp_outputs)                          */
+    uint32_t reserved;         /* 0                                                */
+    double *mean, *s2, *var;   /* [M] each, nullable: eqs. predgp, preds2 (N -> n) */
+    int32_t *sel;              /* design indices, required: row m at sel_off[m],  */
+                               /* or at m * n padded with -1 past n_per[m]         */
+    const int64_t *sel_off;    /* [M + 1] int64 row offsets of sel / alc / alc32,  */
+                               /* or NULL                                          */
+    double *alc;               /* nullable: score of each added point (eq. dxy),   */
+                               /* NaN before n0 and in padding                     */
+    double *alc32;             /* nullable: LAGP_MIXED float32 score of that point */
+    int32_t *pool;             /* [M x Np] nullable: the candidate pools; NULL     */
+                               /* keeps them in the workspace                      */
+    int32_t *status;           /* [M] nullable: LAGP_LOC_* codes                   */
+    int32_t *guard;            /* [M] nullable: steps of the location decided in   */
+                               /* float64 under LAGP_MIXED (see below); 0 else     */
+} lagp_outputs;
+
+/*
+ * lagp_alc_workspace -- bytes of device workspace that lagp_alc_predict and
+ *   lagp_plan_create need for this problem on the current device: the grid of
+ *   the design (unless LAGP_NN_BRUTE), the location queues and factor-row
+ *   entries of per-location designs, and room for the M x Np pools (used
+ *   only when outputs->pool is NULL).  Arguments are checked as by
+ *   lagp_alc_predict.
+ *
+ * lagp_alc_predict -- for every location: the N' nearest design rows (Sec.
+ *   2.2, Sec. 3.1), the greedy ALC design from the n0 nearest to n points
+ *   (Fig. 1 steps 2a, 2b; eqs. dxy, piedef) and the local prediction (eqs.
+ *   predgp, preds2; Fig. 1 step 5).  Uniform sizes (n_per, Np_per, d_per and
+ *   sel_off all NULL) run one workgroup per location with the arithmetic of
+ *   `precision`; otherwise locations are ordered by cost on the device and
+ *   drained by persistent workgroups.  With per-location sizes, LAGP_MIXED
+ *   scores the locations with n_m <= 64 and N'_m <= 1024 in mixed precision
+ *   and computes the others in float64, counting all of their n_m - n0 steps
+ *   in guard[m]; LAGP_FP64_REFORM needs uniform sizes.
+ *   workspace: device memory of at least lagp_alc_workspace bytes, 256-byte
+ *   aligned (else LAGP_EWORKSPACE); calls that overlap must not share it.
+ *   Supported: p <= 8, N' <= 2048, n <= 128 (float64; LAGP_MIXED n <= 64 and
+ *   N' <= 1024 for uniform sizes, LAGP_FP64_REFORM n <= 52 and N' <= 1024);
+ *   others return LAGP_EUNSUPPORTED.  Requires 1 <= n0 <= n_m <= N'_m <= N.
+ */
+lagp_status lagp_alc_workspace(const lagp_problem *prob, size_t *bytes);
+lagp_status lagp_alc_predict(const lagp_problem *prob, const lagp_outputs *out, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* LAGP_ABI_VERSION of the library. */
+int32_t lagp_abi_version(void);
 
 /*
  * lagp_alc_uneven_workspace -- bytes of device workspace that
@@ -230,29 +311,24 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
                                       int32_t *guard, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Plans: the whole float64 path with per-location sizes (lagp_nn_pool_ws
- * with Np_max into `pool`, then lagp_alc_uneven_from_pool) bound to fixed
- * buffers, autotuned and captured into one HIP graph.  Without n_per,
- * Np_per, sel_off and d_per, and when every factor column fits on chip, the
- * designs run one workgroup per location instead of through the location
- * queue (the same kernel and results).
+ * Plans: lagp_alc_predict for one problem, bound to its buffers, autotuned
+ * and captured into one HIP graph.
  *
- * lagp_plan_workspace -- bytes of device workspace that lagp_plan_create
- *   needs: lagp_alc_uneven_workspace's, then lagp_nn_pool_workspace's.
- * lagp_plan_create -- arguments as for lagp_alc_uneven_from_pool plus the
- *   pool [M x Np_max] it fills; the workspace (16-byte aligned) must hold
- *   lagp_plan_workspace bytes.  Unless flags has LAGP_PLAN_NO_TUNE, the
- *   plan first times the variants of each tunable launch on these inputs,
- *   on at most their first 65,536 locations (the NN variant: the grid-pruned
- *   pools of lagp_nn_pool_ws, one, two or four locations per workgroup over
- *   the whole design, or one over a float32 copy of it; for each pool-size
- *   schedule of the ALC kernel, how the chosen factor row reaches the
- *   lanes), and keeps the fastest (the grid without tuning); the chosen
- *   launches are then captured into a graph.  Creation
- *   runs the path on `stream` (several times when tuning), synchronises it,
- *   and finally enqueues one graph launch, whose results the outputs hold
- *   once `stream` has been synchronised.  M >= 1.  The buffers must stay
- *   allocated until the plan is destroyed.
+ * lagp_plan_create -- arguments as for lagp_alc_predict (the workspace of
+ *   lagp_alc_workspace).  Unless plan_flags has LAGP_PLAN_NO_TUNE, the plan
+ *   first times the variants of each tunable launch on these inputs, on at
+ *   most their first 65,536 locations, and keeps the fastest: the NN variant
+ *   (the grid-pruned pools, one, two or four locations per workgroup over the
+ *   whole design, or one over a float32 copy of it) and, for each pool-size
+ *   schedule of the float64 ALC kernel that the problem uses, the workgroup
+ *   shape (one location per 256- or 512-thread workgroup, or several small
+ *   locations per workgroup) and how the chosen factor row reaches the lanes.
+ *   The chosen launches are then captured into a graph.  Creation runs the
+ *   path on `stream` (several times when tuning), synchronises it, and
+ *   finally enqueues one graph launch, whose results the outputs hold once
+ *   `stream` has been synchronised.  M >= 1.  Every buffer the structs point
+ *   to must stay allocated until the plan is destroyed (the structs
+ *   themselves are copied).
  * lagp_plan_launch -- enqueues one run (one graph launch) on `stream`.
  * lagp_plan_describe -- the timings and the chosen variants, as text.
  * lagp_plan_destroy -- frees the plan (NULL is a no-op).
@@ -260,15 +336,8 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
 typedef struct lagp_plan_s *lagp_plan;
 #define LAGP_PLAN_NO_TUNE 1
 
-lagp_status lagp_plan_workspace(int64_t N, int32_t p, int64_t M, int32_t Np_max, int32_t n_max,
-                                size_t *bytes);
-
-lagp_status lagp_plan_create(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
-                             int64_t M, int32_t n0, int32_t n_max, int32_t Np_max, const int32_t *n_per,
-                             const int32_t *Np_per, const int64_t *sel_off, const double *d_per, double d,
-                             double g, int32_t *pool, double *mean, double *s2, double *var, int32_t *sel,
-                             double *alc, int32_t *status, int32_t *guard, void *workspace,
-                             size_t workspace_bytes, int32_t flags, void *stream, lagp_plan *out);
+lagp_status lagp_plan_create(const lagp_problem *prob, const lagp_outputs *out, void *workspace,
+                             size_t workspace_bytes, int32_t plan_flags, void *stream, lagp_plan *plan);
 lagp_status lagp_plan_launch(lagp_plan plan, void *stream);
 lagp_status lagp_plan_describe(lagp_plan plan, char *buf, size_t len);
 lagp_status lagp_plan_destroy(lagp_plan plan);

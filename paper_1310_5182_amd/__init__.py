@@ -7,6 +7,7 @@ path runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import math
 
 import torch
 
@@ -91,26 +92,54 @@ def alc_scores(Xj, Kinv, Xc, x, h, d: float, g: float, precision="fp64",
     return out
 
 
-def _outputs(M: int, n: int, device, out: dict | None = None) -> dict:
-    """The output tensors of an ALC call; entries missing from `out` are added to it."""
+_OUT_SPECS = (("mean", torch.float64, False), ("s2", torch.float64, False), ("var", torch.float64, False),
+              ("sel", torch.int32, True), ("alc", torch.float64, True), ("alc32", torch.float64, True),
+              ("status", torch.int32, False), ("guard", torch.int32, False))
+
+
+def _outputs(M: int, n: int, device, out: dict | None = None, rows: int | None = None) -> dict:
+    """The output tensors of an ALC call; entries missing from `out` are added
+    to it and given ones are checked.  Per-design outputs (sel, alc, alc32) are
+    M x n, or flat of length `rows` when rows are given by offsets."""
     o = out if out is not None else {}
-    f64, i32 = torch.float64, torch.int32
-    for k, shape, dt in (("mean", (M,), f64), ("s2", (M,), f64), ("var", (M,), f64), ("sel", (M, n), i32),
-                         ("alc", (M, n), f64), ("alc32", (M, n), f64), ("status", (M,), i32),
-                         ("guard", (M,), i32)):
+    for k, dt, per_design in _OUT_SPECS:
+        shape = ((rows,) if rows is not None else (M, n)) if per_design else (M,)
         if k not in o:
             o[k] = torch.empty(shape, dtype=dt, device=device)
+            continue
+        t = o[k]
+        if (not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_contiguous() or t.device != device
+                or t.numel() != math.prod(shape)):
+            raise ValueError(f"out[{k!r}] must be a contiguous {dt} tensor of {math.prod(shape)} elements "
+                             f"on {device}")
     return o
+
+
+def _check_xy(X, Y, XX):
+    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
+    if X.dim() != 2 or XX.dim() != 2 or X.shape[1] != XX.shape[1]:
+        raise ValueError("X must be N x p and XX M x p with the same p")
+    if Y.numel() != X.shape[0]:
+        raise ValueError("Y must hold one response per row of X")
+    if not (X.device == Y.device == XX.device):
+        raise ValueError("X, Y and XX must be on one device")
+    return X, Y, XX
+
+
+def _pool_arg(pool, M: int, device) -> torch.Tensor:
+    if (not isinstance(pool, torch.Tensor) or pool.dtype != torch.int32 or not pool.is_contiguous()
+            or pool.device != device or pool.dim() != 2 or pool.shape[0] != M):
+        raise ValueError("pool must be a contiguous M x Np int32 tensor on the device of X")
+    return pool
 
 
 def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision="fp64",
                   out: dict | None = None) -> dict:
     """Greedy ALC local designs and predictions from given pools (M x Np int32)."""
     L = _lib.load()
-    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
-    if pool.dtype != torch.int32 or not pool.is_contiguous() or not pool.is_cuda:
-        raise ValueError("pool must be a contiguous int32 device tensor")
+    X, Y, XX = _check_xy(X, Y, XX)
     M, p = XX.shape
+    pool = _pool_arg(pool, M, X.device)
     Np = pool.shape[1]
     o = _outputs(M, n, X.device, out)
     _lib.check(L.lagp_alc_from_pool(
@@ -121,37 +150,97 @@ def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision
     return o
 
 
-def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precision="fp64",
-                out: dict | None = None) -> dict:
-    """The whole path: NN pools, greedy ALC designs, local predictions."""
-    L = _lib.load()
-    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
-    M, p = XX.shape
-    o = _outputs(M, n, X.device, out)
-    if "pool" not in o:
-        o["pool"] = torch.empty((M, Np), dtype=torch.int32, device=X.device)
-    _lib.check(L.lagp_alc_predict(
-        X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, n0, n, Np, float(d), float(g),
-        _prec(precision), o["pool"].data_ptr(), o["mean"].data_ptr(), o["s2"].data_ptr(),
-        o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["alc32"].data_ptr(),
-        o["status"].data_ptr(), o["guard"].data_ptr(), _stream(X.device)))
-    return o
-
-
-def _i32(t, name: str, M: int) -> int:
+def _i32(t, name: str, M: int, device=None) -> int:
     if t is None:
         return 0
-    if t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda or t.numel() != M:
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda
+            or t.numel() != M or (device is not None and t.device != device)):
         raise ValueError(f"{name} must be a contiguous int32 device tensor of length M")
     return t.data_ptr()
 
 
-def _d_per(t, M: int) -> int:
+def _d_per(t, M: int, device=None) -> int:
     if t is None:
         return 0
-    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda or t.numel() != M:
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda
+            or t.numel() != M or (device is not None and t.device != device)):
         raise ValueError("d_per must be a contiguous float64 device tensor of length M")
     return t.data_ptr()
+
+
+def _sel_off(t, M: int, device) -> int:
+    if t is None:
+        return 0
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_contiguous() or t.device != device
+            or t.numel() != M + 1):
+        raise ValueError("sel_off must be a contiguous int64 tensor of length M + 1 on the device of X")
+    return t.data_ptr()
+
+
+def _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off, normalize, nn, out):
+    """lagp_problem and lagp_outputs for these tensors (the outputs dict is
+    completed in place, including the pools)."""
+    if nn not in ("grid", "brute"):
+        raise ValueError("nn must be 'grid' or 'brute'")
+    M, p = XX.shape
+    dev = X.device
+    rows = None
+    if sel_off is not None:
+        if out is None or "sel" not in out or "alc" not in out:
+            raise ValueError("with sel_off, out must supply flat sel (int32) and alc (float64) rows")
+        rows = out["sel"].numel()
+    o = _outputs(M, n, dev, out, rows)
+    if "pool" not in o:
+        o["pool"] = torch.empty((M, Np), dtype=torch.int32, device=dev)
+    _pool_arg(o["pool"], M, dev)
+    if o["pool"].shape[1] != Np:
+        raise ValueError("out['pool'] must be M x Np")
+    pr = _lib.Problem()
+    pr.struct_size = ctypes.sizeof(_lib.Problem)
+    pr.flags = (_lib.LAGP_NORMALIZE_ALC if normalize else 0) | (_lib.LAGP_NN_BRUTE if nn == "brute" else 0)
+    pr.X, pr.Y, pr.XX = X.data_ptr(), Y.data_ptr(), XX.data_ptr()
+    pr.N, pr.M, pr.p, pr.n0, pr.n, pr.Np = X.shape[0], M, p, n0, n, Np
+    pr.n_per, pr.Np_per = _i32(n_per, "n_per", M, dev), _i32(Np_per, "Np_per", M, dev)
+    pr.d_per = _d_per(d_per, M, dev)
+    pr.d, pr.g, pr.precision = float(d), float(g), _prec(precision)
+    po = _lib.Outputs()
+    po.struct_size = ctypes.sizeof(_lib.Outputs)
+    for k in ("mean", "s2", "var", "sel", "alc", "alc32", "pool", "status", "guard"):
+        setattr(po, k, o[k].data_ptr())
+    po.sel_off = _sel_off(sel_off, M, dev)
+    return pr, po, o
+
+
+def _workspace(L, pr, o, dev) -> torch.Tensor:
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(L.lagp_alc_workspace(ctypes.byref(pr), ctypes.byref(nbytes)))
+    ws = o.get("workspace")
+    if ws is None or ws.numel() < nbytes.value or ws.data_ptr() % 256:
+        ws = o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+    return ws
+
+
+def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precision="fp64",
+                out: dict | None = None, *, n_per=None, Np_per=None, d_per=None, sel_off=None,
+                normalize: bool = False, nn: str = "grid") -> dict:
+    """The whole path in one call (lagp_alc_predict): NN pools, greedy ALC
+    designs, local predictions.
+
+    n, Np: the sizes of every location, or the upper bounds of n_per / Np_per
+    (int32 device tensors of length M); d_per: a lengthscale per location.
+    Without sel_off, sel / alc / alc32 are M x n, padded with -1 / NaN past
+    n_per[m]; with sel_off (int64, M + 1 offsets), `out` must supply them as
+    flat rows.  normalize: scores reported as psi_j Delta / (j - 2) (Sec. 3.1).
+    nn: 'grid' (grid-pruned pools) or 'brute' (the whole design streamed); the
+    pools are the same.  Returns the outputs, the pools and the workspace."""
+    L = _lib.load()
+    X, Y, XX = _check_xy(X, Y, XX)
+    pr, po, o = _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off, normalize, nn,
+                         out)
+    ws = _workspace(L, pr, o, X.device)
+    _lib.check(L.lagp_alc_predict(ctypes.byref(pr), ctypes.byref(po), ws.data_ptr(), ws.numel(),
+                                  _stream(X.device)))
+    return o
 
 
 def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float, n_per=None,
@@ -159,23 +248,22 @@ def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float
                          d_per=None) -> dict:
     """Greedy ALC designs with a design size n_per[m] and a pool size Np_per[m]
     of each location's own (int32 device tensors, None = n_max / the pool
-    width) and optionally a lengthscale d_per[m] of its own (float64, None = d).  pool: M x Np_max from nn_pool(X, XX, Np_max).  Without sel_off,
-    sel and alc are M x n_max with entries past n_per[m] set to -1 / NaN;
-    with sel_off (int64, M + 1 offsets) they are flat rows, and `out` must
-    supply sel and alc of length sel_off[M]."""
+    width) and optionally a lengthscale d_per[m] of its own (float64, None = d).
+    pool: M x Np_max from nn_pool(X, XX, Np_max).  Without sel_off, sel and alc
+    are M x n_max with entries past n_per[m] set to -1 / NaN; with sel_off
+    (int64, M + 1 offsets) they are flat rows, and `out` must supply them."""
     L = _lib.load()
-    X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
-    if pool.dtype != torch.int32 or not pool.is_contiguous() or not pool.is_cuda:
-        raise ValueError("pool must be a contiguous int32 device tensor")
+    X, Y, XX = _check_xy(X, Y, XX)
     M, p = XX.shape
-    Np_max = pool.shape[1]
     dev = X.device
+    pool = _pool_arg(pool, M, dev)
+    Np_max = pool.shape[1]
+    rows = None
     if sel_off is not None:
-        if sel_off.dtype != torch.int64 or not sel_off.is_contiguous() or sel_off.numel() != M + 1:
-            raise ValueError("sel_off must be a contiguous int64 device tensor of length M + 1")
         if out is None or "sel" not in out or "alc" not in out:
             raise ValueError("with sel_off, out must supply flat sel (int32) and alc (float64)")
-    o = _outputs(M, n_max, dev, out)
+        rows = out["sel"].numel()
+    o = _outputs(M, n_max, dev, out, rows)
     nbytes = ctypes.c_size_t(0)
     _lib.check(L.lagp_alc_uneven_workspace(p, M, Np_max, n_max, ctypes.byref(nbytes)))
     ws = o.get("workspace")
@@ -183,8 +271,8 @@ def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float
         ws = o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
     _lib.check(L.lagp_alc_uneven_from_pool(
         X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np_max, n0, n_max,
-        _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M),
-        sel_off.data_ptr() if sel_off is not None else 0, _d_per(d_per, M), float(d), float(g), _prec(precision),
+        _i32(n_per, "n_per", M, dev), _i32(Np_per, "Np_per", M, dev), _sel_off(sel_off, M, dev),
+        _d_per(d_per, M, dev), float(d), float(g), _prec(precision),
         o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
         o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), ws.data_ptr(), ws.numel(),
         _stream(dev)))
@@ -193,50 +281,40 @@ def alc_uneven_from_pool(X, Y, XX, pool, n0: int, n_max: int, d: float, g: float
 
 def alc_uneven_predict(X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
                        Np_per=None, precision="fp64", out: dict | None = None, d_per=None) -> dict:
-    """The whole path with per-location n and N': one pool of the Np_max nearest
-    neighbours per location (each location uses its own prefix), then
-    alc_uneven_from_pool."""
-    X, XX = _f64(X, "X"), _f64(XX, "XX")
-    o = out if out is not None else {}
-    o["pool"] = nn_pool(X, XX, Np_max, out=o.get("pool"))
-    return alc_uneven_from_pool(X, Y, XX, o["pool"], n0, n_max, d, g, n_per=n_per, Np_per=Np_per,
-                                precision=precision, out=o, d_per=d_per)
+    """The whole path with per-location n and N' (alc_predict with n_per /
+    Np_per / d_per): one pool of the Np_max nearest neighbours per location,
+    each location using its own prefix."""
+    return alc_predict(X, Y, XX, n0, n_max, Np_max, d, g, precision, out, n_per=n_per, Np_per=Np_per,
+                       d_per=d_per)
 
 
 class Plan:
-    """The whole float64 path (NN pools of Np_max, then per-location greedy ALC
-    designs and predictions) bound to fixed buffers, autotuned on these inputs
-    and captured into one HIP graph.  `out` holds the pool and the outputs
-    (sel and alc padded to M x n_max); `launch()` enqueues one run on torch's
-    current stream.  The input tensors must stay alive as long as the plan."""
+    """alc_predict for one problem bound to fixed buffers, autotuned on these
+    inputs and captured into one HIP graph (lagp_plan_create).  `out` holds the
+    pools and the outputs (sel and alc padded to M x n); `launch()` enqueues one
+    run on torch's current stream.  The plan keeps references to the input
+    tensors, which must not be modified in place while it is used."""
 
     def __init__(self, X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
-                 Np_per=None, tune: bool = True, d_per=None):
+                 Np_per=None, tune: bool = True, d_per=None, precision="fp64", normalize: bool = False,
+                 nn: str = "grid"):
         L = _lib.load()
-        X, Y, XX = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX")
-        M, p = XX.shape
+        X, Y, XX = _check_xy(X, Y, XX)
         dev = X.device
-        o = _outputs(M, n_max, dev)
-        o["pool"] = torch.empty((M, Np_max), dtype=torch.int32, device=dev)
-        nbytes = ctypes.c_size_t(0)
-        _lib.check(L.lagp_plan_workspace(X.shape[0], p, M, Np_max, n_max, ctypes.byref(nbytes)))
-        o["workspace"] = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+        pr, po, o = _structs(X, Y, XX, n0, n_max, Np_max, d, g, precision, n_per, Np_per, d_per, None,
+                             normalize, nn, None)
+        ws = _workspace(L, pr, o, dev)
         self._keep = (X, Y, XX, n_per, Np_per, d_per)
         self.out, self._dev, self._h = o, dev, ctypes.c_void_p()
-        _lib.check(L.lagp_plan_create(
-            X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, n0, n_max, Np_max,
-            _i32(n_per, "n_per", M), _i32(Np_per, "Np_per", M), 0, _d_per(d_per, M), float(d), float(g),
-            o["pool"].data_ptr(),
-            o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
-            o["alc"].data_ptr(), o["status"].data_ptr(), o["guard"].data_ptr(), o["workspace"].data_ptr(),
-            o["workspace"].numel(), 0 if tune else 1, _stream(dev), ctypes.byref(self._h)))
+        _lib.check(L.lagp_plan_create(ctypes.byref(pr), ctypes.byref(po), ws.data_ptr(), ws.numel(),
+                                      0 if tune else 1, _stream(dev), ctypes.byref(self._h)))
 
     def launch(self) -> dict:
         _lib.check(_lib.load().lagp_plan_launch(self._h, _stream(self._dev)))
         return self.out
 
     def describe(self) -> str:
-        buf = ctypes.create_string_buffer(2048)
+        buf = ctypes.create_string_buffer(4096)
         _lib.check(_lib.load().lagp_plan_describe(self._h, buf, len(buf)))
         return buf.value.decode()
 
@@ -252,16 +330,35 @@ class Plan:
             pass
 
 
-def _sel(sel: torch.Tensor) -> torch.Tensor:
-    if sel.dtype != torch.int32 or not sel.is_contiguous() or not sel.is_cuda or sel.dim() != 2:
-        raise ValueError("sel must be a contiguous M x n int32 device tensor")
+def _sel(sel: torch.Tensor, device=None) -> torch.Tensor:
+    if (not isinstance(sel, torch.Tensor) or sel.dtype != torch.int32 or not sel.is_contiguous()
+            or not sel.is_cuda or sel.dim() != 2 or (device is not None and sel.device != device)):
+        raise ValueError("sel must be a contiguous M x n int32 tensor on the device of X")
     return sel
 
 
 def _per_loc(v, M: int, device, name: str) -> torch.Tensor:
+    """A parameter of every location: a scalar, a 1-element tensor (broadcast)
+    or a tensor of M values; anything else is refused before any launch."""
     if isinstance(v, torch.Tensor):
-        return _f64(v.reshape(M) if v.numel() == M else v, name)
+        if v.numel() == M:
+            t = v.reshape(M)
+        elif v.numel() == 1:
+            t = v.reshape(1).expand(M).contiguous()
+        else:
+            raise ValueError(f"{name} must be a scalar or hold one value per location (M = {M}), "
+                             f"not {v.numel()}")
+        if t.device != device:
+            raise ValueError(f"{name} must be on the device of X")
+        return _f64(t.contiguous(), name)
     return torch.full((M,), float(v), dtype=torch.float64, device=device)
+
+
+def _xy(X, Y):
+    X, Y = _f64(X, "X"), _f64(Y, "Y")
+    if X.dim() != 2 or Y.numel() != X.shape[0] or X.device != Y.device:
+        raise ValueError("X must be N x p and Y hold N responses on the same device")
+    return X, Y
 
 
 def local_nll(X, Y, sel, d, g, order: int = 0) -> dict:
@@ -270,7 +367,8 @@ def local_nll(X, Y, sel, d, g, order: int = 0) -> dict:
     order 0: nll; 1: + dnll/dd, dnll/dg; 2: + d2nll/dd2.  d, g: scalars or M-vectors.
     """
     L = _lib.load()
-    X, Y, sel = _f64(X, "X"), _f64(Y, "Y"), _sel(sel)
+    X, Y = _xy(X, Y)
+    sel = _sel(sel, X.device)
     M, n = sel.shape
     dev = X.device
     d, g = _per_loc(d, M, dev, "d"), _per_loc(g, M, dev, "g")
@@ -294,8 +392,15 @@ class LocalNLL(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, d, g, X, Y, sel):
-        out = local_nll(X, Y, sel, d.detach().contiguous(), g.detach().contiguous(), order=0)
-        ctx.save_for_backward(d.detach().contiguous(), g.detach().contiguous())
+        X, Y = _xy(X, Y)
+        sel = _sel(sel, X.device)
+        M = sel.shape[0]
+        # d and g: M values each, or one shared value broadcast to every location
+        dm = _per_loc(d.detach(), M, X.device, "d")
+        gm = _per_loc(g.detach(), M, X.device, "g")
+        out = local_nll(X, Y, sel, dm, gm, order=0)
+        ctx.save_for_backward(dm, gm)
+        ctx.shapes = (d.shape, g.shape)
         ctx.data = (X, Y, sel)
         return out["nll"]
 
@@ -312,13 +417,24 @@ class LocalNLL(torch.autograd.Function):
             X.data_ptr(), Y.data_ptr(), X.shape[0], X.shape[1], sel.data_ptr(), M, n, d.data_ptr(),
             g.data_ptr(), go.data_ptr(), None if gd is None else gd.data_ptr(),
             None if gg is None else gg.data_ptr(), _stream(X.device)))
+        # a shared (broadcast) parameter receives the sum over the locations
+        sd, sg = ctx.shapes
+        if gd is not None and math.prod(sd) != M:
+            gd = gd.sum().reshape(sd)
+        elif gd is not None:
+            gd = gd.reshape(sd)
+        if gg is not None and math.prod(sg) != M:
+            gg = gg.sum().reshape(sg)
+        elif gg is not None:
+            gg = gg.reshape(sg)
         return gd, gg, None, None, None
 
 
 def local_mle_d(X, Y, sel, d0, g: float, dmin: float = 1e-3, dmax: float = 5.0, maxit: int = 100) -> dict:
     """Maximum-likelihood lengthscale per location (projected Newton, g fixed)."""
     L = _lib.load()
-    X, Y, sel = _f64(X, "X"), _f64(Y, "Y"), _sel(sel)
+    X, Y = _xy(X, Y)
+    sel = _sel(sel, X.device)
     M, n = sel.shape
     dev = X.device
     d0 = _per_loc(d0, M, dev, "d0")
@@ -336,8 +452,11 @@ def local_mle_d(X, Y, sel, d0, g: float, dmin: float = 1e-3, dmax: float = 5.0, 
 def local_predict(X, Y, sel, XX, d, g: float) -> dict:
     """Prediction at XX[m] on the fixed design sel[m] with lengthscale d[m] (eqs. predgp, preds2)."""
     L = _lib.load()
-    X, Y, XX, sel = _f64(X, "X"), _f64(Y, "Y"), _f64(XX, "XX"), _sel(sel)
+    X, Y, XX = _check_xy(X, Y, XX)
+    sel = _sel(sel, X.device)
     M, n = sel.shape
+    if XX.shape[0] != M:
+        raise ValueError("XX must hold one location per row of sel")
     dev = X.device
     d = _per_loc(d, M, dev, "d")
     out = {k: torch.empty(M, dtype=torch.float64, device=dev) for k in ("mean", "s2", "var")}

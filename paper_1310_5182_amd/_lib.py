@@ -17,6 +17,32 @@ LAGP_FP64 = 0
 LAGP_MIXED = 1
 LAGP_FP64_REFORM = 2
 
+LAGP_ABI_VERSION = 2
+LAGP_NORMALIZE_ALC = 1
+LAGP_NN_BRUTE = 2
+
+
+class Problem(ctypes.Structure):
+    """lagp_problem of include/lagp_alc.h (same field order and types)."""
+
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("XX", ctypes.c_void_p),
+                ("N", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("p", ctypes.c_int32), ("n0", ctypes.c_int32), ("n", ctypes.c_int32), ("Np", ctypes.c_int32),
+                ("n_per", ctypes.c_void_p), ("Np_per", ctypes.c_void_p), ("d_per", ctypes.c_void_p),
+                ("d", ctypes.c_double), ("g", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Outputs(ctypes.Structure):
+    """lagp_outputs of include/lagp_alc.h (same field order and types)."""
+
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("mean", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("var", ctypes.c_void_p),
+                ("sel", ctypes.c_void_p), ("sel_off", ctypes.c_void_p),
+                ("alc", ctypes.c_void_p), ("alc32", ctypes.c_void_p), ("pool", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("guard", ctypes.c_void_p)]
+
 # Every symbol declared in include/lagp_alc.h.
 EXPORTS = (
     "lagp_nn_pool",
@@ -24,10 +50,11 @@ EXPORTS = (
     "lagp_nn_pool_ws",
     "lagp_alc_scores",
     "lagp_alc_from_pool",
+    "lagp_alc_workspace",
     "lagp_alc_predict",
+    "lagp_abi_version",
     "lagp_alc_uneven_workspace",
     "lagp_alc_uneven_from_pool",
-    "lagp_plan_workspace",
     "lagp_plan_create",
     "lagp_plan_launch",
     "lagp_plan_describe",
@@ -72,18 +99,19 @@ def load():
     L.lagp_alc_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, i32,
                                      P, P, P, P, P, P, P, P, P]
     L.lagp_alc_from_pool.restype = i32
-    L.lagp_alc_predict.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, f64, f64, i32, P,
-                                   P, P, P, P, P, P, P, P, P]
+    PP, PO = ctypes.POINTER(Problem), ctypes.POINTER(Outputs)
+    L.lagp_alc_workspace.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_alc_workspace.restype = i32
+    L.lagp_alc_predict.argtypes = [PP, PO, P, ctypes.c_size_t, P]
     L.lagp_alc_predict.restype = i32
+    L.lagp_abi_version.argtypes = []
+    L.lagp_abi_version.restype = i32
     L.lagp_alc_uneven_workspace.argtypes = [i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_alc_uneven_workspace.restype = i32
     L.lagp_alc_uneven_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, P, P, P, P, f64, f64,
                                             i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
     L.lagp_alc_uneven_from_pool.restype = i32
-    L.lagp_plan_workspace.argtypes = [i64, i32, i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
-    L.lagp_plan_workspace.restype = i32
-    L.lagp_plan_create.argtypes = [P, P, i64, i32, P, i64, i32, i32, i32, P, P, P, P, f64, f64, P, P, P, P,
-                                   P, P, P, P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
+    L.lagp_plan_create.argtypes = [PP, PO, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_void_p)]
     L.lagp_plan_create.restype = i32
     L.lagp_plan_launch.argtypes = [P, P]
     L.lagp_plan_launch.restype = i32

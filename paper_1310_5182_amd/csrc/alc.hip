@@ -152,10 +152,19 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
 
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane0 = tid & 63;
-    const int64_t m = blockIdx.x;
-    const int p = a.p, Np = a.Np, n = a.n, n0 = a.n0;
-    const double d = a.d, kappa = 1.0 + a.g;
-    const float ninv_d32 = (float)(-1.0 / a.d);
+    int64_t m = blockIdx.x;
+    if (a.list) {  // a location list built on the device: blocks past its end have nothing to do
+        if ((int)blockIdx.x >= *a.list_count) return;
+        m = a.list[blockIdx.x];
+    }
+    // per-location sizes and lengthscale (checked by the list builder), or the uniform ones
+    const int p = a.p, n0 = a.n0;
+    const int Np = __builtin_amdgcn_readfirstlane(a.Np_per ? a.Np_per[m] : a.Np);
+    const int n = __builtin_amdgcn_readfirstlane(a.n_per ? a.n_per[m] : a.n);
+    const double d = uniform(a.d_per ? a.d_per[m] : a.d), kappa = 1.0 + a.g;
+    const int64_t orow = a.sel_off ? a.sel_off[m] : m * (int64_t)a.n;
+    const int64_t prow = m * (int64_t)(a.pool_stride ? a.pool_stride : a.Np);
+    const float ninv_d32 = (float)(-1.0 / d);
     const int wbase = w * WSLOTS;
 
     // ---- stage the location, its pool and zeroed factors in LDS
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     __syncthreads();
     for (int s = tid; s < SLOTS; s += kThreads) {
         bool valid = s < Np;
-        int32_t di = valid ? a.pool[m * Np + s] : INT32_MAX;
+        int32_t di = valid ? a.pool[prow + s] : INT32_MAX;
         if (valid && (di < 0 || di >= a.N)) {  // never read outside X
             ctl_status = kLocBadPool;
             valid = false;
@@ -202,6 +211,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     int status = ctl_status;
     int guard_steps = 0;
     int j = 0;
+    double psi_run = 0.0;  // psi_j = |R_j Y_j|^2 so far (lane 0 of wave 0), for a.normalize
 
     T Q[CBW][KG];
 #pragma unroll
@@ -493,8 +503,12 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                 if constexpr (MIXED) zh32[j] = (float)zh[j];
                 cflag[win] = 1;
                 selslot[j] = win;
-                alc_out[j] = j >= n0 ? v : NAN;
-                if constexpr (MIXED) alc_out32[j] = (j >= n0 && rec_v32[vw] >= 0.0f) ? rec_v32[vw] : NAN;
+                // the score as chosen, or normalised by psi_j / (j - 2) (j >= n0 >= 3)
+                const double nf = a.normalize && j >= n0 ? psi_run / (j - 2) : 1.0;
+                alc_out[j] = j >= n0 ? v * nf : NAN;
+                if constexpr (MIXED)
+                    alc_out32[j] = (j >= n0 && rec_v32[vw] >= 0.0f) ? rec_v32[vw] * (float)nf : NAN;
+                psi_run += tY[j] * tY[j];
                 ctl_susp = 0;
             }
         }
@@ -530,10 +544,17 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     const int lane = lane0;
     // ===== outputs: the design in the order added, its scores, the prediction
     for (int jj = tid; jj < j; jj += kThreads) {
-        a.sel[m * n + jj] = cid[selslot[jj]];
-        if (a.alc) a.alc[m * n + jj] = alc_out[jj];
-        if (a.alc32) a.alc32[m * n + jj] = MIXED ? (double)alc_out32[jj] : NAN;
+        a.sel[orow + jj] = cid[selslot[jj]];
+        if (a.alc) a.alc[orow + jj] = alc_out[jj];
+        if (a.alc32) a.alc32[orow + jj] = MIXED ? (double)alc_out32[jj] : NAN;
     }
+    // padded rows (no offsets, n below the row length): fill the tail
+    if (!a.sel_off)
+        for (int jj = n + tid; jj < a.n; jj += kThreads) {
+            a.sel[orow + jj] = -1;
+            if (a.alc) a.alc[orow + jj] = NAN;
+            if (a.alc32) a.alc32[orow + jj] = NAN;
+        }
     // local prediction (eqs. predgp, preds2): mu = z_h.(R Y), psi = |R Y|^2
     if (w == 0) {
         const double zi = (status == kLocOk && lane < n) ? zh[lane] : 0.0;
@@ -553,9 +574,9 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         }
         if (status != kLocOk)
             for (int jj = j + lane; jj < n; jj += kWave) {
-                a.sel[m * n + jj] = -1;
-                if (a.alc) a.alc[m * n + jj] = NAN;
-                if (a.alc32) a.alc32[m * n + jj] = NAN;
+                a.sel[orow + jj] = -1;
+                if (a.alc) a.alc[orow + jj] = NAN;
+                if (a.alc32) a.alc32[orow + jj] = NAN;
             }
     }
 }
@@ -565,6 +586,17 @@ static hipError_t launch_t(const AlcArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL((alc_kernel<T, NW, CBW, KG, G>), dim3((unsigned)a.M), dim3(NW * kWave), 0, st, a);
     return hipGetLastError();
+}
+
+// Mixed precision over a device-built location list (grid a.M, the list's
+// upper bound): pools of up to 512 (big = false) or 1024 candidates, n <= 64.
+hipError_t launch_alc_mixed_list(const AlcArgs &a, bool big, hipStream_t st)
+{
+    if (a.M == 0) return hipSuccess;
+    if (a.p > kPmax || !a.list || !a.list_count) return hipErrorInvalidValue;
+    static_assert(kMixNmax == 64 && kMixNpMax == 1024, "the list schedules below");
+    if (big) return launch_t<float, 8, 8, 16, 4>(a, st);
+    return launch_t<float, 8, 4, 16, 4>(a, st);
 }
 
 static bool mfma_supported(int precision, int p, int Np, int n)

@@ -333,7 +333,9 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             const double tn = uniform(pub[par][vw][3]);
             if (tid == 0) {
                 seldi[j] = j >= n0 ? wdi : red_i[par][vw];
-                alc_out[j] = vbest;
+                // ap1 still holds psi_j = t.t over the first j entries (wave 0):
+                // the normalised score psi_j Delta / (j - 2) when asked (j >= n0 >= 3)
+                alc_out[j] = a.normalize && j >= n0 ? vbest * ap1 / (j - 2) : vbest;
             }
             if (w == 0) {
                 ap0 = fma(wh, tn, ap0);
@@ -449,7 +451,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 if (a.s2) a.s2[m] = ok ? s2 : NAN;
                 if (a.var) a.var[m] = (ok && n > 2) ? s2 * n / (n - 2) : NAN;
                 if (a.status) a.status[m] = status;
-                if (a.guard) a.guard[m] = 0;
+                // standing in for the mixed kernel: every step was decided in float64
+                if (a.guard) a.guard[m] = a.f64_guard ? (j > n0 ? j - n0 : 0) : 0;
             }
             if (!ok)
                 for (int jj = j + lane; jj < n; jj += kWave) {
@@ -607,8 +610,11 @@ struct PlanWs {
     int32_t *hist;     // [kKeys] counts, then running insert offsets
     int32_t *counter;  // [kNumSched]
     int32_t *qinfo;    // [kNumSched][2]: first entry, count
+    int32_t *mcount;   // [2] lengths of the mixed-precision lists
     int32_t *key;      // [M]
     int32_t *queue;    // [M]
+    int32_t *mlist[2]; // [M] each: locations for the mixed kernel, pools <= 512 / <= 1024
+    int mixed;         // route the locations the mixed kernel covers to mlist
 };
 
 __global__ void plan_zero(PlanWs w)
@@ -620,6 +626,7 @@ __global__ void plan_zero(PlanWs w)
         w.qinfo[2 * t] = 0;
         w.qinfo[2 * t + 1] = 0;
     }
+    if (t < 2) w.mcount[t] = 0;
 }
 
 // Classify every location: its schedule and a cost class (four per octave of
@@ -648,6 +655,12 @@ __global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
             a.sel[orow + jj] = -1;
             if (a.alc) a.alc[orow + jj] = NAN;
         }
+        return;
+    }
+    if (w.mixed && n <= kMixNmax && Np <= kMixNpMax) {  // the mixed kernel takes it
+        const int l = Np <= kMixNpMax / 2 ? 0 : 1;
+        w.mlist[l][atomicAdd(&w.mcount[l], 1)] = (int32_t)m;
+        w.key[m] = -1;
         return;
     }
     const double cost = (double)Np * n * n;
@@ -744,7 +757,8 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
     DevInfo info;
     hipError_t e = dev_info(info);
     if (e != hipSuccess) return e;
-    size_t total = kHdrBytes + 2 * align256((size_t)M * 4);
+    // header, keys, queue, the two mixed-precision lists
+    size_t total = kHdrBytes + 4 * align256((size_t)M * 4);
     const int top = sched_for(Np_max);
     for (int b = 0; b <= top; b++) {
         const int gc = gcols_for(b, p, n_max);
@@ -759,7 +773,7 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
 
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
                              const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
-                             hipStream_t st, int bcast)
+                             hipStream_t st, int bcast, bool mixed)
 {
     if (a.M == 0) return hipSuccess;
     DevInfo info;
@@ -775,14 +789,21 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
     w.hist = (int32_t *)base;
     w.counter = w.hist + kKeys;
     w.qinfo = w.counter + kNumSched;
+    w.mcount = w.qinfo + 2 * kNumSched;
     size_t off = kHdrBytes;
     w.key = (int32_t *)(base + off);
     off += align256((size_t)a.M * 4);
     w.queue = (int32_t *)(base + off);
     off += align256((size_t)a.M * 4);
+    for (int l = 0; l < 2; l++) {
+        w.mlist[l] = (int32_t *)(base + off);
+        off += align256((size_t)a.M * 4);
+    }
+    w.mixed = mixed && a.p <= kIncPmax;
 
     IncArgs x{};
     x.a = a;
+    x.a.f64_guard = w.mixed;  // the float64 kernel stands in for the mixed one
     x.n_per = n_per;
     x.Np_per = Np_per;
     x.sel_off = sel_off;
@@ -796,6 +817,20 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
     hipLaunchKernelGGL(plan_scan, dim3(1), dim3(64), 0, st, w);
     hipLaunchKernelGGL(plan_scatter, dim3(lgrid), dim3(256), 0, st, w, a.M);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (w.mixed) {
+        // the locations the mixed kernel covers, one workgroup each
+        for (int l = 0; l < 2; l++) {
+            AlcArgs am = a;
+            am.n_per = n_per;
+            am.Np_per = Np_per;
+            am.sel_off = sel_off;
+            am.d_per = d_per;
+            am.pool_stride = a.Np;
+            am.list = w.mlist[l];
+            am.list_count = w.mcount + l;
+            if ((e = launch_alc_mixed_list(am, l == 1, st)) != hipSuccess) return e;
+        }
+    }
 
     const int top = sched_for(a.Np);
     for (int b = 0; b <= top; b++) {

@@ -158,24 +158,152 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
     return ok();
 }
 
-lagp_status lagp_alc_predict(const double *X, const double *Y, int64_t N, int32_t p,
-                             const double *XX, int64_t M, int32_t n0, int32_t n, int32_t Np,
-                             double d, double g, int32_t precision, int32_t *pool,
-                             double *mean, double *s2, double *var, int32_t *sel, double *alc,
-                             double *alc32, int32_t *status, int32_t *guard, void *stream)
+}  // extern "C"
+
+namespace {
+
+size_t align256(size_t v)
 {
-    lagp_status s = check_common(X, N, p, XX, M, Np);
+    return (v + 255) & ~(size_t)255;
+}
+
+// Workspace parts of a problem: [queues / spilled columns][grid of the design][pools].
+struct WsLayout {
+    size_t alc = 0, nn = 0, pool = 0;
+    size_t total() const { return align256(alc) + align256(nn) + align256(pool); }
+};
+
+// Checks every argument of lagp_alc_predict / lagp_alc_workspace that the host
+// can see and works out the path and its workspace.  `out` may be NULL (the
+// workspace query).
+lagp_status resolve(const lagp_problem *pr, const lagp_outputs *out, lagp::PathArgs *P, WsLayout *L)
+{
+    if (!pr) return fail(LAGP_EINVAL, "problem must be non-NULL");
+    if (pr->struct_size != sizeof(lagp_problem))
+        return fail(LAGP_EINVAL, "lagp_problem.struct_size = %u, this library's is %zu (ABI version %d)",
+                    pr->struct_size, sizeof(lagp_problem), LAGP_ABI_VERSION);
+    if (out && out->struct_size != sizeof(lagp_outputs))
+        return fail(LAGP_EINVAL, "lagp_outputs.struct_size = %u, this library's is %zu (ABI version %d)",
+                    out->struct_size, sizeof(lagp_outputs), LAGP_ABI_VERSION);
+    if (pr->flags & ~(LAGP_NORMALIZE_ALC | LAGP_NN_BRUTE))
+        return fail(LAGP_EINVAL, "unknown flags 0x%x", pr->flags & ~(LAGP_NORMALIZE_ALC | LAGP_NN_BRUTE));
+    if (pr->reserved != 0 || (out && out->reserved != 0)) return fail(LAGP_EINVAL, "reserved fields must be 0");
+    lagp_status s = check_common(pr->X, pr->N, pr->p, pr->XX, pr->M, pr->Np);
     if (s != LAGP_OK) return s;
-    s = check_alc(Y, Np, n0, n, d, g, precision, sel, M);
+    const int prec = pr->precision;
+    const bool uniform = !pr->n_per && !pr->Np_per && !pr->d_per && !(out && out->sel_off);
+    s = check_alc(pr->Y, pr->Np, pr->n0, pr->n, pr->d, pr->g, prec, out ? out->sel : nullptr, out ? pr->M : 0);
     if (s != LAGP_OK) return s;
-    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
-    if (lagp::nn_pool_cap(Np) == 0 || !lagp::alc_supported(precision, p, Np, n))
-        return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d, precision = %d", p, Np, n,
-                    precision);
-    s = lagp_nn_pool(X, N, p, XX, M, Np, pool, stream);
+    if ((pr->flags & LAGP_NORMALIZE_ALC) && pr->n0 < 3)
+        return fail(LAGP_EINVAL, "LAGP_NORMALIZE_ALC divides by j - 2: needs n0 >= 3 (n0 = %d)", pr->n0);
+    if (lagp::nn_pool_cap(pr->Np) == 0)
+        return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", pr->Np);
+    // which ALC launch: the uniform kernels, or the cost-ordered queues
+    bool queued;
+    if (prec == LAGP_FP64_REFORM) {
+        if (!uniform) return fail(LAGP_EUNSUPPORTED, "LAGP_FP64_REFORM needs uniform n, N' and d");
+        if (!lagp::alc_supported(prec, pr->p, pr->Np, pr->n))
+            return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d, precision = %d", pr->p,
+                        pr->Np, pr->n, prec);
+        queued = false;
+    } else {
+        queued = !uniform || !lagp::alc_supported(prec, pr->p, pr->Np, pr->n);
+        if (queued && !lagp::alc_uneven_supported(pr->p, pr->Np, pr->n))
+            return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d", pr->p, pr->Np, pr->n);
+    }
+    WsLayout l;
+    if (queued) {
+        hipError_t e = lagp::alc_uneven_workspace(pr->p, pr->M, pr->Np, pr->n, &l.alc);
+        if (e != hipSuccess) return hip_fail(e, "workspace query");
+    }
+    if (!(pr->flags & LAGP_NN_BRUTE)) l.nn = lagp::nn_pool_workspace(pr->N, pr->p, pr->M);
+    l.pool = (size_t)pr->M * (size_t)pr->Np * 4;
+    *L = l;
+    if (P) {
+        lagp::PathArgs q;
+        lagp::AlcArgs &a = q.a;
+        a = lagp::AlcArgs{pr->X, pr->Y, pr->N, pr->p, pr->XX, pr->M, nullptr, pr->Np, pr->n0, pr->n, pr->d, pr->g,
+                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        if (out) {
+            a.mean = out->mean;
+            a.s2 = out->s2;
+            a.var = out->var;
+            a.sel = out->sel;
+            a.alc = out->alc;
+            a.alc32 = out->alc32;
+            a.status = out->status;
+            a.guard = out->guard;
+            a.pool = q.pool = out->pool;
+            a.sel_off = out->sel_off;
+        }
+        a.n_per = pr->n_per;
+        a.Np_per = pr->Np_per;
+        a.d_per = pr->d_per;
+        a.normalize = (pr->flags & LAGP_NORMALIZE_ALC) != 0;
+        q.precision = prec;
+        q.nn_brute = (pr->flags & LAGP_NN_BRUTE) != 0;
+        q.uniform = !queued;
+        *P = q;
+    }
+    return LAGP_OK;
+}
+
+// Points the path at its parts of the workspace.
+lagp_status carve(lagp::PathArgs *P, const WsLayout &l, void *ws, size_t ws_bytes)
+{
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < l.total())
+        return fail(LAGP_EWORKSPACE, "workspace must be 256-byte aligned and hold %zu bytes (%zu given)", l.total(),
+                    ws_bytes);
+    char *b = (char *)ws;
+    P->alc_ws = l.alc ? b : nullptr;
+    P->alc_ws_bytes = l.alc;
+    P->nn_ws = l.nn ? b + align256(l.alc) : nullptr;
+    if (!P->pool) P->a.pool = P->pool = (int32_t *)(b + align256(l.alc) + align256(l.nn));
+    return LAGP_OK;
+}
+
+}  // namespace
+
+lagp_status lagp::prepare_path(const lagp_problem *prob, const lagp_outputs *out, void *ws, size_t ws_bytes,
+                               PathArgs *P)
+{
+    if (!out) return fail(LAGP_EINVAL, "outputs must be non-NULL");
+    WsLayout l;
+    lagp_status s = resolve(prob, out, P, &l);
     if (s != LAGP_OK) return s;
-    return lagp_alc_from_pool(X, Y, N, p, XX, M, pool, Np, n0, n, d, g, precision, mean, s2, var, sel, alc,
-                              alc32, status, guard, stream);
+    return carve(P, l, ws, ws_bytes);
+}
+
+extern "C" {
+
+lagp_status lagp_alc_workspace(const lagp_problem *prob, size_t *bytes)
+{
+    if (!bytes) return fail(LAGP_EINVAL, "bytes must be non-NULL");
+    WsLayout l;
+    lagp_status s = resolve(prob, nullptr, nullptr, &l);
+    if (s != LAGP_OK) return s;
+    *bytes = l.total();
+    return ok();
+}
+
+lagp_status lagp_alc_predict(const lagp_problem *prob, const lagp_outputs *out, void *workspace,
+                             size_t workspace_bytes, void *stream)
+{
+    if (!out) return fail(LAGP_EINVAL, "outputs must be non-NULL");
+    lagp::PathArgs P;
+    WsLayout l;
+    lagp_status s = resolve(prob, out, &P, &l);
+    if (s != LAGP_OK) return s;
+    if (prob->M == 0) return ok();
+    if ((s = carve(&P, l, workspace, workspace_bytes)) != LAGP_OK) return s;
+    hipError_t e = lagp::run_path(P, -1, -1, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "alc_predict launch");
+    return ok();
+}
+
+int32_t lagp_abi_version(void)
+{
+    return LAGP_ABI_VERSION;
 }
 
 lagp_status lagp_alc_uneven_workspace(int32_t p, int64_t M, int32_t Np_max, int32_t n_max, size_t *bytes)

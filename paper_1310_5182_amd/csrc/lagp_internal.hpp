@@ -37,7 +37,46 @@ struct AlcArgs {
     double *alc32;  // mixed: float32 score of each chosen point (nullable)
     int32_t *status;
     int32_t *guard;
+    // Per-location designs (all NULL: a.n, a.Np and a.d everywhere, row m of
+    // sel / alc / alc32 at m * a.n).  With them a.n and a.Np are upper bounds.
+    const int32_t *n_per = nullptr;
+    const int32_t *Np_per = nullptr;
+    const int64_t *sel_off = nullptr;
+    const double *d_per = nullptr;
+    int pool_stride = 0;          // row stride of pool (0: a.Np)
+    const int32_t *list = nullptr;       // mixed kernel: locations to run, list[b] for block b
+    const int32_t *list_count = nullptr; // ... of which the first *list_count are valid
+    int normalize = 0;   // scores reported as psi_j Delta / (j - 2) (Sec. 3.1, Fig. 3 step 9)
+    int f64_guard = 0;   // float64 kernel standing in for LAGP_MIXED: guard counts every step
 };
+
+// Internal form of lagp_problem / lagp_outputs after validation, with the
+// workspace carved up.
+struct PathArgs {
+    AlcArgs a;          // per-location fields set; a.pool = pool
+    int32_t *pool = nullptr;  // the pools: the caller's, or in the workspace
+    int precision = 0;
+    bool nn_brute = false;
+    bool uniform = true;  // no per-location n, N', d or row offsets
+    void *alc_ws = nullptr;   // queues and spilled factor columns of per-location designs
+    size_t alc_ws_bytes = 0;
+    void *nn_ws = nullptr;    // grid of the design, and the float32 copy of the NN variants
+};
+
+// Whole path (pools, designs, predictions) with the given NN variant (see
+// plan.cpp; -1: the default) and incremental-kernel broadcast mask / shape.
+hipError_t run_path(const PathArgs &P, int nn_variant, int bcast, hipStream_t st);
+
+}  // namespace lagp
+
+struct lagp_problem;
+struct lagp_outputs;
+
+namespace lagp {
+
+// Validates a problem and its outputs (as lagp_alc_predict does) and carves the
+// workspace; sets lagp_last_error on failure.
+int prepare_path(const lagp_problem *prob, const lagp_outputs *out, void *ws, size_t ws_bytes, PathArgs *P);
 
 // Largest LDS buffer the NN kernel needs for a pool of Np (0 if unsupported).
 int nn_pool_cap(int Np);
@@ -70,9 +109,16 @@ hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1);
 // when d_per is not NULL, lengthscale d.
 bool alc_uneven_supported(int p, int Np_max, int n_max);
 hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes);
+// With `mixed`, locations with n_m <= 64 and N'_m <= 1024 run the mixed
+// (float32 MFMA) kernel and the others run in float64 with every step counted
+// in guard.
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
                              const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
-                             hipStream_t st, int bcast = -1);
+                             hipStream_t st, int bcast = -1, bool mixed = false);
+// Mixed (float32 MFMA) kernel over the locations of a.list (per-location
+// sizes from a's per-location fields); `big` selects the 1024-slot schedule.
+hipError_t launch_alc_mixed_list(const AlcArgs &a, bool big, hipStream_t st);
+constexpr int kMixNmax = 64, kMixNpMax = 1024;
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

@@ -88,13 +88,94 @@ def test_alc_validation(L):
     assert alc(L, M=0) == 0
 
 
+def problem(**kw):
+    from paper_1310_5182_amd import _lib
+
+    pr = _lib.Problem()
+    pr.struct_size = ctypes.sizeof(_lib.Problem)
+    vals = dict(X=FAKE, Y=FAKE, XX=FAKE, N=100, M=3, p=2, n0=6, n=20, Np=50, d=0.5, g=1e-3, precision=0, flags=0)
+    vals.update(kw)
+    for k, v in vals.items():
+        setattr(pr, k, v)
+    return pr
+
+
+def outputs(**kw):
+    from paper_1310_5182_amd import _lib
+
+    po = _lib.Outputs()
+    po.struct_size = ctypes.sizeof(_lib.Outputs)
+    po.sel = FAKE
+    for k, v in kw.items():
+        setattr(po, k, v)
+    return po
+
+
+def predict(L, pr, po, ws=FAKE * 256, nbytes=1 << 40):
+    return L.lagp_alc_predict(ctypes.byref(pr) if pr is not None else None,
+                              ctypes.byref(po) if po is not None else None, ws, nbytes, None)
+
+
+def test_struct_layout_and_abi_guard(L):
+    from paper_1310_5182_amd import _lib
+
+    # the ctypes mirrors have the C layout (the library accepts exactly these sizes)
+    assert ctypes.sizeof(_lib.Problem) == 112 and ctypes.sizeof(_lib.Outputs) == 88
+    assert L.lagp_abi_version() == _lib.LAGP_ABI_VERSION
+    assert predict(L, problem(M=0), outputs()) == 0
+    assert L.lagp_last_error() == b""
+    for bad in (0, 104, 120):
+        assert predict(L, problem(M=0, struct_size=bad), outputs()) == -1
+        assert b"struct_size" in L.lagp_last_error()
+        assert predict(L, problem(M=0), outputs(struct_size=bad)) == -1
+        assert b"lagp_outputs.struct_size" in L.lagp_last_error()
+    nb = ctypes.c_size_t(0)
+    assert L.lagp_alc_workspace(ctypes.byref(problem(struct_size=8)), ctypes.byref(nb)) == -1
+
+
 def test_predict_validation(L):
-    r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 3, 6, 5, 10, 0.5, 1e-3, 0, FAKE,
-                           None, None, None, FAKE, None, None, None, None, None)
-    assert r == -1
-    r = L.lagp_alc_predict(FAKE, FAKE, 100, 2, FAKE, 0, 2, 5, 10, 0.5, 1e-3, 1, FAKE,
-                           None, None, None, FAKE, None, None, None, None, None)
-    assert r == 0
+    assert predict(L, None, outputs()) == -1
+    assert predict(L, problem(), None) == -1
+    assert predict(L, problem(), outputs(sel=None)) == -1
+    assert predict(L, problem(flags=8), outputs()) == -1            # unknown flag
+    assert predict(L, problem(reserved=1), outputs()) == -1
+    assert predict(L, problem(), outputs(reserved=1)) == -1
+    assert predict(L, problem(n0=0), outputs()) == -1
+    assert predict(L, problem(n=51), outputs()) == -1               # n above N'
+    assert predict(L, problem(Np=101), outputs()) == -1             # N' above N
+    assert predict(L, problem(d=0.0), outputs()) == -1
+    assert predict(L, problem(g=float("nan")), outputs()) == -1
+    assert predict(L, problem(precision=3), outputs()) == -1
+    assert predict(L, problem(p=9), outputs()) == -4
+    assert predict(L, problem(Y=None), outputs()) == -1
+    # the normalisation of Fig. 3 step 9 divides by j - 2
+    assert predict(L, problem(flags=1, n0=2), outputs()) == -1
+    assert b"n0 >= 3" in L.lagp_last_error()
+    assert predict(L, problem(flags=1, n0=3, M=0), outputs()) == 0
+    # the re-forming kernels take uniform sizes only
+    assert predict(L, problem(precision=2, n_per=FAKE), outputs()) == -4
+    assert predict(L, problem(precision=2), outputs(sel_off=FAKE)) == -4
+    assert predict(L, problem(N=10**5, n=129, Np=2000), outputs()) == -4
+    assert predict(L, problem(N=10**5, Np=4096), outputs()) == -4
+    assert predict(L, problem(M=0, precision=1), outputs()) == 0
+
+
+def test_predict_workspace(L):
+    nb = ctypes.c_size_t(0)
+    assert L.lagp_alc_workspace(None, ctypes.byref(nb)) == -1
+    assert L.lagp_alc_workspace(ctypes.byref(problem()), None) == -1
+    # uniform float64 sizes: no queue, so the query needs no device
+    assert L.lagp_alc_workspace(ctypes.byref(problem(flags=2)), ctypes.byref(nb)) == 0
+    assert nb.value == 768                                        # the pools, 3 x 50 int32, 256-aligned
+    assert L.lagp_alc_workspace(ctypes.byref(problem()), ctypes.byref(nb)) == 0
+    grid = ctypes.c_size_t(0)
+    assert L.lagp_nn_pool_workspace(100, 2, 3, ctypes.byref(grid)) == 0
+    assert nb.value >= grid.value + 3 * 50 * 4
+    need = nb.value
+    assert predict(L, problem(), outputs(), nbytes=need - 1) == -2
+    assert predict(L, problem(), outputs(), ws=FAKE * 256 + 16, nbytes=need) == -2   # not 256-byte aligned
+    assert predict(L, problem(), outputs(), ws=None, nbytes=need) == -2
+    assert b"256-byte aligned" in L.lagp_last_error()
 
 
 def test_python_binding_rejects_cpu_tensors():
@@ -148,15 +229,20 @@ def test_uneven_validation(L):
 
 def test_plan_validation(L):
     h = ctypes.c_void_p()
-    args = [FAKE, FAKE, 5000, 4, FAKE, 3, 6, 100, 2000, None, None, None, None, 0.3, 1e-5, FAKE, None, None,
-            None, FAKE, None, None, None, FAKE, 1 << 30, 0, None]
-    assert L.lagp_plan_create(*args, None) == -1                       # no handle
-    bad = list(args); bad[5] = 0
-    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -1              # M = 0
-    bad = list(args); bad[7] = 129
-    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -4              # n_max beyond 128
-    bad = list(args); bad[6] = 0
-    assert L.lagp_plan_create(*bad, ctypes.byref(h)) == -1              # n0 = 0
+
+    def create(pr, po=None, handle=True, flags=0):
+        po = po or outputs()
+        return L.lagp_plan_create(ctypes.byref(pr) if pr is not None else None, ctypes.byref(po), FAKE * 256,
+                                  1 << 40, flags, None, ctypes.byref(h) if handle else None)
+
+    assert create(problem(), handle=False) == -1                     # no handle
+    assert create(None) == -1
+    assert create(problem(M=0)) == -1                                 # a plan needs M >= 1
+    assert b"M >= 1" in L.lagp_last_error()
+    assert create(problem(N=5000, n=129, Np=2000)) == -4              # n beyond 128
+    assert create(problem(n0=0)) == -1
+    assert create(problem(struct_size=96)) == -1
+    assert create(problem(), flags=4) == -1                           # unknown plan flag
     assert h.value is None
     assert L.lagp_plan_destroy(None) == 0
     assert L.lagp_plan_launch(None, None) == -1
@@ -181,8 +267,6 @@ def test_nn_pool_ws_validation(L):
     assert ws(FAKE, 100, 3, FAKE, 3, 10, None, FAKE, need) == -1
     assert ws(FAKE, 10**6, 3, FAKE, 3, 5000, FAKE, FAKE, 1 << 30) == -4
     assert ws(FAKE, 100, 3, FAKE, 0, 10, FAKE, None, 0) == 0     # M = 0: no-op
-    assert L.lagp_plan_workspace(100, 2, 10, 50, 20, None) == -1
-    assert L.lagp_plan_workspace(100, 17, 10, 50, 20, ctypes.byref(nb)) == -4
 
 
 def test_scores_validation(L):

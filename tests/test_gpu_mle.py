@@ -8,7 +8,6 @@ import os
 import numpy as np
 import pytest
 
-import parity
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -136,7 +135,7 @@ def test_mle_matches_oracle(lagp, orc):
     e_d = check_d_hat(orc, W, sel, got["d"], want["d"], ok)
     _log("mle", dict(converged=int(ok.sum()), max_rel_d=e_d, max_rel_nll=e_f,
                      iters_gpu=float(got["iters"].mean()), iters_oracle=float(want["iters"].mean())))
-    assert ok.sum() >= 0.9 * len(ok)
+    assert ok.all(), want["status"]  # every design of this workload converges on both sides
     assert e_f < 1e-10
 
 
@@ -150,18 +149,21 @@ def test_predict_on_fixed_design(lagp, orc):
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in got.items()}
     assert np.all(got["status"] == 0)
-    worst = 0.0
+    worst, gap_max = 0.0, 0.0
     for m in range(len(sel)):
         ref = orc.gp_predict(W.X[sel[m]], W.Y[sel[m]], W.XX[m], d[m], W.g)
-        # the parity protocol's output bound: 1e-9, raised to what float64 can
-        # resolve at this conditioning (kappa eps cond(K), over v for s2 and V)
-        kc = parity.cond_bounds(W.X, sel[m:m + 1], d[m], W.g)[0]
+        # the parity protocol's output bound: 1e-10, raised only to 10x the gap
+        # between the oracle's two float64 routes on this design (Cholesky vs
+        # the inverse grown by the partitioned inverse, eq. piedef)
+        refb = orc.gp_predict_b(W.X[sel[m]], W.Y[sel[m]], W.XX[m], d[m], W.g)
         for k in ("mean", "s2", "var"):
-            tol = max(1e-9, 10 * (kc if k == "mean" else kc / abs(ref["v"])))
+            gap = float(rel(refb[k], ref[k], 1e-8))
+            gap_max = max(gap_max, gap)
+            tol = max(1e-10, 10 * gap)
             r = rel(got[k][m], ref[k], 1e-8)
             worst = max(worst, r / tol)
             assert r < tol, (m, k, r, tol)
-    _log("predict", dict(worst_over_tol=worst))
+    _log("predict", dict(worst_over_tol=worst, max_route_gap=gap_max))
 
 
 def test_config4_pipeline_subsample(lagp, orc):
@@ -177,7 +179,9 @@ def test_config4_pipeline_subsample(lagp, orc):
     sel = o["sel"].cpu().numpy()
     ref = orc.local_mle(W.X, W.Y, sel, 0.2, W.g, 1e-3, 5.0, 100)
     dh = mle["d"].cpu().numpy()
-    ok = (ref["status"] == 0) & (mle["status"].cpu().numpy() == 0)
+    assert np.array_equal(mle["status"].cpu().numpy(), ref["status"])
+    ok = ref["status"] == 0
+    assert ok.all(), ref["status"]
     check_d_hat(orc, W, sel, dh, ref["d"], ok)
     assert np.max(rel(mle["nll"].cpu().numpy()[ok], ref["nll"][ok], 1.0)) < 1e-10
     mean = pr["mean"].cpu().numpy()

@@ -257,3 +257,63 @@ def test_nn_pool_grid_nonuniform(lagp, orc, case):
         torch.cuda.synchronize()
         want = orc.nn_pool(X, XX, npl)
         assert np.array_equal(got.cpu().numpy(), want), (case, npl)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
+def test_exact_score_ties(lagp, orc, precision):
+    """Every design row twice (rows i and i + N/2 identical): while both twins
+    are candidates their scores are exactly equal, and the smaller design index
+    must win (Fig. 1 step 2b with ties to the smaller index)."""
+    r = np.random.default_rng(31)
+    A = r.random((3000, 8))
+    X = np.vstack([A, A])
+    Y = workloads.response_sines(X)
+    XX = r.random((16, 8))
+    W = workloads.Workload("twins", X, Y, XX, 6, 30, 200, 0.5, 1e-4)
+    print(f"[parity] exact ties {precision} N={W.N} M={W.M}", flush=True)
+    g = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
+    assert np.array_equal(g["pool"], orc.nn_pool(W.X, W.XX, W.Np))
+    half = A.shape[0]
+    for m in range(W.M):
+        sel = list(g["sel"][m])
+        for j in range(W.n0, W.n):
+            if sel[j] >= half:  # the larger twin only after the smaller one
+                assert sel[j] - half in sel[:j], (m, j, sel)
+    check_alc(orc, W, g, W.n0, W.n, W.Np, precision, 1e-4 if precision == "mixed" else 1e-10,
+              f"exact_ties_{precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
+def test_status_not_pd_and_step_failure(lagp, orc, precision):
+    """Per-location failures with a nugget below float64 resolution (1 + g == 1):
+    status 1 when the nearest-neighbour start holds two identical rows (K_{n0}
+    singular), status 2 when every candidate duplicates the design (no positive
+    conditional variance).  Both sides must report the same code, NaN outputs
+    and no design past the failure."""
+    r = np.random.default_rng(41)
+    base = r.random((400, 3))
+    twin = base[7]
+    cluster = np.full((60, 3), 0.5) + np.array([0.0, 0.0, 3.0])  # 60 copies of one point, far away
+    X = np.vstack([base, twin[None, :], cluster])
+    Y = np.sin(3 * X).sum(axis=1)
+    g_tiny = 1e-20
+    # n0 = 2: the location at the twin starts with both copies -> status 1
+    XX1 = np.vstack([twin, twin + 1e-3])
+    W1 = workloads.Workload("not_pd", X, Y, XX1, 2, 6, 40, 0.3, g_tiny)
+    # n0 = 1: the location at the cluster sees only copies of its start -> status 2
+    XX2 = np.vstack([cluster[:1], cluster[:1] + 1e-2])
+    W2 = workloads.Workload("step_fail", X, Y, XX2, 1, 5, 40, 0.3, g_tiny)
+    for W, code in ((W1, 1), (W2, 2)):
+        print(f"[parity] status {W.name} {precision}", flush=True)
+        gg = run_gpu(lagp, W, W.n0, W.n, W.Np, precision)
+        ref = orc.lagp(W.X, W.Y, W.XX, W.n0, W.n, W.Np, W.d, W.g)
+        assert np.array_equal(gg["pool"], ref["pool"])
+        assert list(ref["status"]) == [code, code], ref["status"]
+        assert np.array_equal(gg["status"], ref["status"]), (W.name, gg["status"])
+        for m in range(W.M):
+            for k in ("mean", "s2", "var"):
+                assert np.isnan(gg[k][m]), (W.name, m, k)
+            row = gg["sel"][m]
+            k = int(np.sum(row >= 0))
+            assert np.all(row[k:] == -1) and np.array_equal(row[:k], gg["pool"][m, :k]), row
+            assert np.all(np.isnan(gg["alc"][m, max(k, W.n0):]))

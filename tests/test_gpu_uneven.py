@@ -67,19 +67,7 @@ def check_against_oracle(orc, W, g, n0, n_max, n_per, Np_per, name, tau_out=1e-1
         assert np.all(g["sel"][m, n_per[m]:] == -1) and np.all(np.isnan(g["alc"][m, n_per[m]:]))
     seq = parity.sequence_check(g["sel"], g["pool"], forced, n0, n_per=n_per)
     mean_floor = 1e-6 * np.sqrt(np.mean(W.Y ** 2))
-    worst, rep = 0.0, {}
-    for k in ("mean", "s2", "var"):
-        rel = np.empty(M)
-        tol = np.empty(M)
-        for m in range(M):
-            kc = parity.cond_bounds(W.X, g["sel"][m:m + 1, :n_per[m]], dv[m], W.g)[0]
-            b = forced[k][m]
-            floor = mean_floor if k == "mean" else 0.0
-            rel[m] = abs(g[k][m] - b) / max(abs(b), floor)
-            bound = kc if k == "mean" else kc / abs(forced["v"][m])
-            tol[m] = max(tau_out, 10 * bound)
-        rep[k] = dict(max_rel=float(rel.max()), n_cond_limited=int(np.sum(tol > tau_out)))
-        worst = max(worst, float(np.max(rel / tol)))
+    worst, rep = parity.output_check(g, forced, W.X, dv, W.g, tau_out, mean_floor)
     free = orc.alc(W.X, W.Y, W.XX, g["pool"], n0, n_max, W.d, W.g, n_per=n_per, Np_per=Np_per, d_per=d_per)
     same = int(sum(np.array_equal(free["sel"][m, :n_per[m]], g["sel"][m, :n_per[m]]) for m in range(M)))
     rec = dict(M=M, N=W.N, p=W.p, n_range=[int(n_per.min()), int(n_per.max())],
