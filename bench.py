@@ -71,7 +71,7 @@ def alc_evals(n0: int, n: int, Np: int) -> int:
 
 
 def scores_microbench(lagp, torch, timer, reps: int = 50) -> dict:
-    """One location against N' = 60,000 candidates at design sizes j = 16 .. 128
+    """One location against N' = 60,000 candidates at design sizes j = 16 .. 512
     (the paper's ALC-in-isolation experiment, Sec. 4, on a 2-d design):
     lagp_alc_scores in float64 and mixed precision.  K_j^{-1} and h are the
     caller's inputs, formed here with numpy as the paper's host code formed them.
@@ -82,7 +82,7 @@ def scores_microbench(lagp, torch, timer, reps: int = 50) -> dict:
     Nc, p, d, g = 60000, 2, 0.1, 1e-4
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     out = {"Nc": Nc, "p": p, "d": d, "g": g, "reps": reps, "j": {}}
-    for j in (16, 32, 48, 64, 96, 128):
+    for j in (16, 32, 48, 64, 96, 128, 160, 256, 384, 512):
         Xj, Xc, x = workloads.scores_case(j, Nc, p, 0)
         D = ((Xj[:, None, :] - Xj[None, :, :]) ** 2).sum(-1)
         Kinv = np.linalg.inv(np.exp(-D / d) + g * np.eye(j))

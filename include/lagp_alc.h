@@ -165,8 +165,10 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
  *   delta [Nc]     out: v_j(x) - v_{j+1}(x) for each candidate (eq. dxy),
  *                  computed as (K(c,x) - k_c^T K_j^{-1} h)^2 / s_c with
  *                  s_c = 1 + g - k_c^T K_j^{-1} k_c; -INFINITY where s_c <= 0
- * The quadratic forms k_c^T K_j^{-1} k_c of 64-candidate tiles are products on
- * the matrix cores (16x16x4 MFMA).  Supported: 1 <= j <= 128, p <= 16;
+ * The quadratic forms k_c^T K_j^{-1} k_c of candidate tiles are products on
+ * the matrix cores (16x16x4 MFMA); K_j^{-1} is staged in LDS up to j = 128
+ * and read from global memory (L2) beyond.  Supported: 1 <= j <= 512,
+ * p <= 16 (the design sizes of the paper's ALC-in-isolation sweep, Sec. 4);
  * Nc = 0 is a no-op.
  */
 lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double *Kinv, const double *Xc,

@@ -211,6 +211,111 @@ __global__ __launch_bounds__((sc_block<T, J>())) void alc_scores_kernel(ScArgs a
     }
 }
 
+// Designs beyond kScoresJmax, whose K_j^{-1} (up to 2 MB in float64) cannot
+// be staged in LDS: it is read straight from the caller's array (from L2 after
+// the first tiles: every workgroup walks it in the same order).  A workgroup
+// scores 16 candidates at a time.  Their kernel values Q (J x 16) sit in LDS;
+// wave w forms the row blocks I = w, w + 4, ... of U = K_j^{-1} Q^T on the
+// matrix cores (A: a 16 x 4 block of K_j^{-1} from global memory, B: a 4 x 16
+// block of Q^T from LDS) and folds each block into the two sums every score
+// needs, q_c^T U_c = q_c^T K_j^{-1} q_c and h^T U_c = h^T K_j^{-1} q_c (so no
+// w = K_j^{-1} h is formed); the four waves' partial sums meet in LDS.
+template <typename T>
+__host__ __device__ constexpr size_t sb_lds(int J, int p)
+{
+    return 8 * ((size_t)J * p + kMaxP) + sizeof(T) * ((size_t)J + (size_t)J * 16 + 16 + 2 * 4 * 16);
+}
+
+constexpr int kSbBlock = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kSbBlock) void alc_scores_big_kernel(ScArgs a)
+{
+    constexpr int TB = kSbBlock, NW = TB / kWave;
+    typedef typename ScMma<T>::acc acc_t;
+    extern __shared__ double sb_dyn[];
+    const int j = a.j, p = a.p, J = (j + 15) & ~15, KK = J / 4, RT = J / 16;
+    double *xj = sb_dyn;           // [J][p], zeros past j
+    double *xs = xj + J * p;       // [kMaxP]
+    T *hs = (T *)(xs + kMaxP);     // [J] h, zeros past j
+    T *Q = hs + J;                 // [J][16] kernel values of the tile's candidates
+    T *cxs = Q + J * 16;           // [16] K(c, x)
+    T *part = cxs + 16;            // [2][NW][16] the waves' partial sums
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int t = tid; t < J * p; t += TB) xj[t] = t < j * p ? a.Xj[t] : 0.0;
+    if (tid < p) xs[tid] = a.x[tid];
+    for (int t = tid; t < J; t += TB) hs[t] = t < j ? (T)a.h[t] : (T)0;
+    __syncthreads();
+
+    const T kappa = (T)(1.0 + a.g), nid = (T)(-1.0 / a.d);
+    const int c16 = tid & 15;
+    const int64_t ntiles = (a.Nc + 15) / 16;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // kernel values: thread t takes candidate t % 16 and rows t / 16 + 16 i
+        const int64_t cand = tile * 16 + c16;
+        const bool valid = cand < a.Nc;
+        double xc[kMaxP];
+#pragma unroll
+        for (int k = 0; k < kMaxP; k++) xc[k] = valid && k < p ? a.Xc[cand * p + k] : 0.0;
+        for (int b = tid >> 4; b < J; b += TB / 16) {
+            const T kv = corr_t<T>(sqdist_t<T>(xc, xj + b * p, p), nid);
+            Q[b * 16 + c16] = valid && b < j ? kv : (T)0;
+        }
+        if (tid < 16) cxs[tid] = corr_t<T>(sqdist_t<T>(xc, xs, p), nid);
+        __syncthreads();
+
+        // row blocks of U, two at a time so that two accumulations are in flight
+        T qp = 0, hp = 0;
+        const int ko = lane >> 4, ci = lane & 15;
+        for (int I0 = wv; I0 < RT; I0 += 2 * NW) {
+            const int I1 = I0 + NW;
+            const bool two = I1 < RT;
+            acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
+            const int r0 = 16 * I0 + ci, r1 = 16 * I1 + ci;
+#pragma unroll 8
+            for (int kk = 0; kk < KK; kk++) {
+                const int col = 4 * kk + ko;  // K_j^{-1} is symmetric: read column `row` as row `col`
+                const bool in0 = r0 < j && col < j, in1 = two && r1 < j && col < j;
+                const double k0 = a.Kinv[in0 ? (int64_t)col * j + r0 : 0];
+                const double k1 = a.Kinv[in1 ? (int64_t)col * j + r1 : 0];
+                const T bq = Q[col * 16 + ci];
+                acc0 = ScMma<T>::run(in0 ? (T)k0 : (T)0, bq, acc0);
+                acc1 = ScMma<T>::run(in1 ? (T)k1 : (T)0, bq, acc1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row0 = 16 * I0 + ScMma<T>::row(ko, r);
+                qp = fma(acc0[r], Q[row0 * 16 + ci], qp);
+                hp = fma(acc0[r], hs[row0], hp);
+                if (two) {
+                    const int row1 = 16 * I1 + ScMma<T>::row(ko, r);
+                    qp = fma(acc1[r], Q[row1 * 16 + ci], qp);
+                    hp = fma(acc1[r], hs[row1], hp);
+                }
+            }
+        }
+        qp = row_sum4(qp);
+        hp = row_sum4(hp);
+        if (lane < 16) {
+            part[wv * 16 + lane] = qp;
+            part[(NW + wv) * 16 + lane] = hp;
+        }
+        __syncthreads();
+        if (tid < 16) {
+            T q = 0, hw = 0;
+#pragma unroll
+            for (int v = 0; v < NW; v++) {
+                q += part[v * 16 + tid];
+                hw += part[(NW + v) * 16 + tid];
+            }
+            const T s = kappa - q, cov = cxs[tid] - hw;
+            if (valid) a.delta[cand] = s > (T)0 ? (double)(cov * cov / s) : -INFINITY;
+        }
+        __syncthreads();  // Q and part are rewritten by the next tile
+    }
+}
+
 template <typename T, int J>
 const void *kernel_of()
 {
@@ -244,6 +349,12 @@ hipError_t scores_setup()
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(mu);
     if (ready[dev]) return hipSuccess;
+    const int big = (int)sb_lds<double>(kScoresJbig, kMaxP);
+    if ((e = hipFuncSetAttribute((const void *)&alc_scores_big_kernel<double>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)&alc_scores_big_kernel<float>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, big)) != hipSuccess)
+        return e;
     for (int J = 16; J <= kScoresJmax; J += 16) {
         const int lim = (int)sc_lds<double>(J, kMaxP);
         if ((e = hipFuncSetAttribute(scores_kernel<double>(J), hipFuncAttributeMaxDynamicSharedMemorySize, lim)) !=
@@ -275,9 +386,28 @@ hipError_t launch_j(const ScArgs &a, hipStream_t st)
 }
 
 template <typename T>
+hipError_t launch_big(const ScArgs &a, hipStream_t st)
+{
+    const int J = (a.j + 15) & ~15;
+    const size_t lds = sb_lds<T>(J, a.p);
+    const void *k = (const void *)&alc_scores_big_kernel<T>;
+    int nb = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kSbBlock, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t ntiles = (a.Nc + 15) / 16;
+    const int64_t resident = (int64_t)cus * (nb > 0 ? nb : 1);
+    const dim3 grid((unsigned)(ntiles < resident ? ntiles : resident));
+    hipLaunchKernelGGL((alc_scores_big_kernel<T>), grid, dim3(kSbBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_t(const ScArgs &a, hipStream_t st)
 {
     const int J = (a.j + 15) & ~15;
+    if (J > kScoresJmax) return launch_big<T>(a, st);
     switch (J) {
 #define LAGP_SC_CASE(JJ)              \
     case JJ:                          \
@@ -304,7 +434,7 @@ hipError_t launch_alc_scores(const double *Xj, int j, int p, const double *Kinv,
                              hipStream_t st)
 {
     if (Nc == 0) return hipSuccess;
-    if (j < 1 || j > kScoresJmax || p < 1 || p > kMaxP) return hipErrorInvalidValue;
+    if (j < 1 || j > kScoresJbig || p < 1 || p > kMaxP) return hipErrorInvalidValue;
     hipError_t e = scores_setup();
     if (e != hipSuccess) return e;
     const ScArgs a{Xj, j, p, Kinv, Xc, Nc, x, h, d, g, delta};

@@ -122,7 +122,7 @@ lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double
     if (precision != LAGP_FP64 && precision != LAGP_MIXED)
         return fail(LAGP_EINVAL, "precision = %d is not LAGP_FP64 or LAGP_MIXED", precision);
     if (j < 1) return fail(LAGP_EINVAL, "j = %d < 1", j);
-    if (j > lagp::kScoresJmax) return fail(LAGP_EUNSUPPORTED, "j = %d > %d", j, lagp::kScoresJmax);
+    if (j > lagp::kScoresJbig) return fail(LAGP_EUNSUPPORTED, "j = %d > %d", j, lagp::kScoresJbig);
     if (p < 1) return fail(LAGP_EINVAL, "p = %d < 1", p);
     if (p > lagp::kMaxP) return fail(LAGP_EUNSUPPORTED, "p = %d > %d", p, lagp::kMaxP);
     if (Nc < 0) return fail(LAGP_EINVAL, "Nc = %lld < 0", (long long)Nc);

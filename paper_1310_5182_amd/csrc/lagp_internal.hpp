@@ -10,7 +10,8 @@ namespace lagp {
 int set_error(int code, const char *fmt, ...);
 
 constexpr int kMaxP = 16;  // largest input dimension any kernel accepts
-constexpr int kScoresJmax = 128;  // largest design of the batch-scores kernel
+constexpr int kScoresJmax = 128;  // largest design whose K_j^{-1} the batch-scores kernel stages in LDS
+constexpr int kScoresJbig = 512;  // largest design of the batch scores (K_j^{-1} read from L2 beyond 128)
 
 // Per-location status codes (the LAGP_LOC_* values of the public header).
 constexpr int kLocOk = 0, kLocInitNotPd = 1, kLocStepFail = 2, kLocNonfinite = 3, kLocBadPool = 4,

@@ -274,7 +274,8 @@ def test_scores_validation(L):
     sc = lambda j=4, p=2, Nc=10, d=0.5, g=1e-3, prec=0, delta=P: L.lagp_alc_scores(  # noqa: E731
         P, j, p, P, P, Nc, P, P, d, g, prec, delta, None)
     assert sc(j=0) == -1
-    assert sc(j=129) == -4
+    assert sc(j=513) == -4
+    assert b"512" in L.lagp_last_error()
     assert sc(p=0) == -1
     assert sc(p=17) == -4
     assert sc(Nc=-1) == -1

@@ -54,7 +54,12 @@ def _log(rec):
 CASES = [(1, 1000, 2, 0.1, 1e-4), (6, 3001, 8, 0.5, 1e-4), (16, 64, 3, 0.3, 1e-5), (17, 5000, 3, 0.3, 1e-5),
          (33, 777, 1, 0.2, 1e-4), (50, 20003, 8, 0.5, 1e-4), (64, 4097, 2, 0.1, 1e-4), (80, 2500, 4, 0.3, 1e-4),
          (96, 10000, 8, 0.5, 1e-4), (113, 999, 5, 0.4, 1e-3), (128, 60000, 2, 0.1, 1e-4),
-         (128, 1000, 16, 2.0, 1e-4)]
+         (128, 1000, 16, 2.0, 1e-4),
+         # designs past the LDS-staged inverse (K_j^{-1} read from global memory), up to
+         # the j = 512 of the paper's ALC-in-isolation sweep (Sec. 4, Fig. 4)
+         (129, 3001, 2, 0.1, 1e-4), (160, 4000, 2, 0.1, 1e-4), (256, 2000, 2, 0.1, 1e-4),
+         (300, 1500, 8, 0.5, 1e-4), (384, 2000, 2, 0.1, 1e-4), (512, 2000, 2, 0.1, 1e-4),
+         (512, 517, 16, 2.0, 1e-3)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"j{c[0]}_Nc{c[1]}_p{c[2]}")
