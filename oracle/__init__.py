@@ -72,6 +72,9 @@ class Oracle:
         L.orc_mle_d.restype = i32
         L.orc_local_mle.argtypes = [P, P, i32, P, i64, i32, P, f64, f64, f64, i32, i32, P]
         L.orc_local_mle.restype = i32
+        L.orc_mspe.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, P, i32, i32,
+                               P, P, P, P, P, P, P, P, P]
+        L.orc_mspe.restype = i32
         self.L = L
 
     def nn_pool(self, X, XX, Np: int, threads: int = 0) -> np.ndarray:
@@ -194,6 +197,32 @@ class Oracle:
         return dict(d=out[:, 0], nll=out[:, 1], iters=out[:, 2].astype(int), status=out[:, 3].astype(int))
 
 
+    def mspe(self, X, Y, XX, pool, n0: int, n: int, d: float, g: float, *, forced=None, mode_b: bool = False,
+             threads: int = 0) -> dict:
+        """Local designs by the MSPE criterion (eq. mspe): at every step the
+        candidate minimising V_j(x | x') + (d mu_j / dd)^2 / G_{j+1}.  Returns
+        sel, jsel (criterion of the choice), jmin, amin (its smallest value and
+        where), nu (route noise, mode_b), dmu, gsel (M x n), the prediction on
+        the final design (mean, s2, var, v, psi) and status."""
+        X, Y, XX = _f64(X), _f64(Y), _f64(np.atleast_2d(XX))
+        pool = _i32(np.atleast_2d(pool))
+        M, Np = pool.shape
+        forced = None if forced is None else _i32(np.atleast_2d(forced))
+        if forced is not None:
+            assert forced.shape == (M, n)
+        sel, amin = np.full((M, n), -1, np.int32), np.full((M, n), -1, np.int32)
+        jsel, jmin, nu, dmu, gsel = (np.full((M, n), np.nan) for _ in range(5))
+        pred = np.full((M, 5), np.nan)
+        status = np.zeros(M, np.int32)
+        rc = self.L.orc_mspe(_p(X), _p(Y), X.shape[0], X.shape[1], _p(XX), M, _p(pool), Np, n0, n, d, g,
+                             _p(forced), int(mode_b), threads, _p(sel), _p(jsel), _p(jmin), _p(amin), _p(nu),
+                             _p(dmu), _p(gsel), _p(pred), _p(status))
+        if rc:
+            raise ValueError(f"orc_mspe: {STATUS.get(rc, rc)}")
+        return dict(sel=sel, jsel=jsel, jmin=jmin, amin=amin, nu=nu, dmu=dmu, gsel=gsel, mean=pred[:, 0],
+                    s2=pred[:, 1], var=pred[:, 2], v=pred[:, 3], psi=pred[:, 4], status=status)
+
+
 _default: Oracle | None = None
 
 
@@ -242,3 +271,7 @@ def mle_d(*a, **k):
 
 def local_mle(*a, **k):
     return default().local_mle(*a, **k)
+
+
+def mspe(*a, **k):
+    return default().mspe(*a, **k)

@@ -850,3 +850,319 @@ int orc_local_mle(const double *X, const double *Y, int p, const int32_t *sel, i
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* MSPE criterion for the local design (Sec. 2.2, eqs. mspe and newv). */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The candidate x' minimising
+ *   J(x', x) = V_j(x | x') + (d mu_j(x) / d theta)^2 / G_{j+1}(theta)
+ * with theta the lengthscale d (the value the design is built at):
+ *   V_j(x | x') = (j + 1) psi_j / (j (j - 1)) * v_{j+1}(x)          (eq. newv)
+ *   v_{j+1}(x)  = kappa - k_{j+1}(x)^T K_{j+1}^{-1} k_{j+1}(x),  X_{j+1} = X_j + {x'}
+ *   mu_j(x)     = k_j(x)^T K_j^{-1} Y_j                            (eq. predgp)
+ *   d mu_j / dd = kdot_j(x)^T K_j^{-1} Y_j - k_j(x)^T K_j^{-1} Kdot_j K_j^{-1} Y_j
+ *   G_{j+1}     = (1/2) [tr(W^2) - tr(W)^2 / (j + 1)],  W = K_{j+1}^{-1} Kdot_{j+1}
+ * where Kdot = dK/dd = exp(-D/d) * D / d^2 (the nugget does not depend on d)
+ * and G is the expected information about d in j + 1 responses of
+ * N(0, tau^2 K_{j+1}) with the scale tau^2 unknown (the information of d
+ * less what tau^2 absorbs); it does not depend on the unseen response
+ * y_{j+1}, so the expectation over the future response is exact.
+ *
+ * Mode A (plain): for every candidate a fresh Cholesky inverse of K_{j+1}
+ * and the products above written out.  Mode B (for route noise): K_{j+1}^{-1}
+ * bordered from K_j^{-1} by the partitioned inverse (eq. piedef), so that
+ *   v_{j+1} = v_j - cov^2 / s,
+ *   tr W_{j+1}   = tr(K_j^{-1} Kdot_j) + e / s,
+ *   tr W_{j+1}^2 = tr((K_j^{-1} Kdot_j)^2) + 2 a^T K_j^{-1} a / s + e^2 / s^2,
+ * with u = K_j^{-1} k', s = kappa - k'.u, cov = K(x', x) - k_j(x).u,
+ * e = u^T Kdot_j u - 2 kdot'.u and a = kdot' - Kdot_j u.
+ * nu_j = max over candidates of |J_A - J_B| / |J_min|.
+ */
+
+/* Inverse of the SPD matrix A (n x n) through its Cholesky factor (L is
+ * scratch); 1 if A is not positive definite. */
+static int spd_inverse(const double *A, double *Ai, double *L, double *e, double *t, double *col, int n)
+{
+    if (cholesky(A, L, n)) return 1;
+    for (int c = 0; c < n; c++) {
+        for (int r = 0; r < n; r++) e[r] = r == c ? 1.0 : 0.0;
+        forward_solve(L, e, t, n);
+        backward_solve_t(L, t, col, n);
+        for (int r = 0; r < n; r++) Ai[r * n + c] = col[r];
+    }
+    return 0;
+}
+
+typedef struct {
+    double *K, *Kd, *Ki, *L, *A1, *Ki1, *Kd1, *W, *e, *t, *col, *h, *hd, *al, *wv, *tmp, *kc, *kdc, *u, *a,
+        *ta, *k1;
+    int32_t *slot;
+    uint8_t *chosen;
+} mspe_work;
+
+static int mspe_alloc(mspe_work *w, int n, int Np)
+{
+    size_t n1 = (size_t)(n + 1);
+    double **mats[] = {&w->K, &w->Kd, &w->Ki, &w->L, &w->A1, &w->Ki1, &w->Kd1, &w->W};
+    for (int q = 0; q < 8; q++) *mats[q] = (double *)malloc(sizeof(double) * n1 * n1);
+    double **vecs[] = {&w->e, &w->t, &w->col, &w->h, &w->hd, &w->al, &w->wv, &w->tmp, &w->kc, &w->kdc, &w->u,
+                       &w->a, &w->ta, &w->k1};
+    for (int q = 0; q < 14; q++) *vecs[q] = (double *)malloc(sizeof(double) * n1);
+    w->slot = (int32_t *)malloc(sizeof(int32_t) * n1);
+    w->chosen = (uint8_t *)malloc((size_t)Np);
+    int ok = w->slot && w->chosen;
+    for (int q = 0; q < 8; q++) ok = ok && *mats[q];
+    for (int q = 0; q < 14; q++) ok = ok && *vecs[q];
+    return ok;
+}
+
+static void mspe_free(mspe_work *w)
+{
+    double *all[] = {w->K, w->Kd, w->Ki, w->L, w->A1, w->Ki1, w->Kd1, w->W, w->e, w->t, w->col, w->h, w->hd,
+                     w->al, w->wv, w->tmp, w->kc, w->kdc, w->u, w->a, w->ta, w->k1};
+    for (int q = 0; q < 22; q++) free(all[q]);
+    free(w->slot);
+    free(w->chosen);
+}
+
+/* Correlation and its derivative in d for two rows. */
+static void kern_dk(const double *a, const double *b, int p, double d, double *k, double *kd)
+{
+    const double r2 = sqdist(a, b, p);
+    *k = exp(-r2 / d);
+    *kd = *k * r2 / (d * d);
+}
+
+/* One location.  Per step j (entries j < n0 describe the NN start): sel, the
+ * criterion of the choice (jsel), the smallest criterion (jmin) and its design
+ * index (amin), the route noise (nu, mode B), d mu_j / dd (dmu) and G_{j+1}
+ * of the choice (gsel).  pred as in orc_alc. */
+static int mspe_one(const double *X, const double *Y, int p, const double *x, const int32_t *pool, int Np,
+                    int n0, int n, double d, double g, const int32_t *forced, int mode_b, int32_t *sel,
+                    double *jsel, double *jmin, int32_t *amin, double *nu, double *dmu, double *gsel,
+                    double *pred, mspe_work *w)
+{
+    const double kappa = 1.0 + g;
+    for (int k = 0; k < p; k++)
+        if (!isfinite(x[k])) return ORC_NONFINITE;
+    memset(w->chosen, 0, (size_t)Np);
+    for (int q = 0; q < 5; q++) pred[q] = NAN;
+    for (int j = 0; j < n; j++) {
+        sel[j] = amin[j] = -1;
+        jsel[j] = jmin[j] = nu[j] = dmu[j] = gsel[j] = NAN;
+    }
+    int rc = ORC_OK;
+    for (int j = 0; j < n; j++) {
+        int take = -1;
+        if (j < n0) {
+            if (forced) {
+                for (int s = 0; s < Np; s++)
+                    if (pool[s] == forced[j]) { take = s; break; }
+                if (take < 0 || w->chosen[take]) { rc = ORC_BAD_FORCED; break; }
+            } else {
+                take = j;
+            }
+        } else {
+            /* the current design: K_j, Kdot_j, K_j^{-1}, alpha, w = K^{-1} h, psi_j, v_j */
+            for (int a = 0; a < j; a++) {
+                const double *xa = X + (int64_t)pool[w->slot[a]] * p;
+                for (int b = 0; b < j; b++) {
+                    double kv, kdv;
+                    kern_dk(xa, X + (int64_t)pool[w->slot[b]] * p, p, d, &kv, &kdv);
+                    w->K[a * j + b] = kv + (a == b ? g : 0.0);
+                    w->Kd[a * j + b] = kdv;
+                }
+                kern_dk(xa, x, p, d, &w->h[a], &w->hd[a]);
+            }
+            if (spd_inverse(w->K, w->Ki, w->L, w->e, w->t, w->col, j)) { rc = ORC_STEP_FAIL; break; }
+            double psi = 0.0, hw = 0.0, hd_al = 0.0, w_kd_al = 0.0;
+            for (int a = 0; a < j; a++) {
+                w->al[a] = 0.0;
+                w->wv[a] = 0.0;
+                for (int b = 0; b < j; b++) {
+                    w->al[a] += w->Ki[a * j + b] * Y[pool[w->slot[b]]];
+                    w->wv[a] += w->Ki[a * j + b] * w->h[b];
+                }
+            }
+            for (int a = 0; a < j; a++) {
+                psi += Y[pool[w->slot[a]]] * w->al[a];
+                hw += w->h[a] * w->wv[a];
+                hd_al += w->hd[a] * w->al[a];
+                double kda = 0.0;
+                for (int b = 0; b < j; b++) kda += w->Kd[a * j + b] * w->al[b];
+                w_kd_al += w->wv[a] * kda;
+            }
+            const double vj = kappa - hw;
+            const double dm = hd_al - w_kd_al;  /* d mu_j / dd */
+            const double coef = (j + 1) * psi / ((double)j * (j - 1));
+            /* mode B constants: tr(K^{-1} Kdot) and tr((K^{-1} Kdot)^2) */
+            double T1 = 0.0, T2 = 0.0;
+            if (mode_b) {
+                for (int a = 0; a < j; a++)
+                    for (int b = 0; b < j; b++) {
+                        double s = 0.0;
+                        for (int c = 0; c < j; c++) s += w->Ki[a * j + c] * w->Kd[c * j + b];
+                        w->W[a * j + b] = s;
+                    }
+                for (int a = 0; a < j; a++) {
+                    T1 += w->W[a * j + a];
+                    for (int b = 0; b < j; b++) T2 += w->W[a * j + b] * w->W[b * j + a];
+                }
+            }
+            double best = INFINITY, maxdiff = 0.0, fj = NAN, fg = NAN, bg = NAN;
+            int best_slot = -1, fslot = -1;
+            const int J1 = j + 1;
+            for (int s = 0; s < Np; s++) {
+                if (w->chosen[s]) continue;
+                const double *xc = X + (int64_t)pool[s] * p;
+                for (int a = 0; a < j; a++) kern_dk(X + (int64_t)pool[w->slot[a]] * p, xc, p, d, &w->kc[a], &w->kdc[a]);
+                double kcx, kdcx;
+                kern_dk(xc, x, p, d, &kcx, &kdcx);
+                /* mode A: K_{j+1} and Kdot_{j+1} written out, a fresh inverse */
+                for (int a = 0; a < J1; a++)
+                    for (int b = 0; b < J1; b++) {
+                        double kv, kdv;
+                        if (a < j && b < j) {
+                            kv = w->K[a * j + b];
+                            kdv = w->Kd[a * j + b];
+                        } else if (a < j) {
+                            kv = w->kc[a];
+                            kdv = w->kdc[a];
+                        } else if (b < j) {
+                            kv = w->kc[b];
+                            kdv = w->kdc[b];
+                        } else {
+                            kv = kappa;
+                            kdv = 0.0;
+                        }
+                        w->A1[a * J1 + b] = kv;
+                        w->Kd1[a * J1 + b] = kdv;
+                    }
+                double crit = INFINITY, G = NAN;
+                if (!spd_inverse(w->A1, w->Ki1, w->L, w->e, w->t, w->col, J1)) {
+                    for (int a = 0; a < j; a++) w->k1[a] = w->h[a];
+                    w->k1[j] = kcx;
+                    double q = 0.0;
+                    for (int a = 0; a < J1; a++) {
+                        double r = 0.0;
+                        for (int b = 0; b < J1; b++) r += w->Ki1[a * J1 + b] * w->k1[b];
+                        q += w->k1[a] * r;
+                    }
+                    const double v1 = kappa - q;
+                    double tW = 0.0, tW2 = 0.0;
+                    for (int a = 0; a < J1; a++)
+                        for (int b = 0; b < J1; b++) {
+                            double r = 0.0;
+                            for (int c = 0; c < J1; c++) r += w->Ki1[a * J1 + c] * w->Kd1[c * J1 + b];
+                            w->W[a * J1 + b] = r;
+                        }
+                    for (int a = 0; a < J1; a++) {
+                        tW += w->W[a * J1 + a];
+                        for (int b = 0; b < J1; b++) tW2 += w->W[a * J1 + b] * w->W[b * J1 + a];
+                    }
+                    G = 0.5 * (tW2 - tW * tW / J1);
+                    if (G > 0.0) crit = coef * v1 + dm * dm / G;
+                }
+                if (mode_b) {
+                    /* the same criterion through the partitioned inverse */
+                    double sB = kappa, covB = kcx, e = 0.0, aKa = 0.0;
+                    for (int a = 0; a < j; a++) {
+                        w->u[a] = 0.0;
+                        for (int b = 0; b < j; b++) w->u[a] += w->Ki[a * j + b] * w->kc[b];
+                    }
+                    for (int a = 0; a < j; a++) {
+                        sB -= w->kc[a] * w->u[a];
+                        covB -= w->h[a] * w->u[a];
+                        double kdu = 0.0;
+                        for (int b = 0; b < j; b++) kdu += w->Kd[a * j + b] * w->u[b];
+                        e += w->u[a] * kdu - 2.0 * w->kdc[a] * w->u[a];
+                        w->a[a] = w->kdc[a] - kdu;
+                    }
+                    for (int a = 0; a < j; a++) {
+                        double r = 0.0;
+                        for (int b = 0; b < j; b++) r += w->Ki[a * j + b] * w->a[b];
+                        aKa += w->a[a] * r;
+                    }
+                    double critB = INFINITY;
+                    if (sB > 0.0) {
+                        const double v1 = vj - covB * covB / sB;
+                        const double tW = T1 + e / sB, tW2 = T2 + 2.0 * aKa / sB + e * e / (sB * sB);
+                        const double GB = 0.5 * (tW2 - tW * tW / J1);
+                        if (GB > 0.0) critB = coef * v1 + dm * dm / GB;
+                    }
+                    if (isfinite(crit) && isfinite(critB)) {
+                        const double df = fabs(crit - critB);
+                        if (df > maxdiff) maxdiff = df;
+                    }
+                }
+                if (forced && pool[s] == forced[j]) { fj = crit; fslot = s; fg = G; }
+                if (crit < best || (crit == best && best_slot >= 0 && pool[s] < pool[best_slot])) {
+                    best = crit;
+                    best_slot = s;
+                    bg = G;
+                }
+            }
+            if (best_slot < 0 || !isfinite(best)) { rc = ORC_STEP_FAIL; break; }
+            jmin[j] = best;
+            amin[j] = pool[best_slot];
+            nu[j] = mode_b ? maxdiff / fabs(best) : NAN;
+            dmu[j] = dm;
+            if (forced) {
+                if (fslot < 0) { rc = ORC_BAD_FORCED; break; }
+                take = fslot;
+                jsel[j] = fj;
+                gsel[j] = fg;
+            } else {
+                take = best_slot;
+                jsel[j] = best;
+                gsel[j] = bg;
+            }
+        }
+        w->chosen[take] = 1;
+        w->slot[j] = take;
+        sel[j] = pool[take];
+    }
+    if (rc == ORC_OK) {
+        double *Dn = w->Ki1, *Yn = w->k1;
+        for (int a = 0; a < n; a++) {
+            memcpy(Dn + (size_t)a * p, X + (int64_t)sel[a] * p, sizeof(double) * p);
+            Yn[a] = Y[sel[a]];
+        }
+        if (orc_gp_predict(Dn, Yn, n, p, x, d, g, pred)) rc = ORC_STEP_FAIL;
+    }
+    return rc;
+}
+
+/* Batched MSPE designs (OpenMP over locations); outputs M x n (pred M x 5). */
+int orc_mspe(const double *X, const double *Y, int64_t N, int p, const double *XX, int64_t M,
+             const int32_t *pool, int Np, int n0, int n, double d, double g, const int32_t *forced, int mode_b,
+             int nthreads, int32_t *sel, double *jsel, double *jmin, int32_t *amin, double *nu, double *dmu,
+             double *gsel, double *pred, int32_t *status)
+{
+    if (!(d > 0.0) || !(g > 0.0) || !isfinite(d) || !isfinite(g) || p < 1 || n0 < 2 || n0 > n || n > Np ||
+        Np > N)
+        return ORC_BAD_ARGS;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        mspe_work w;
+        int ok = mspe_alloc(&w, n, Np) && p <= n + 1;  /* Dn reuses an (n + 1)^2 buffer */
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t m = 0; m < M; m++) {
+            const int64_t o = m * (int64_t)n;
+            int rc = ok ? mspe_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np, Np, n0, n, d, g,
+                                   forced ? forced + o : NULL, mode_b, sel + o, jsel + o, jmin + o, amin + o,
+                                   nu + o, dmu + o, gsel + o, pred + m * 5, &w)
+                        : ORC_BAD_ARGS;
+            if (rc != ORC_OK)
+                for (int q = 0; q < 5; q++) pred[m * 5 + q] = NAN;
+            status[m] = rc;
+        }
+        mspe_free(&w);
+    }
+    return ORC_OK;
+}

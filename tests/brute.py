@@ -111,3 +111,49 @@ def nll_by_quadrature(D: np.ndarray, Yd: np.ndarray, d: float, g: float) -> floa
     val, _ = integrate.quad(lambda u: math.exp(log_f(u) - c), umode - 40, umode + 40, limit=400,
                             epsabs=0, epsrel=1e-12)
     return -(c + math.log(val))
+
+
+def mu_of(D: np.ndarray, Yd: np.ndarray, x: np.ndarray, d: float, g: float) -> float:
+    """Predictive mean k^T K^{-1} Y (eq. predgp) via numpy.linalg.solve."""
+    K = corr(D, D, d) + g * np.eye(D.shape[0])
+    return corr(D, x[None, :], d)[:, 0] @ np.linalg.solve(K, Yd)
+
+
+def mspe_criterion(D: np.ndarray, Yd: np.ndarray, x: np.ndarray, c: np.ndarray, d: float, g: float) -> float:
+    """J(c, x) of eq. mspe by brute force: V_j(x | c) of eq. newv from a fresh
+    solve on the design with c appended, d mu_j / dd by central differences of
+    the mean in d, and G_{j+1} = (tr W^2 - tr(W)^2 / (j + 1)) / 2 with
+    W = K_{j+1}^{-1} dK_{j+1}/dd from numpy.linalg.solve."""
+    j = D.shape[0]
+    K = corr(D, D, d) + g * np.eye(j)
+    psi = Yd @ np.linalg.solve(K, Yd)
+    D1 = np.vstack([D, c[None, :]])
+    v1 = v_of(D1, x, d, g)
+    h = 1e-4 * d
+    dmu = (mu_of(D, Yd, x, d + h, g) - mu_of(D, Yd, x, d - h, g)) / (2 * h)
+    R2 = np.zeros((j + 1, j + 1))
+    for k in range(D1.shape[1]):
+        t = D1[:, k][:, None] - D1[:, k][None, :]
+        R2 = R2 + t * t
+    K1 = np.exp(-R2 / d) + g * np.eye(j + 1)
+    W = np.linalg.solve(K1, np.exp(-R2 / d) * R2 / d ** 2)
+    G = 0.5 * (np.trace(W @ W) - np.trace(W) ** 2 / (j + 1))
+    return (j + 1) * psi / (j * (j - 1)) * v1 + dmu * dmu / G
+
+
+def greedy_mspe(X: np.ndarray, Y: np.ndarray, x: np.ndarray, P: np.ndarray, n0: int, n: int, d: float,
+                g: float):
+    """Designs minimising eq. mspe by brute force: returns (sel, criterion per step)."""
+    sel = list(P[:n0])
+    best = []
+    for _ in range(n0, n):
+        D, Yd = X[sel], Y[sel]
+        scores = []
+        for c in P:
+            if c in sel:
+                continue
+            scores.append((mspe_criterion(D, Yd, x, X[c], d, g), c))
+        s, c = min(scores)
+        sel.append(c)
+        best.append(s)
+    return np.array(sel, dtype=np.int32), np.array(best)

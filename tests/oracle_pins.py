@@ -46,6 +46,12 @@ What pins what:
                       h = K(X_j, x) from numpy; the one-point closed form
   scores_greedy     - the batch scores at a step of a greedy run reproduce that
                       step's best score and argmax
+  mspe_brute        - designs by the MSPE criterion (eq. mspe) = brute force with
+                      fresh solves, central differences of the mean in d and
+                      numpy traces for the expected information
+  mspe_parts        - the criterion splits into eq. newv's variance term, whose
+                      v_j and psi_j the ALC route gives independently, plus
+                      (d mu / dd)^2 / G; the partitioned-inverse route agrees
   per_location_d    - a lengthscale of each location's own (the second design
                       stage of Fig. 1 step 4) gives, location by location,
                       the run with that scalar lengthscale; invalid entries
@@ -464,7 +470,45 @@ def per_location_d(orc):
     assert np.array_equal(f["sel"][[0, 2, 4]], a["sel"][[0, 2, 4]])
 
 
+def mspe_brute(orc):
+    X, Y, XX = workloads.uniform(8, 70, 2, 3)
+    d, g, n0, n, Np = 0.15, 1e-3, 3, 9, 25
+    pool = orc.nn_pool(X, XX, Np)
+    out = orc.mspe(X, Y, XX, pool, n0, n, d, g)
+    assert np.all(out["status"] == 0)
+    for m in range(XX.shape[0]):
+        sel, best = brute.greedy_mspe(X, Y, XX[m], pool[m], n0, n, d, g)
+        assert np.array_equal(out["sel"][m], sel), (m, out["sel"][m], sel)
+        assert _rel(out["jsel"][m, n0:], best) < 1e-7, m
+        # d mu / dd against central differences of the mean
+        for j in (n0, n - 1):
+            D, Yd = X[out["sel"][m, :j]], Y[out["sel"][m, :j]]
+            h = 1e-4 * d
+            fd = (brute.mu_of(D, Yd, XX[m], d + h, g) - brute.mu_of(D, Yd, XX[m], d - h, g)) / (2 * h)
+            assert abs(out["dmu"][m, j] - fd) <= 1e-7 * max(1e-3, abs(fd)), (m, j)
+
+
+def mspe_parts(orc):
+    W = workloads.make(4, N=3000, M=4)
+    n0, n, Np = 6, 18, 120
+    pool = orc.nn_pool(W.X, W.XX, Np)
+    out = orc.mspe(W.X, W.Y, W.XX, pool, n0, n, 0.2, W.g, mode_b=True)
+    assert np.all(out["status"] == 0)
+    assert np.nanmax(out["nu"]) < 1e-8, np.nanmax(out["nu"])
+    # along the MSPE sequence, the ALC route's v_j, score and psi_j rebuild the
+    # variance term: J - dmu^2 / G = (j + 1) psi_j / (j (j - 1)) (v_j - Delta)
+    a = orc.alc(W.X, W.Y, W.XX, pool, n0, n, 0.2, W.g, forced=out["sel"])
+    for m in range(W.M):
+        for j in range(n0, n):
+            var_term = (j + 1) * a["psitraj"][m, j] / (j * (j - 1)) * (a["vtraj"][m, j] - a["dsel"][m, j])
+            got = out["jsel"][m, j] - out["dmu"][m, j] ** 2 / out["gsel"][m, j]
+            assert abs(got - var_term) <= 1e-9 * abs(out["jsel"][m, j]), (m, j)
+    # every choice is the minimiser it reports
+    assert np.array_equal(out["sel"][:, n0:], out["amin"][:, n0:])
+    assert np.all(out["gsel"][:, n0:] > 0)
+
+
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
        special_cases, design_point, predict_textbook, route_b, predict_b, psi_trajectory, forced,
        nll_textbook, nll_derivatives_fd, mle_optimality, mle_global, local_mle_batched, scores_brute,
-       scores_greedy, per_location_d]
+       scores_greedy, mspe_brute, mspe_parts, per_location_d]

@@ -63,6 +63,16 @@ MUTANTS = {
                       "tr->psitraj[j] = j > 0 ? dot(w->yj, w->yj, j) : 0.0;"),
     # batched MLE gathering the first location's responses for every design
     "local_mle_gather": ("Yn[a] = Y[sel[m * n + a]];", "Yn[a] = Y[sel[a]];"),
+    # MSPE: expected information without the unknown scale's share
+    "mspe_info_no_scale": ("G = 0.5 * (tW2 - tW * tW / J1);", "G = 0.5 * tW2;"),
+    # MSPE: mean derivative without the K^{-1} Kdot K^{-1} term
+    "mspe_dmu_one_term": ("const double dm = hd_al - w_kd_al;", "const double dm = hd_al;"),
+    # MSPE: variance factor (j + 1) psi / (j (j - 1)) with j - 1 replaced by j
+    "mspe_coef": ("const double coef = (j + 1) * psi / ((double)j * (j - 1));",
+                  "const double coef = (j + 1) * psi / ((double)j * j);"),
+    # MSPE: the largest criterion chosen instead of the smallest
+    "mspe_argmax": ("if (crit < best || (crit == best && best_slot >= 0 && pool[s] < pool[best_slot])) {",
+                    "if (!(crit <= best) || best_slot < 0 || (crit == best && pool[s] < pool[best_slot])) {"),
     # Newton iteration stopping on the first backtracking success without moving on
     "mle_one_step": ("        if (moved <= 1e-10 * d) { status = 0; it++; break; }",
                      "        status = 0; it++; break;"),
