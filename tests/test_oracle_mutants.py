@@ -15,8 +15,12 @@ MUTANTS = {
     # the sign slip of Fig. 3 step 5 taken literally: (c + u.h)^2 / s
     "cov_sign": ("double cov = kcx - dot(w->zc, w->zh, j);", "double cov = kcx + dot(w->zc, w->zh, j);"),
     # nugget dropped from the candidate self-covariance
-    "kappa_no_nugget": ("    const double kappa = 1.0 + g;\n    for (int k = 0; k < p; k++)",
-                        "    const double kappa = 1.0;\n    for (int k = 0; k < p; k++)"),
+    "kappa_no_nugget": ("    const double kappa = 1.0 + g;\n    for (int k = 0; k < p; k++)\n"
+                        "        if (!isfinite(x[k])) return ORC_NONFINITE;\n    memset(w->chosen, 0, (size_t)Np);\n"
+                        "    for (int q = 0; q < 5; q++) tr->pred",
+                        "    const double kappa = 1.0;\n    for (int k = 0; k < p; k++)\n"
+                        "        if (!isfinite(x[k])) return ORC_NONFINITE;\n    memset(w->chosen, 0, (size_t)Np);\n"
+                        "    for (int q = 0; q < 5; q++) tr->pred"),
     # nugget wrongly added to the cross-covariance with x
     "nugget_on_h": ("w->h[a] = kern(xa, x, p, d);", "w->h[a] = kern(xa, x, p, d) + g;"),
     # transposed operand in the triangular solve
