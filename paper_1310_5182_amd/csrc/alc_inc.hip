@@ -466,6 +466,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             for (int jj = n + tid; jj < a.n; jj += TB) {
                 a.sel[orow + jj] = -1;
                 if (a.alc) a.alc[orow + jj] = NAN;
+                if (a.alc32) a.alc32[orow + jj] = NAN;
             }
         __syncthreads();  // LDS is restaged for the next location
     }
