@@ -136,6 +136,10 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
  *                           were not trusted and were redone in float64; 0 for
  *                           LAGP_FP64
  * Exact score ties go to the smallest design index.
+ * LAGP_MIXED uses float32 scores only where the nugget bounds the conditioning
+ * enough for them: cond(K_j) <= (j + g) / g, and (n + g) / g * 2^-24 <= 2^-4
+ * (n / g up to about 10^6, e.g. n = 50 with g >= 5e-5).  Otherwise the
+ * designs are computed in float64 with all n - n0 steps counted in guard.
  * Supported sizes: p <= 8 and Np <= 1024; LAGP_MIXED needs n <= 64,
  * LAGP_FP64_REFORM n <= 52, and LAGP_FP64 every candidate's factor row on
  * chip (n <= 50 at p = 8, N' = 1024; larger n at smaller p or N').  Others
@@ -251,9 +255,11 @@ typedef struct lagp_outputs {
  *   sel_off all NULL) run one workgroup per location with the arithmetic of
  *   `precision`; otherwise locations are ordered by cost on the device and
  *   drained by persistent workgroups.  With per-location sizes, LAGP_MIXED
- *   scores the locations with n_m <= 64 and N'_m <= 1024 in mixed precision
- *   and computes the others in float64, counting all of their n_m - n0 steps
- *   in guard[m]; LAGP_FP64_REFORM needs uniform sizes.
+ *   scores the locations with n_m <= 64, N'_m <= 1024 and
+ *   (n_m + g) / g * 2^-24 <= 2^-4 (the conditioning rule of
+ *   lagp_alc_from_pool) in mixed precision and computes the others in
+ *   float64, counting all of their n_m - n0 steps in guard[m];
+ *   LAGP_FP64_REFORM needs uniform sizes.
  *   workspace: device memory of at least lagp_alc_workspace bytes, 256-byte
  *   aligned (else LAGP_EWORKSPACE); calls that overlap must not share it.
  *   Supported: p <= 8, N' <= 2048, n <= 128 (float64; LAGP_MIXED n <= 64 and

@@ -31,8 +31,16 @@
 // re-score of every candidate within kBandTau of the float32 best, the Schur
 // complement of the chosen point, the update and the prediction stay in
 // float64.  A step whose float32 scores look untrustworthy (band overflow,
-// re-score disagreement above kTrustErr, a tiny float32 conditional variance)
+// re-score disagreement above kTrustErr, a tiny float32 conditional variance,
+// or a candidate outside the band that could still beat the best, see below)
 // is re-scored entirely in float64 and counted in guard[m].
+//
+// Float32 scores lose most where s = kappa - z.z is small (cancellation), so
+// the band members' re-scores also measure the absolute float32 errors of s
+// and of cov = K(c,x) - z.z_h; with delta = 8 times the larger of the two
+// (plus 2^-22 kappa), a candidate outside the band whose score could reach
+// the float64 best, (|cov| + delta)^2 / (s - delta) >= best (or s <= delta),
+// sends the step to float64.
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
@@ -135,10 +143,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     __shared__ int32_t selslot[NMAX];
     __shared__ T red_s[NW];
     __shared__ int32_t red_i[NW], red_k[NW];
-    __shared__ double rec_v[NW], rec_s[NW], rec_e[NW];
+    __shared__ double rec_v[NW], rec_s[NW], rec_e[NW], rec_d[NW];
+    __shared__ float fs32[MIXED ? SLOTS : 1], fc32[MIXED ? SLOTS : 1];  // float32 s and cov of each slot
     __shared__ float rec_v32[NW];
     __shared__ int32_t rec_i[NW], rec_k[NW], rec_n[NW];
-    __shared__ int ctl_status, ctl_susp;
+    __shared__ int ctl_status, ctl_susp, ctl_wide;
 
     const T *RA;
     const T *zhT;
@@ -171,6 +180,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
     if (tid == 0) {
         ctl_status = kLocOk;
         ctl_susp = 0;
+        ctl_wide = 0;
     }
     if (tid < p) xs[tid] = a.XX[m * p + tid];
     __syncthreads();
@@ -317,6 +327,10 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                     if constexpr (MIXED) {
                         if (live && !(sv > kSmallS * (float)kappa)) susp = true;
                         sc[cg + q] = score;
+                        if (lane < 16) {
+                            fs32[slot] = sv;
+                            fc32[slot] = cv;
+                        }
                     }
                     const int32_t di = score >= (T)0 ? cid[slot] : INT32_MAX;
                     if (beats(score, di, best_s, best_i)) {
@@ -365,7 +379,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
         // ===== (2) float64 re-score: each wave its own band members
         bool fallback = false;
         if constexpr (MIXED) fallback = j >= n0 && ctl_susp != 0;
-        double bv = -1.0, bsv = 0.0, err = 0.0;
+        double bv = -1.0, bsv = 0.0, err = 0.0, eabs = 0.0;
         float bv32 = -1.0f;  // float32 score of this wave's float64 best (-1: none)
         int32_t bi64 = INT32_MAX;
         int bk = -1, cnt = 0;
@@ -375,7 +389,11 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             const double cov = cxv[slot] - wave_sum(z * zh[lane]);
             const double v = s > 0.0 ? cov * cov / s : -1.0;
             const int32_t di = v >= 0.0 ? cid[slot] : INT32_MAX;
-            if (v32 >= 0.0) err = v > 0.0 ? fmax(err, fabs(v32 - v) / v) : INFINITY;
+            if (v32 >= 0.0) {
+                err = v > 0.0 ? fmax(err, fabs(v32 - v) / v) : INFINITY;
+                if constexpr (MIXED)
+                    eabs = fmax(eabs, fmax(fabs((double)fs32[slot] - s), fabs((double)fc32[slot] - cov)));
+            }
             if (beats(v, di, bv, bi64)) {
                 bv = v;
                 bi64 = di;
@@ -408,6 +426,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             rec_v[w] = bv;
             rec_s[w] = bsv;
             rec_e[w] = err;
+            rec_d[w] = eabs;
             rec_v32[w] = bv32;
             rec_i[w] = bi64;
             rec_k[w] = bk;
@@ -425,6 +444,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
             v = uniform(v);
             vw = __builtin_amdgcn_readfirstlane(vw);
             err = wave_max(lane < NW ? rec_e[lane] : 0.0);
+            eabs = wave_max(lane < NW ? rec_d[lane] : 0.0);
             total = (int)wave_sum(lane < NW ? (float)rec_n[lane] : 0.0f);
         } else {
             // few waves: a short serial pass keeps register pressure low
@@ -438,8 +458,27 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                     vw = q;
                 }
         }
-        if constexpr (MIXED)
+        if constexpr (MIXED) {
             if (j >= n0 && !fallback && (!(v > 0.0) || err > kTrustErr || total > kWaveBandCap)) fallback = true;
+            if (j >= n0 && !fallback) {
+                // every candidate outside the band: could its score reach the best?
+                const double delta = 8.0 * eabs + 0x1p-22 * kappa;
+                const float thr = (float)bs * (1.0f - kBandTau);
+                bool wide = false;
+                for (int t = lane; t < WSLOTS; t += kWave) {
+                    const int slot = wbase + t;
+                    if (cflag[slot] != 0) continue;
+                    const float s32 = fs32[slot], c32 = fc32[slot];
+                    const float sc32 = s32 > 0.0f ? c32 * c32 * __builtin_amdgcn_rcpf(s32) : -1.0f;
+                    if (sc32 >= thr) continue;  // a band member: re-scored in float64
+                    const double sd = (double)s32 - delta, cu = fabs((double)c32) + delta;
+                    if (!(sd > 0.0) || cu * cu / sd >= v * (1.0 - 0x1p-20)) wide = true;
+                }
+                if (__ballot(wide) && lane == 0) ctl_wide = 1;
+                __syncthreads();
+                if (ctl_wide) fallback = true;
+            }
+        }
         if (fallback) {
             // ===== the whole step in float64: each wave re-scores all its live candidates
             __syncthreads();
@@ -510,6 +549,7 @@ __global__ __launch_bounds__(NW *kWave) void alc_kernel(AlcArgs a)
                     alc_out32[j] = (j >= n0 && rec_v32[vw] >= 0.0f) ? rec_v32[vw] * (float)nf : NAN;
                 psi_run += tY[j] * tY[j];
                 ctl_susp = 0;
+                ctl_wide = 0;
             }
         }
         // new column j of Q, K(candidate, x*): one candidate per lane, then moved
@@ -618,6 +658,12 @@ hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st)
 {
     if (a.M == 0) return hipSuccess;
     if (precision == 0 && alc_inc_supported(a.p, a.Np, a.n)) return launch_alc_inc(a, st);
+    if (precision == 1 && !mixed_trusted(a.n, a.g) && alc_inc_supported(a.p, a.Np, a.n)) {
+        // float32 scores cannot be trusted at this conditioning: float64, every step in guard
+        AlcArgs b = a;
+        b.f64_guard = 1;
+        return launch_alc_inc(b, st);
+    }
     if (precision == 2) precision = 0;
     if (!mfma_supported(precision, a.p, a.Np, a.n)) return hipErrorNotSupported;
     if (precision == 0) {

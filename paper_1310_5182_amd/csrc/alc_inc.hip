@@ -658,7 +658,7 @@ __global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
         }
         return;
     }
-    if (w.mixed && n <= kMixNmax && Np <= kMixNpMax) {  // the mixed kernel takes it
+    if (w.mixed && n <= kMixNmax && Np <= kMixNpMax && mixed_trusted(n, a.g)) {  // the mixed kernel takes it
         const int l = Np <= kMixNpMax / 2 ? 0 : 1;
         w.mlist[l][atomicAdd(&w.mcount[l], 1)] = (int32_t)m;
         w.key[m] = -1;

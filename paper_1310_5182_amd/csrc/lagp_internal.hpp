@@ -110,9 +110,9 @@ hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1);
 // when d_per is not NULL, lengthscale d.
 bool alc_uneven_supported(int p, int Np_max, int n_max);
 hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes);
-// With `mixed`, locations with n_m <= 64 and N'_m <= 1024 run the mixed
-// (float32 MFMA) kernel and the others run in float64 with every step counted
-// in guard.
+// With `mixed`, locations with n_m <= 64, N'_m <= 1024 and
+// mixed_trusted(n_m, g) run the mixed (float32 MFMA) kernel and the others run
+// in float64 with every step counted in guard.
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
                              const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
                              hipStream_t st, int bcast = -1, bool mixed = false);
@@ -120,6 +120,16 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
 // sizes from a's per-location fields); `big` selects the 1024-slot schedule.
 hipError_t launch_alc_mixed_list(const AlcArgs &a, bool big, hipStream_t st);
 constexpr int kMixNmax = 64, kMixNpMax = 1024;
+// Float32 scores are used only where the nugget keeps every K_j well enough
+// conditioned for them: the correlation part of K_j has eigenvalues in
+// [0, j], so cond(K_j) <= (j + g) / g, and float32 scoring is trusted while
+// that bound for the whole design times the float32 unit roundoff 2^-24 is at
+// most 2^-4 (n / g up to about 10^6).  Other locations asking for mixed
+// precision run in float64 with every step counted in guard.
+__host__ __device__ inline bool mixed_trusted(int n, double g)
+{
+    return (n + g) / g * 0x1p-24 <= 0x1p-4;
+}
 
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {

@@ -366,21 +366,50 @@ __global__ __launch_bounds__(kGpThreads) void local_gp_kernel(GpArgs a)
         if (!bad_sel) {
             const int ta = tid >> 4 & 15, tb = tid & 15;
             for (int r = ta; r < n; r += 16)
-                for (int b = tb; b < n; b += 16) W.M1[r * S + b] = exp(-W.r2(r, b) / d_in) + (r == b ? g : 0.0);
+                for (int b = tb; b < n; b += 16) {
+                    const double k = exp(-W.r2(r, b) / d_in) + (r == b ? g : 0.0);
+                    W.M1[r * S + b] = k;
+                    W.M2[r * S + b] = k;  // K itself, kept for the refinement below
+                }
             __syncthreads();
             if (!W.invert()) {
                 st = 1;
             } else {
-                // h in rowk, then A h and A Y row by row
+                // h in rowk; alpha = A Y (colk) and u = A h (piv) row by row.  The
+                // sweep's inverse carries an error of order cond(K) eps, so both
+                // solves get one step of iterative refinement against K:
+                // alpha += A (Y - K alpha), u += A (h - K u), the residuals kept in
+                // the unused last column of M2 and M1 (row stride n + 1).
                 if (tid < n) W.rowk[tid] = corr64(sqdist_strict(W.xs + tid * p, 1, x, 1, p), d_in);
                 __syncthreads();
-                double s[3] = {0.0, 0.0, 0.0};  // h.A.Y, Y.A.Y, h.A.h
                 if (tid < n) {
                     double ay = 0.0, ah = 0.0;
                     for (int b = 0; b < n; b++) {
                         ay = fma(W.M1[tid * S + b], W.ys[b], ay);
                         ah = fma(W.M1[tid * S + b], W.rowk[b], ah);
                     }
+                    W.colk[tid] = ay;
+                    W.piv[tid] = ah;
+                }
+                __syncthreads();
+                if (tid < n) {
+                    double ky = 0.0, kh = 0.0;
+                    for (int b = 0; b < n; b++) {
+                        ky = fma(W.M2[tid * S + b], W.colk[b], ky);
+                        kh = fma(W.M2[tid * S + b], W.piv[b], kh);
+                    }
+                    W.M2[tid * S + n] = W.ys[tid] - ky;
+                    W.M1[tid * S + n] = W.rowk[tid] - kh;
+                }
+                __syncthreads();
+                double s[3] = {0.0, 0.0, 0.0};  // h.A.Y, Y.A.Y, h.A.h
+                if (tid < n) {
+                    double cy = 0.0, ch = 0.0;
+                    for (int b = 0; b < n; b++) {
+                        cy = fma(W.M1[tid * S + b], W.M2[b * S + n], cy);
+                        ch = fma(W.M1[tid * S + b], W.M1[b * S + n], ch);
+                    }
+                    const double ay = W.colk[tid] + cy, ah = W.piv[tid] + ch;
                     s[0] = W.rowk[tid] * ay;
                     s[1] = W.ys[tid] * ay;
                     s[2] = W.rowk[tid] * ah;
