@@ -180,6 +180,34 @@ lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double
                             int32_t precision, double *delta, void *stream);
 
 /*
+ * lagp_mspe_workspace -- bytes of device workspace lagp_mspe_from_pool needs
+ *   for M locations with pools of Np and designs of n points (about
+ *   16 n Np bytes per resident workgroup; 0 for M = 0).
+ * lagp_mspe_from_pool -- local designs by the MSPE criterion (Sec. 2.2,
+ *   eq. mspe with the variance term of eq. newv) instead of ALC, and the
+ *   local predictions on them.  From the NN start of n0 pool points, step j
+ *   adds the candidate minimising
+ *     J(x') = (j + 1) psi_j / (j (j - 1)) v_{j+1}(x) + (d mu_j / dd)^2 / G_{j+1}
+ *   with psi_j = Y_j^T K_j^{-1} Y_j, v_{j+1}(x) the predictive variance term
+ *   kappa - k^T K^{-1} k on X_j + {x'}, d mu_j / dd the derivative of the
+ *   predictive mean (eq. predgp) in the lengthscale, and G_{j+1} read as the
+ *   expected information about d in j + 1 responses of N(0, tau^2 K_{j+1})
+ *   with the scale tau^2 unknown: (tr(W^2) - tr(W)^2 / (j + 1)) / 2,
+ *   W = K_{j+1}^{-1} dK_{j+1}/dd.  Exact ties go to the smaller design index.
+ *   Arguments, pools, outputs and status codes as for lagp_alc_from_pool
+ *   (float64 only); crit [M x n] receives J of each chosen point (NaN for
+ *   j < n0).  workspace: at least lagp_mspe_workspace(M, Np, n) bytes,
+ *   256-byte aligned (else LAGP_EWORKSPACE); calls that overlap must not
+ *   share it.  Requires 2 <= n0 <= n <= Np <= N (EINVAL); supported p <= 8,
+ *   Np <= 1024, n <= 64 (else LAGP_EUNSUPPORTED).  M = 0 is a no-op.
+ */
+lagp_status lagp_mspe_workspace(int64_t M, int32_t Np, int32_t n, size_t *bytes);
+lagp_status lagp_mspe_from_pool(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
+                                int64_t M, const int32_t *pool, int32_t Np, int32_t n0, int32_t n, double d,
+                                double g, double *mean, double *s2, double *var, int32_t *sel, double *crit,
+                                int32_t *status, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * ---------------------------------------------------------------------------
  * The whole hot path in one call: problem and outputs as structs.
  *

@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_FP64_REFORM, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "alc_scores", "alc_multistage", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
+__all__ = ["nn_pool", "mspe_from_pool", "mspe_predict", "alc_scores", "alc_multistage", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED, "fp64_reform": LAGP_FP64_REFORM}
@@ -147,6 +147,44 @@ def alc_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, precision
         float(d), float(g), _prec(precision), o["mean"].data_ptr(), o["s2"].data_ptr(),
         o["var"].data_ptr(), o["sel"].data_ptr(), o["alc"].data_ptr(), o["alc32"].data_ptr(),
         o["status"].data_ptr(), o["guard"].data_ptr(), _stream(X.device)))
+    return o
+
+
+def mspe_from_pool(X, Y, XX, pool, n0: int, n: int, d: float, g: float, out: dict | None = None,
+                   workspace: torch.Tensor | None = None) -> dict:
+    """Local designs by the MSPE criterion (eq. mspe, lagp_mspe_from_pool) from
+    given pools, and the predictions on them; out["crit"] holds the criterion
+    of each chosen point.  The workspace (uint8 device tensor) is allocated
+    here if None or too small."""
+    L = _lib.load()
+    X, Y, XX = _check_xy(X, Y, XX)
+    M, p = XX.shape
+    pool = _pool_arg(pool, M, X.device)
+    Np = pool.shape[1]
+    o = _outputs(M, n, X.device, out)
+    if "crit" not in o:
+        o["crit"] = torch.empty((M, n), dtype=torch.float64, device=X.device)
+    elif (o["crit"].dtype != torch.float64 or not o["crit"].is_contiguous() or o["crit"].device != X.device
+          or o["crit"].numel() != M * n):
+        raise ValueError(f"out['crit'] must be a contiguous float64 tensor of {M * n} elements on {X.device}")
+    nbytes = ctypes.c_size_t(0)
+    _lib.check(L.lagp_mspe_workspace(M, Np, n, ctypes.byref(nbytes)))
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=X.device)
+    _lib.check(L.lagp_mspe_from_pool(
+        X.data_ptr(), Y.data_ptr(), X.shape[0], p, XX.data_ptr(), M, pool.data_ptr(), Np, n0, n,
+        float(d), float(g), o["mean"].data_ptr(), o["s2"].data_ptr(), o["var"].data_ptr(), o["sel"].data_ptr(),
+        o["crit"].data_ptr(), o["status"].data_ptr(), workspace.data_ptr(), workspace.numel(),
+        _stream(X.device)))
+    o["workspace"] = workspace
+    return o
+
+
+def mspe_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, out: dict | None = None) -> dict:
+    """Grid-pruned NN pools, then MSPE designs and predictions (eq. mspe)."""
+    pool = nn_pool(X, XX, Np, grid=True)
+    o = mspe_from_pool(X, Y, XX, pool, n0, n, d, g, out=out)
+    o["pool"] = pool
     return o
 
 

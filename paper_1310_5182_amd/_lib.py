@@ -49,6 +49,8 @@ EXPORTS = (
     "lagp_nn_pool_workspace",
     "lagp_nn_pool_ws",
     "lagp_alc_scores",
+    "lagp_mspe_workspace",
+    "lagp_mspe_from_pool",
     "lagp_alc_from_pool",
     "lagp_alc_workspace",
     "lagp_alc_predict",
@@ -94,6 +96,11 @@ def load():
     L.lagp_nn_pool_workspace.restype = i32
     L.lagp_nn_pool_ws.argtypes = [P, i64, i32, P, i64, i32, P, P, ctypes.c_size_t, P]
     L.lagp_nn_pool_ws.restype = i32
+    L.lagp_mspe_workspace.argtypes = [i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.lagp_mspe_workspace.restype = i32
+    L.lagp_mspe_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, P, P, P, P, P, P, P,
+                                      ctypes.c_size_t, P]
+    L.lagp_mspe_from_pool.restype = i32
     L.lagp_alc_scores.argtypes = [P, i32, i32, P, P, i64, P, P, f64, f64, i32, P, P]
     L.lagp_alc_scores.restype = i32
     L.lagp_alc_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, i32,

@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]
-SOURCES = ["lagp_api.cpp", "plan.cpp", "nn_pool.hip", "alc.hip", "alc_inc.hip", "alc_scores.hip", "local_mle.hip"]
+SOURCES = ["lagp_api.cpp", "plan.cpp", "nn_pool.hip", "alc.hip", "alc_inc.hip", "alc_scores.hip", "local_mle.hip", "mspe.hip"]
 
 
 def _compile(src: str, extra: list[str]) -> str:

@@ -158,6 +158,49 @@ lagp_status lagp_alc_from_pool(const double *X, const double *Y, int64_t N, int3
     return ok();
 }
 
+lagp_status lagp_mspe_workspace(int64_t M, int32_t Np, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(LAGP_EINVAL, "bytes must be non-NULL");
+    if (M < 0) return fail(LAGP_EINVAL, "M = %lld < 0", (long long)M);
+    if (Np < 1 || n < 1) return fail(LAGP_EINVAL, "Np = %d and n = %d must be >= 1", Np, n);
+    if (Np > lagp::kMspeNpMax || n > lagp::kMspeNmax)
+        return fail(LAGP_EUNSUPPORTED, "MSPE designs need Np <= %d and n <= %d", lagp::kMspeNpMax, lagp::kMspeNmax);
+    if (M == 0) {
+        *bytes = 0;
+        return ok();
+    }
+    hipError_t e = lagp::mspe_workspace(M, Np, n, bytes);
+    if (e != hipSuccess) return hip_fail(e, "workspace query");
+    return ok();
+}
+
+lagp_status lagp_mspe_from_pool(const double *X, const double *Y, int64_t N, int32_t p, const double *XX,
+                                int64_t M, const int32_t *pool, int32_t Np, int32_t n0, int32_t n, double d,
+                                double g, double *mean, double *s2, double *var, int32_t *sel, double *crit,
+                                int32_t *status, void *workspace, size_t workspace_bytes, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    s = check_alc(Y, Np, n0, n, d, g, LAGP_FP64, sel, M);
+    if (s != LAGP_OK) return s;
+    if (n0 < 2) return fail(LAGP_EINVAL, "MSPE designs need n0 >= 2 (eq. newv divides by j (j - 1))");
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (p > lagp::kMspePmax || Np > lagp::kMspeNpMax || n > lagp::kMspeNmax)
+        return fail(LAGP_EUNSUPPORTED, "MSPE designs need p <= %d, Np <= %d and n <= %d", lagp::kMspePmax,
+                    lagp::kMspeNpMax, lagp::kMspeNmax);
+    if (M == 0) return ok();
+    size_t need = 0;
+    hipError_t e = lagp::mspe_workspace(M, Np, n, &need);
+    if (e != hipSuccess) return hip_fail(e, "workspace query");
+    if (!workspace || ((uintptr_t)workspace & 255) || workspace_bytes < need)
+        return fail(LAGP_EWORKSPACE, "workspace must be 256-byte aligned and hold %zu bytes (%zu given)", need,
+                    workspace_bytes);
+    lagp::AlcArgs a{X, Y, N, p, XX, M, pool, Np, n0, n, d, g, mean, s2, var, sel, crit, nullptr, status, nullptr};
+    e = lagp::launch_mspe(a, workspace, workspace_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mspe launch");
+    return ok();
+}
+
 }  // extern "C"
 
 namespace {

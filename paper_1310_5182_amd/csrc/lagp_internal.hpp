@@ -131,6 +131,13 @@ __host__ __device__ inline bool mixed_trusted(int n, double g)
     return (n + g) / g * 0x1p-24 <= 0x1p-4;
 }
 
+// Local designs by the MSPE criterion (eq. mspe), float64, uniform n and N':
+// workspace for M locations, and the launch (a.alc receives the criterion of
+// each chosen point).
+constexpr int kMspeNmax = 64, kMspeNpMax = 1024, kMspePmax = 8;
+hipError_t mspe_workspace(int64_t M, int Np, int n, size_t *bytes);
+hipError_t launch_mspe(const AlcArgs &a, void *ws, size_t ws_bytes, hipStream_t st);
+
 // Local likelihood / MLE / fixed-design prediction, one wave per location.
 struct GpArgs {
     const double *X, *Y;

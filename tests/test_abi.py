@@ -284,3 +284,27 @@ def test_scores_validation(L):
     assert sc(prec=2) == -1
     assert sc(delta=None) == -1
     assert sc(Nc=0, delta=None) == 0     # no-op before any pointer is needed
+
+
+def mspe(L, N=100, p=2, M=3, Np=10, n0=2, n=5, d=0.5, g=1e-3, ws=FAKE, ws_bytes=1 << 40):
+    return L.lagp_mspe_from_pool(FAKE, FAKE, N, p, FAKE, M, FAKE, Np, n0, n, d, g, None, None, None, FAKE, None,
+                                 None, ws, ws_bytes, None)
+
+
+def test_mspe_validation(L):
+    import ctypes as ct
+
+    assert mspe(L, n0=1) == -1  # eq. newv divides by j (j - 1)
+    assert b"n0 >= 2" in L.lagp_last_error()
+    assert mspe(L, n0=6, n=5) == -1
+    assert mspe(L, n=11) == -1
+    assert mspe(L, d=0.0) == -1
+    assert mspe(L, g=-1.0) == -1
+    assert mspe(L, N=10**6, Np=2000, n=10) == -4
+    assert mspe(L, N=10**6, Np=500, n=65) == -4
+    assert mspe(L, p=9) == -4
+    assert mspe(L, M=0) == 0  # no-op, no HIP call
+    nb = ct.c_size_t(7)
+    assert L.lagp_mspe_workspace(0, 10, 5, ct.byref(nb)) == 0 and nb.value == 0
+    assert L.lagp_mspe_workspace(10, 2000, 5, ct.byref(nb)) == -4
+    assert L.lagp_mspe_workspace(10, 10, 5, None) == -1
