@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import LAGP_FP64, LAGP_FP64_REFORM, LAGP_MIXED, LagpError  # noqa: F401
 
-__all__ = ["nn_pool", "mspe_from_pool", "mspe_predict", "alc_scores", "alc_multistage", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
+__all__ = ["nn_pool", "nn_pool_static", "mspe_from_pool", "mspe_predict", "alc_scores", "alc_multistage", "alc_from_pool", "alc_predict", "alc_uneven_from_pool", "alc_uneven_predict", "Plan",
            "local_nll", "LocalNLL", "local_mle_d", "local_predict", "PRECISIONS", "version"]
 
 PRECISIONS = {"fp64": LAGP_FP64, "mixed": LAGP_MIXED, "fp64_reform": LAGP_FP64_REFORM}
@@ -69,6 +69,24 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
     _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
                                  workspace.data_ptr(), workspace.numel(), _stream(X.device)))
+    return out
+
+
+def nn_pool_static(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The grid-pruned pools of nn_pool(grid=True) built in the library's static
+    device scratch (lagp_nn_pool_static): the call allocates nothing when `out`
+    is given.  Calls on one GPU share that scratch and must not overlap."""
+    L = _lib.load()
+    X, XX = _f64(X, "X"), _f64(XX, "XX")
+    M, p = XX.shape
+    if X.dim() != 2 or X.shape[1] != p:
+        raise ValueError("X must be N x p with the p of XX")
+    if out is None:
+        out = torch.empty((M, Np), dtype=torch.int32, device=X.device)
+    elif out.dtype != torch.int32 or tuple(out.shape) != (M, Np) or not out.is_contiguous() or out.device != X.device:
+        raise ValueError("out must be a contiguous M x Np int32 tensor on the device of X")
+    _lib.check(L.lagp_nn_pool_static(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
+                                     _stream(X.device)))
     return out
 
 

@@ -115,6 +115,26 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
     return ok();
 }
 
+lagp_status lagp_nn_pool_static(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
+                                int32_t Np, int32_t *pool, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (lagp::nn_pool_cap(Np) == 0) return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", Np);
+    const size_t need = lagp::nn_pool_workspace(N, p, M);
+    if (need > lagp::kNnStaticScratch)
+        return fail(LAGP_EWORKSPACE, "N = %lld, p = %d, M = %lld need %zu bytes of scratch; the static scratch holds %zu",
+                    (long long)N, p, (long long)M, need, lagp::kNnStaticScratch);
+    if (M == 0) return ok();
+    void *ws = nullptr;
+    hipError_t e = lagp::nn_static_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    e = lagp::launch_nn_grid(X, N, p, XX, M, Np, pool, ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
+    return ok();
+}
+
 lagp_status lagp_alc_scores(const double *Xj, int32_t j, int32_t p, const double *Kinv, const double *Xc,
                             int64_t Nc, const double *x, const double *h, double d, double g,
                             int32_t precision, double *delta, void *stream)

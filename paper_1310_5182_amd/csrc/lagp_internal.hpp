@@ -89,6 +89,11 @@ int nn_pool_groupings(int Np);
 // the stream then reads instead of X; launch_nn_grid uses all of it for the
 // grid of the design (cells, their boxes, the rows cell by cell) and prunes.
 size_t nn_pool_workspace(int64_t N, int p, int64_t M);
+// Allocation-free grid-pruned pools: the same kernels on a file-scope
+// device array of kNnStaticScratch bytes (one copy per GPU, resolved to its
+// device address once per device).
+constexpr size_t kNnStaticScratch = (size_t)64 << 20;
+hipError_t nn_static_scratch(void **ptr);
 hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
                           void *ws, hipStream_t st);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,

@@ -48,6 +48,8 @@
 #include "lagp_device.hpp"
 #include "lagp_internal.hpp"
 
+#include <mutex>
+
 namespace lagp {
 
 constexpr int kNnBlock = 256;
@@ -1032,6 +1034,31 @@ hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, i
     if (Np <= 1024) return launch_grid_cap<2048, 1024>(X, N, p, XX, M, Np, pool, g, st);
     if (Np <= kNnMaxNp) return launch_grid_cap<3072, 2048>(X, N, p, XX, M, Np, pool, g, st);
     return hipErrorInvalidValue;
+}
+
+// Scratch of lagp_nn_pool_static: the bucketed design and the cell tables of
+// launch_nn_grid.  Each GPU holds its own copy until the process ends; host
+// code reaches it only through the address nn_static_scratch resolves.
+static __device__ __align__(256) unsigned char scratch[kNnStaticScratch];
+
+hipError_t nn_static_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!a) return hipErrorInvalidSymbol;
+        addr[dev] = a;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 int nn_pool_cap(int Np)
