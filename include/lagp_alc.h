@@ -234,7 +234,7 @@ lagp_status lagp_mspe_from_pool(const double *X, const double *Y, int64_t N, int
  * layout of the structs fails loudly instead of passing shifted fields).
  * lagp_abi_version() returns LAGP_ABI_VERSION of the library.
  */
-#define LAGP_ABI_VERSION 2
+#define LAGP_ABI_VERSION 3
 
 /* lagp_problem.flags */
 #define LAGP_NORMALIZE_ALC 1u  /* report each selected point's score multiplied */
@@ -265,6 +265,14 @@ typedef struct lagp_problem {
     double d, g;               /* lengthscale and nugget, finite and > 0           */
     int32_t precision;         /* LAGP_FP64, LAGP_MIXED or LAGP_FP64_REFORM        */
     int32_t reserved;          /* 0                                                */
+    const double *d_sep;       /* [p] lengthscales of the separable kernel, or    */
+                               /* NULL (isotropic, d / d_per): K(x, x') =         */
+                               /* exp(-sum_k (x_k - x'_k)^2 / d_sep[k]), the      */
+                               /* vectorised lengthscale of Sec. 3.1; d is then   */
+                               /* unused.  LAGP_FP64 only, not with d_per.  The   */
+                               /* pools stay Euclidean.  A d_sep entry that is    */
+                               /* not finite and > 0 gives every location         */
+                               /* LAGP_LOC_BAD_SHAPE.                             */
 } lagp_problem;
 
 typedef struct lagp_outputs {

@@ -59,7 +59,9 @@ class Oracle:
         L.orc_gp_predict.restype = i32
         L.orc_gp_predict_b.argtypes = [P, P, i32, i32, P, f64, f64, P]
         L.orc_gp_predict_b.restype = i32
-        L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, P, f64,
+        L.orc_gp_predict_sep.argtypes = [P, P, i32, i32, P, P, f64, P]
+        L.orc_gp_predict_sep.restype = i32
+        L.orc_alc.argtypes = [P, P, i64, i32, P, i64, P, i32, P, i32, P, i32, i32, i32, f64, P, P, f64,
                               P, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_alc.restype = i32
         L.orc_alc_scores.argtypes = [P, i32, i32, P, i64, P, f64, f64, i32, P, P, P]
@@ -94,6 +96,13 @@ class Oracle:
         rc = self.L.orc_gp_predict(_p(D), _p(Yd), D.shape[0], D.shape[1], _p(x), d, g, _p(out))
         return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
 
+    def gp_predict_sep(self, D, Yd, x, dsep, g: float) -> dict:
+        """gp_predict with the separable kernel (dsep: p lengthscales)."""
+        D, Yd, x, dsep = _f64(np.atleast_2d(D)), _f64(Yd), _f64(x), _f64(dsep)
+        out = np.empty(5)
+        rc = self.L.orc_gp_predict_sep(_p(D), _p(Yd), D.shape[0], D.shape[1], _p(x), _p(dsep), g, _p(out))
+        return dict(mean=out[0], s2=out[1], var=out[2], v=out[3], psi=out[4], status=rc)
+
     def gp_predict_b(self, D, Yd, x, d: float, g: float) -> dict:
         """gp_predict through K^{-1} grown row by row by the partitioned inverse
         (eq. piedef): the paper's route, for the output route noise."""
@@ -104,9 +113,10 @@ class Oracle:
 
     def alc(self, X, Y, XX, pool, n0: int, n: int, d: float, g: float, *, Np: int | None = None,
             n_per=None, Np_per=None, forced=None, mode_b: bool = False, threads: int = 0,
-            d_per=None) -> dict:
+            d_per=None, dsep=None) -> dict:
         """Greedy ALC local designs and local predictions for every location
-        (d_per: an own lengthscale per location, overriding d).
+        (d_per: an own lengthscale per location, overriding d; dsep: p
+        lengthscales of the separable kernel, overriding d).
 
         Returns arrays: sel, dsel, dmax, amax, dsecond, nu, psitraj (M x nmax),
         vtraj (M x (nmax + 1)), mean, s2, var, v, psi (M), status (M); with
@@ -131,8 +141,11 @@ class Oracle:
         pred_b = np.full((M, 5), np.nan)
         status = np.zeros(M, np.int32)
         d_per = None if d_per is None else _f64(d_per)
+        dsep = None if dsep is None else _f64(dsep)
+        assert dsep is None or dsep.shape == (X.shape[1],)
         rc = self.L.orc_alc(_p(X), _p(Y), X.shape[0], X.shape[1], _p(XX), M, _p(pool), Np_stride,
-                            _p(Np_per), Np, _p(n_per), n, nmax, n0, d, _p(d_per), g, _p(forced), int(mode_b),
+                            _p(Np_per), Np, _p(n_per), n, nmax, n0, d, _p(d_per), _p(dsep), g, _p(forced),
+                            int(mode_b),
                             threads, _p(sel), _p(dsel), _p(dmax), _p(amax), _p(dsecond), _p(nu),
                             _p(vtraj), _p(pred), _p(status), _p(psitraj), _p(pred_b))
         if rc:

@@ -80,6 +80,21 @@ static double kern(const double *a, const double *b, int p, double d)
     return exp(-sqdist(a, b, p) / d);
 }
 
+/* The separable version with one lengthscale per input (the vectorised
+ * lengthscale Sec. 3.1 names as a simple modification of the candidate-vector
+ * steps): exp(-sum_k (a_k - b_k)^2 / dsep_k), summed left to right.  dsep NULL:
+ * the isotropic kernel with lengthscale d. */
+static double kern2(const double *a, const double *b, int p, double d, const double *dsep)
+{
+    if (!dsep) return kern(a, b, p, d);
+    double s = 0.0;
+    for (int k = 0; k < p; k++) {
+        double t = a[k] - b[k];
+        s = s + t * t / dsep[k];
+    }
+    return exp(-s);
+}
+
 /* ------------------------------------------------------------------ */
 /* Nearest-neighbour pool (Sec. 2.2 NN sub-design; Sec. 3.1 N' NNs).    */
 /* ------------------------------------------------------------------ */
@@ -189,8 +204,8 @@ static double dot(const double *a, const double *b, int j)
  * out[0] = mean, out[1] = s2 (Student-t scale, df n), out[2] = V = s2 n/(n-2)
  * (NaN if n <= 2), out[3] = v = kappa - k^T K^{-1} k, out[4] = psi.
  * Returns 0, or 1 if K is not positive definite. */
-int orc_gp_predict(const double *D, const double *Yd, int n, int p, const double *x,
-                   double d, double g, double *out)
+static int gp_predict(const double *D, const double *Yd, int n, int p, const double *x,
+                      double d, const double *dsep, double g, double *out)
 {
     double kappa = 1.0 + g;
     double *K = (double *)malloc(sizeof(double) * (size_t)n * n);
@@ -201,9 +216,9 @@ int orc_gp_predict(const double *D, const double *Yd, int n, int p, const double
     double *zh = (double *)malloc(sizeof(double) * (size_t)n);
     int rc = 0;
     for (int a = 0; a < n; a++) {
-        for (int b = 0; b < n; b++) K[a * n + b] = kern(D + a * p, D + b * p, p, d);
+        for (int b = 0; b < n; b++) K[a * n + b] = kern2(D + a * p, D + b * p, p, d, dsep);
         K[a * n + a] += g;
-        h[a] = kern(D + a * p, x, p, d);
+        h[a] = kern2(D + a * p, x, p, d, dsep);
     }
     if (cholesky(K, L, n)) {
         rc = 1;
@@ -224,6 +239,19 @@ int orc_gp_predict(const double *D, const double *Yd, int n, int p, const double
     }
     free(K); free(L); free(h); free(w); free(alpha); free(zh);
     return rc;
+}
+
+int orc_gp_predict(const double *D, const double *Yd, int n, int p, const double *x,
+                   double d, double g, double *out)
+{
+    return gp_predict(D, Yd, n, p, x, d, NULL, g, out);
+}
+
+/* orc_gp_predict with the separable kernel (dsep: p lengthscales). */
+int orc_gp_predict_sep(const double *D, const double *Yd, int n, int p, const double *x,
+                       const double *dsep, double g, double *out)
+{
+    return gp_predict(D, Yd, n, p, x, 1.0, dsep, g, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -364,7 +392,7 @@ static double dxy_score(const double *Kinv, const double *kc, const double *h, d
  * Returns a status code; the trace is filled as far as it got.
  */
 static int alc_one(const double *X, const double *Y, int p, const double *x,
-                   const int32_t *pool, int Np, int n0, int n, double d, double g,
+                   const int32_t *pool, int Np, int n0, int n, double d, const double *dsep, double g,
                    const int32_t *forced, int mode_b, orc_trace *tr, orc_work *w)
 {
     const double kappa = 1.0 + g;
@@ -391,9 +419,9 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
             for (int a = 0; a < j; a++) {
                 const double *xa = X + (int64_t)pool[slot_of[a]] * p;
                 for (int b = 0; b < j; b++)
-                    w->K[a * j + b] = kern(xa, X + (int64_t)pool[slot_of[b]] * p, p, d);
+                    w->K[a * j + b] = kern2(xa, X + (int64_t)pool[slot_of[b]] * p, p, d, dsep);
                 w->K[a * j + a] += g;
-                w->h[a] = kern(xa, x, p, d);
+                w->h[a] = kern2(xa, x, p, d, dsep);
                 w->yj[a] = Y[pool[slot_of[a]]];
             }
             if (cholesky(w->K, w->L, j)) { rc = j <= n0 ? ORC_INIT_NOT_PD : ORC_STEP_FAIL; break; }
@@ -425,10 +453,10 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
                 if (w->chosen[s]) continue;
                 const double *xc = X + (int64_t)pool[s] * p;
                 for (int a = 0; a < j; a++)
-                    w->kc[a] = kern(X + (int64_t)pool[slot_of[a]] * p, xc, p, d);
+                    w->kc[a] = kern2(X + (int64_t)pool[slot_of[a]] * p, xc, p, d, dsep);
                 forward_solve(w->L, w->kc, w->zc, j);
                 double sc = kappa - dot(w->zc, w->zc, j);
-                double kcx = kern(xc, x, p, d);
+                double kcx = kern2(xc, x, p, d, dsep);
                 double cov = kcx - dot(w->zc, w->zh, j);
                 double delta = sc > 0.0 ? cov * cov / sc : -INFINITY;
                 if (mode_b) {
@@ -467,7 +495,7 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
         /* Mode B bookkeeping: grow K^{-1} by the partitioned inverse. */
         if (mode_b) {
             const double *xn = X + (int64_t)pool[take_slot] * p;
-            for (int a = 0; a < j; a++) w->kc[a] = kern(X + (int64_t)pool[slot_of[a]] * p, xn, p, d);
+            for (int a = 0; a < j; a++) w->kc[a] = kern2(X + (int64_t)pool[slot_of[a]] * p, xn, p, d, dsep);
             if (piedef_grow(Kinv, Kinv2, w->kc, kappa, w->u, w->gv, j)) mode_b = 0;
             double *t = Kinv; Kinv = Kinv2; Kinv2 = t;
         }
@@ -484,13 +512,13 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
             memcpy(w->Dn + (size_t)a * p, X + (int64_t)tr->sel[a] * p, sizeof(double) * p);
             w->Yn[a] = Y[tr->sel[a]];
         }
-        if (orc_gp_predict(w->Dn, w->Yn, n, p, x, d, g, tr->pred)) rc = ORC_STEP_FAIL;
+        if (gp_predict(w->Dn, w->Yn, n, p, x, d, dsep, g, tr->pred)) rc = ORC_STEP_FAIL;
         else tr->vtraj[n] = tr->pred[3];
         /* Mode B: the same prediction from K_n^{-1} as grown by eq. piedef
          * (eqs. predgp, preds2 with the explicit inverse): the output route noise. */
         if (rc == ORC_OK && mode_b) {
             double mu = 0.0, psi = 0.0, hwh = 0.0;
-            for (int a = 0; a < n; a++) w->h[a] = kern(w->Dn + (size_t)a * p, x, p, d);
+            for (int a = 0; a < n; a++) w->h[a] = kern2(w->Dn + (size_t)a * p, x, p, d, dsep);
             for (int a = 0; a < n; a++) {
                 double alpha_a = dot(Kinv + (size_t)a * n, w->Yn, n);
                 double wa = dot(Kinv + (size_t)a * n, w->h, n);
@@ -521,6 +549,8 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
  * M x (n_stride + 1); pred is M x 5.  Any per-step output may be NULL.
  * psitraj (M x n_stride): psi_j = Y_j^T K_j^{-1} Y_j before step j, the
  * global variance estimate of the normalisation of Sec. 3.1 (Fig. 3 step 9).
+ * dsep: NULL, or p lengthscales of the separable kernel (kern2), replacing d
+ * (not with d_per).
  * pred_b (M x 5): with mode_b, pred recomputed from the K_n^{-1} that the
  * partitioned-inverse update (eq. piedef) built along the design, i.e. the
  * output of the paper's route; its gap to pred measures the output route
@@ -528,13 +558,19 @@ static int alc_one(const double *X, const double *Y, int p, const double *x,
  */
 int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX, int64_t M,
             const int32_t *pool, int Np_stride, const int32_t *Np_per, int Np,
-            const int32_t *n_per, int n, int n_stride, int n0, double d, const double *d_per, double g,
+            const int32_t *n_per, int n, int n_stride, int n0, double d, const double *d_per,
+            const double *dsep, double g,
             const int32_t *forced, int mode_b, int nthreads,
             int32_t *sel, double *dsel, double *dmax, int32_t *amax, double *dsecond,
             double *nu, double *vtraj, double *pred, int32_t *status, double *psitraj, double *pred_b)
 {
     if (!(d > 0.0) || !(g > 0.0) || !isfinite(d) || !isfinite(g) || p < 1 || n0 < 1)
         return ORC_BAD_ARGS;
+    if (dsep) {
+        if (d_per) return ORC_BAD_ARGS;  /* one lengthscale per location, or one per input */
+        for (int k = 0; k < p; k++)
+            if (!(dsep[k] > 0.0) || !isfinite(dsep[k])) return ORC_BAD_ARGS;
+    }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -558,7 +594,7 @@ int orc_alc(const double *X, const double *Y, int64_t N, int p, const double *XX
                 !isfinite(dm))
                 rc = ORC_BAD_ARGS;
             else
-                rc = alc_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np_stride, Npm, n0, nm, dm, g,
+                rc = alc_one(X, Y, p, XX + m * p, pool + m * (int64_t)Np_stride, Npm, n0, nm, dm, dsep, g,
                              forced ? forced + m * (int64_t)n_stride : NULL, mode_b, &tr, &w);
             if (rc == ORC_BAD_ARGS) {
                 for (int j = 0; j < n_stride; j++) { t_sel[j] = -1; t_amax[j] = -1; }

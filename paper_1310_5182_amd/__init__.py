@@ -233,7 +233,17 @@ def _sel_off(t, M: int, device) -> int:
     return t.data_ptr()
 
 
-def _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off, normalize, nn, out):
+def _d_sep(t, p: int, device) -> int:
+    if t is None:
+        return 0
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() or t.device != device
+            or t.numel() != p):
+        raise ValueError("d_sep must be a contiguous float64 tensor of p lengthscales on the device of X")
+    return t.data_ptr()
+
+
+def _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off, normalize, nn, out,
+             d_sep=None):
     """lagp_problem and lagp_outputs for these tensors (the outputs dict is
     completed in place, including the pools)."""
     if nn not in ("grid", "brute"):
@@ -258,6 +268,7 @@ def _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off
     pr.N, pr.M, pr.p, pr.n0, pr.n, pr.Np = X.shape[0], M, p, n0, n, Np
     pr.n_per, pr.Np_per = _i32(n_per, "n_per", M, dev), _i32(Np_per, "Np_per", M, dev)
     pr.d_per = _d_per(d_per, M, dev)
+    pr.d_sep = _d_sep(d_sep, p, dev)
     pr.d, pr.g, pr.precision = float(d), float(g), _prec(precision)
     po = _lib.Outputs()
     po.struct_size = ctypes.sizeof(_lib.Outputs)
@@ -278,7 +289,7 @@ def _workspace(L, pr, o, dev) -> torch.Tensor:
 
 def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precision="fp64",
                 out: dict | None = None, *, n_per=None, Np_per=None, d_per=None, sel_off=None,
-                normalize: bool = False, nn: str = "grid") -> dict:
+                normalize: bool = False, nn: str = "grid", d_sep=None) -> dict:
     """The whole path in one call (lagp_alc_predict): NN pools, greedy ALC
     designs, local predictions.
 
@@ -288,11 +299,13 @@ def alc_predict(X, Y, XX, n0: int, n: int, Np: int, d: float, g: float, precisio
     n_per[m]; with sel_off (int64, M + 1 offsets), `out` must supply them as
     flat rows.  normalize: scores reported as psi_j Delta / (j - 2) (Sec. 3.1).
     nn: 'grid' (grid-pruned pools) or 'brute' (the whole design streamed); the
-    pools are the same.  Returns the outputs, the pools and the workspace."""
+    pools are the same.  d_sep: p lengthscales of the separable kernel (float64
+    device tensor; d is then unused).  Returns the outputs, the pools and the
+    workspace."""
     L = _lib.load()
     X, Y, XX = _check_xy(X, Y, XX)
     pr, po, o = _structs(X, Y, XX, n0, n, Np, d, g, precision, n_per, Np_per, d_per, sel_off, normalize, nn,
-                         out)
+                         out, d_sep)
     ws = _workspace(L, pr, o, X.device)
     _lib.check(L.lagp_alc_predict(ctypes.byref(pr), ctypes.byref(po), ws.data_ptr(), ws.numel(),
                                   _stream(X.device)))
@@ -353,14 +366,14 @@ class Plan:
 
     def __init__(self, X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
                  Np_per=None, tune: bool = True, d_per=None, precision="fp64", normalize: bool = False,
-                 nn: str = "grid"):
+                 nn: str = "grid", d_sep=None):
         L = _lib.load()
         X, Y, XX = _check_xy(X, Y, XX)
         dev = X.device
         pr, po, o = _structs(X, Y, XX, n0, n_max, Np_max, d, g, precision, n_per, Np_per, d_per, None,
-                             normalize, nn, None)
+                             normalize, nn, None, d_sep)
         ws = _workspace(L, pr, o, dev)
-        self._keep = (X, Y, XX, n_per, Np_per, d_per)
+        self._keep = (X, Y, XX, n_per, Np_per, d_per, d_sep)
         self.out, self._dev, self._h = o, dev, ctypes.c_void_p()
         _lib.check(L.lagp_plan_create(ctypes.byref(pr), ctypes.byref(po), ws.data_ptr(), ws.numel(),
                                       0 if tune else 1, _stream(dev), ctypes.byref(self._h)))

@@ -17,7 +17,7 @@ LAGP_FP64 = 0
 LAGP_MIXED = 1
 LAGP_FP64_REFORM = 2
 
-LAGP_ABI_VERSION = 2
+LAGP_ABI_VERSION = 3
 LAGP_NORMALIZE_ALC = 1
 LAGP_NN_BRUTE = 2
 
@@ -31,7 +31,8 @@ class Problem(ctypes.Structure):
                 ("p", ctypes.c_int32), ("n0", ctypes.c_int32), ("n", ctypes.c_int32), ("Np", ctypes.c_int32),
                 ("n_per", ctypes.c_void_p), ("Np_per", ctypes.c_void_p), ("d_per", ctypes.c_void_p),
                 ("d", ctypes.c_double), ("g", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_sep", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):

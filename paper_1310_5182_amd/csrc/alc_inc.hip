@@ -137,7 +137,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
     __shared__ int32_t red_i[2][NW], red_k[2][NW];
     __shared__ double alc_out[kIncNmax];
     __shared__ int32_t seldi[kIncNmax];
-    __shared__ double xs[kIncPmax];
+    __shared__ double xs[kIncPmax], sk[kIncPmax];  // x, and the coordinate scales 1 / sqrt(d_k)
     __shared__ int ctl_status, ctl_loc;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -165,11 +165,22 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
         const int n = __builtin_amdgcn_readfirstlane(x.n_per ? x.n_per[m] : a.n);
         const int Np = __builtin_amdgcn_readfirstlane(x.Np_per ? x.Np_per[m] : a.Np);
         const int64_t orow = x.sel_off ? x.sel_off[m] : m * a.n;
-        const double nid = uniform(-1.0 / (x.d_per ? x.d_per[m] : a.d));  // checked > 0 by the queue
+        // separable kernel: coordinates scaled by 1 / sqrt(d_k), so that
+        // exp(-sum_k (c_k - x_k)^2 / d_k) = exp(-|c' - x'|^2), lengthscale 1
+        const double nid = a.dsep ? -1.0 : uniform(-1.0 / (x.d_per ? x.d_per[m] : a.d));  // checked > 0 by the queue
 
         // ---- stage the location; every lane loads its own pool positions
-        if (tid == 0) ctl_status = kLocOk;
-        if (tid < p) xs[tid] = a.XX[m * p + tid];
+        if (tid == 0) {
+            int st = kLocOk;
+            if (a.dsep)
+                for (int k = 0; k < p; k++)
+                    if (!(a.dsep[k] > 0.0) || !isfinite(a.dsep[k])) st = kLocBadShape;
+            ctl_status = st;
+        }
+        if (tid < p) {
+            xs[tid] = a.XX[m * p + tid];
+            sk[tid] = a.dsep ? 1.0 / sqrt(a.dsep[tid]) : 1.0;
+        }
         __syncthreads();
         double z[S][ZR];
         double sv[S], cv[S], ty[S];  // conditional variance, covariance with x, residual of y
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             di[s] = valid ? id : INT32_MAX;
             double q = 0.0;
             for (int k = 0; k < p; k++) {
-                const double c = valid ? a.X[(int64_t)id * p + k] - xs[k] : 0.0;
+                const double c = valid ? (a.X[(int64_t)id * p + k] - xs[k]) * sk[k] : 0.0;  // sk = 1: exact
                 cx[k * CAP + pos] = c;
                 q = fma(c, c, q);
             }

@@ -261,6 +261,10 @@ lagp_status resolve(const lagp_problem *pr, const lagp_outputs *out, lagp::PathA
         return fail(LAGP_EINVAL, "LAGP_NORMALIZE_ALC divides by j - 2: needs n0 >= 3 (n0 = %d)", pr->n0);
     if (lagp::nn_pool_cap(pr->Np) == 0)
         return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", pr->Np);
+    if (pr->d_sep) {
+        if (prec != LAGP_FP64) return fail(LAGP_EUNSUPPORTED, "the separable kernel (d_sep) needs LAGP_FP64");
+        if (pr->d_per) return fail(LAGP_EINVAL, "d_sep and d_per exclude each other");
+    }
     // which ALC launch: the uniform kernels, or the cost-ordered queues
     bool queued;
     if (prec == LAGP_FP64_REFORM) {
@@ -270,7 +274,9 @@ lagp_status resolve(const lagp_problem *pr, const lagp_outputs *out, lagp::PathA
                         pr->Np, pr->n, prec);
         queued = false;
     } else {
-        queued = !uniform || !lagp::alc_supported(prec, pr->p, pr->Np, pr->n);
+        // the separable kernel lives in the incremental kernel, uniform or queued
+        queued = !uniform || (pr->d_sep ? !lagp::alc_inc_supported(pr->p, pr->Np, pr->n)
+                                        : !lagp::alc_supported(prec, pr->p, pr->Np, pr->n));
         if (queued && !lagp::alc_uneven_supported(pr->p, pr->Np, pr->n))
             return fail(LAGP_EUNSUPPORTED, "no schedule for p = %d, Np = %d, n = %d", pr->p, pr->Np, pr->n);
     }
@@ -302,6 +308,7 @@ lagp_status resolve(const lagp_problem *pr, const lagp_outputs *out, lagp::PathA
         a.n_per = pr->n_per;
         a.Np_per = pr->Np_per;
         a.d_per = pr->d_per;
+        a.dsep = pr->d_sep;
         a.normalize = (pr->flags & LAGP_NORMALIZE_ALC) != 0;
         q.precision = prec;
         q.nn_brute = (pr->flags & LAGP_NN_BRUTE) != 0;

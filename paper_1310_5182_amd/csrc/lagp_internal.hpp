@@ -49,6 +49,7 @@ struct AlcArgs {
     const int32_t *list_count = nullptr; // ... of which the first *list_count are valid
     int normalize = 0;   // scores reported as psi_j Delta / (j - 2) (Sec. 3.1, Fig. 3 step 9)
     int f64_guard = 0;   // float64 kernel standing in for LAGP_MIXED: guard counts every step
+    const double *dsep = nullptr;  // [p] separable lengthscales (float64 incremental kernel only), or NULL
 };
 
 // Internal form of lagp_problem / lagp_outputs after validation, with the

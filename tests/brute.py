@@ -17,11 +17,20 @@ def sqdist_rows(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     return s
 
 
-def corr(A: np.ndarray, B: np.ndarray, d: float) -> np.ndarray:
-    """exp(-||a - b||^2 / d) for all row pairs (Sec. 2.1)."""
+def corr(A: np.ndarray, B: np.ndarray, d) -> np.ndarray:
+    """exp(-||a - b||^2 / d) for all row pairs (Sec. 2.1); with d a vector of
+    one lengthscale per input, the separable form exp(-sum_k (a_k - b_k)^2 / d_k)."""
     out = np.empty((A.shape[0], B.shape[0]))
+    dv = np.asarray(d, dtype=float)
     for j in range(B.shape[0]):
-        out[:, j] = np.exp(-sqdist_rows(A, B[j]) / d)
+        if dv.ndim == 0:
+            out[:, j] = np.exp(-sqdist_rows(A, B[j]) / d)
+        else:
+            s = np.zeros(A.shape[0])
+            for k in range(A.shape[1]):
+                t = A[:, k] - B[j, k]
+                s = s + t * t / dv[k]
+            out[:, j] = np.exp(-s)
     return out
 
 

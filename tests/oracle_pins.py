@@ -52,6 +52,13 @@ What pins what:
   mspe_parts        - the criterion splits into eq. newv's variance term, whose
                       v_j and psi_j the ALC route gives independently, plus
                       (d mu / dd)^2 / G; the partitioned-inverse route agrees
+  separable_brute   - the separable kernel (one lengthscale per input, the
+                      vectorised lengthscale of Sec. 3.1) = brute force with
+                      fresh solves on that kernel; its prediction = numpy.solve
+  separable_reduces - equal lengthscales give the isotropic designs; doubling
+                      one input while quadrupling its lengthscale is exact
+                      (bit-identical); an input with an enormous lengthscale
+                      drops out (bit-identical to the run without it)
   per_location_d    - a lengthscale of each location's own (the second design
                       stage of Fig. 1 step 4) gives, location by location,
                       the run with that scalar lengthscale; invalid entries
@@ -508,7 +515,55 @@ def mspe_parts(orc):
     assert np.all(out["gsel"][:, n0:] > 0)
 
 
+def separable_brute(orc):
+    X, Y, XX = workloads.uniform(9, 90, 3, 3)
+    dsep = np.array([0.05, 0.3, 1.5])
+    g, n0, n, Np = 1e-3, 3, 10, 30
+    pool = orc.nn_pool(X, XX, Np)
+    out = orc.alc(X, Y, XX, pool, n0, n, 0.5, g, dsep=dsep)
+    assert np.all(out["status"] == 0)
+    for m in range(XX.shape[0]):
+        sel, best = brute.greedy(X, XX[m], pool[m], n0, n, dsep, g)
+        assert np.array_equal(out["sel"][m], sel), (m, out["sel"][m], sel)
+        assert _rel(out["dsel"][m, n0:], best) < 1e-9, m
+        ref = brute.predict(X[sel], Y[sel], XX[m], dsep, g)
+        for k in ("mean", "s2", "var"):
+            assert _rel(out[k][m], ref[k]) < 1e-9, (m, k)
+        fixed = orc.gp_predict_sep(X[sel], Y[sel], XX[m], dsep, g)
+        assert _rel(fixed["s2"], ref["s2"]) < 1e-9 and _rel(fixed["mean"], ref["mean"]) < 1e-9
+
+
+def separable_reduces(orc):
+    W = workloads.make(4, N=3000, M=6)
+    n0, n, Np = 6, 18, 120
+    pool = orc.nn_pool(W.X, W.XX, Np)
+    iso = orc.alc(W.X, W.Y, W.XX, pool, n0, n, W.d, W.g)
+    eq = orc.alc(W.X, W.Y, W.XX, pool, n0, n, 123.0, W.g, dsep=np.full(W.p, W.d))
+    assert np.array_equal(iso["sel"], eq["sel"])
+    for k in ("mean", "s2", "var"):
+        assert _rel(iso[k], eq[k]) < 1e-12, k
+    # input 2 doubled with its lengthscale quadrupled: every kernel value bit-identical
+    dsep = np.array([0.1, 0.25, 0.4, 0.9])
+    a = orc.alc(W.X, W.Y, W.XX, pool, n0, n, 1.0, W.g, dsep=dsep)
+    X2, XX2, d2 = W.X.copy(), W.XX.copy(), dsep.copy()
+    X2[:, 2] *= 2.0
+    XX2[:, 2] *= 2.0
+    d2[2] *= 4.0
+    b = orc.alc(X2, W.Y, XX2, pool, n0, n, 1.0, W.g, dsep=d2)
+    for k in ("sel", "dsel", "mean", "s2", "var"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    # input 3 with an enormous lengthscale contributes exp(-t^2 / 1e300) = 1 exactly
+    big = dsep.copy()
+    big[3] = 1e300
+    c = orc.alc(W.X, W.Y, W.XX, pool, n0, n, 1.0, W.g, dsep=big)
+    e = orc.alc(np.ascontiguousarray(W.X[:, :3]), W.Y, np.ascontiguousarray(W.XX[:, :3]), pool, n0, n, 1.0,
+                W.g, dsep=dsep[:3])
+    for k in ("sel", "dsel", "mean", "s2", "var"):
+        assert np.array_equal(c[k], e[k], equal_nan=True), k
+    assert not np.array_equal(a["sel"], c["sel"])  # the input mattered before it was dropped
+
+
 ALL = [pool_exact, greedy_brute, hand_j1, tie_rule, invariants, y_independence, scale_invariance,
        special_cases, design_point, predict_textbook, route_b, predict_b, psi_trajectory, forced,
        nll_textbook, nll_derivatives_fd, mle_optimality, mle_global, local_mle_batched, scores_brute,
-       scores_greedy, mspe_brute, mspe_parts, per_location_d]
+       scores_greedy, mspe_brute, mspe_parts, separable_brute, separable_reduces, per_location_d]

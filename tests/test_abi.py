@@ -120,17 +120,27 @@ def test_struct_layout_and_abi_guard(L):
     from paper_1310_5182_amd import _lib
 
     # the ctypes mirrors have the C layout (the library accepts exactly these sizes)
-    assert ctypes.sizeof(_lib.Problem) == 112 and ctypes.sizeof(_lib.Outputs) == 88
-    assert L.lagp_abi_version() == _lib.LAGP_ABI_VERSION
+    assert ctypes.sizeof(_lib.Problem) == 120 and ctypes.sizeof(_lib.Outputs) == 88
+    assert L.lagp_abi_version() == _lib.LAGP_ABI_VERSION == 3
     assert predict(L, problem(M=0), outputs()) == 0
     assert L.lagp_last_error() == b""
-    for bad in (0, 104, 120):
+    for bad in (0, 112, 128):  # 112: the version-2 layout, without d_sep
         assert predict(L, problem(M=0, struct_size=bad), outputs()) == -1
         assert b"struct_size" in L.lagp_last_error()
+    for bad in (0, 80, 96):
         assert predict(L, problem(M=0), outputs(struct_size=bad)) == -1
         assert b"lagp_outputs.struct_size" in L.lagp_last_error()
     nb = ctypes.c_size_t(0)
     assert L.lagp_alc_workspace(ctypes.byref(problem(struct_size=8)), ctypes.byref(nb)) == -1
+
+
+def test_separable_validation(L):
+    """d_sep (the separable kernel) needs LAGP_FP64 and excludes d_per."""
+    assert predict(L, problem(d_sep=FAKE, precision=1), outputs()) == -4
+    assert b"d_sep" in L.lagp_last_error()
+    assert predict(L, problem(d_sep=FAKE, precision=2), outputs()) == -4
+    assert predict(L, problem(d_sep=FAKE, d_per=FAKE), outputs()) == -1
+    assert predict(L, problem(d_sep=FAKE, M=0), outputs()) == 0
 
 
 def test_predict_validation(L):

@@ -22,7 +22,7 @@ MUTANTS = {
                         "        if (!isfinite(x[k])) return ORC_NONFINITE;\n    memset(w->chosen, 0, (size_t)Np);\n"
                         "    for (int q = 0; q < 5; q++) tr->pred"),
     # nugget wrongly added to the cross-covariance with x
-    "nugget_on_h": ("w->h[a] = kern(xa, x, p, d);", "w->h[a] = kern(xa, x, p, d) + g;"),
+    "nugget_on_h": ("w->h[a] = kern2(xa, x, p, d, dsep);", "w->h[a] = kern2(xa, x, p, d, dsep) + g;"),
     # transposed operand in the triangular solve
     "solve_transposed": ("for (int k = 0; k < r; k++) s -= L[r * j + k] * z[k];",
                          "for (int k = 0; k < r; k++) s -= L[k * j + r] * z[k];"),
@@ -40,8 +40,8 @@ MUTANTS = {
     # NN start skips the nearest point
     "init_off_by_one": ("                take_slot = j;\n", "                take_slot = j + 1;\n"),
     # last coordinate dropped from the distance
-    "dist_drops_coord": ("    for (int k = 0; k < p; k++) {\n        double t = a[k] - b[k];",
-                         "    for (int k = 0; k + 1 < p; k++) {\n        double t = a[k] - b[k];"),
+    "dist_drops_coord": ("    for (int k = 0; k < p; k++) {\n        double t = a[k] - b[k];\n        s = s + t * t;\n",
+                         "    for (int k = 0; k + 1 < p; k++) {\n        double t = a[k] - b[k];\n        s = s + t * t;\n"),
     # partitioned inverse with the sign of g flipped (mode B)
     "piedef_sign": ("for (int a = 0; a < j; a++) gv[a] = -m * u[a];\n    int J",
                     "for (int a = 0; a < j; a++) gv[a] = m * u[a];\n    int J"),
@@ -77,6 +77,10 @@ MUTANTS = {
     # MSPE: the largest criterion chosen instead of the smallest
     "mspe_argmax": ("if (crit < best || (crit == best && best_slot >= 0 && pool[s] < pool[best_slot])) {",
                     "if (!(crit <= best) || best_slot < 0 || (crit == best && pool[s] < pool[best_slot])) {"),
+    # separable kernel: lengthscales paired with the wrong inputs
+    "sep_index_shift": ("s = s + t * t / dsep[k];", "s = s + t * t / dsep[(k + 1) % p];"),
+    # separable kernel: the location's kernel vector h left isotropic
+    "sep_h_isotropic": ("w->h[a] = kern2(xa, x, p, d, dsep);", "w->h[a] = kern(xa, x, p, d);"),
     # Newton iteration stopping on the first backtracking success without moving on
     "mle_one_step": ("        if (moved <= 1e-10 * d) { status = 0; it++; break; }",
                      "        status = 0; it++; break;"),
