@@ -380,11 +380,16 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  *   first times the variants of each tunable launch on these inputs, on at
  *   most their first 65,536 locations, and keeps the fastest: the NN variant
  *   (the grid-pruned pools, one, two or four locations per workgroup over the
- *   whole design, or one over a float32 copy of it) and, for each pool-size
- *   schedule of the float64 ALC kernel that the problem uses, the workgroup
- *   shape (one location per 256- or 512-thread workgroup, or several small
- *   locations per workgroup) and how the chosen factor row reaches the lanes.
- *   The chosen launches are then captured into a graph.  Creation runs the
+ *   whole design, or one over a float32 copy of it), for each pool-size class
+ *   of the float64 ALC kernel that the locations fall into (pools of up to
+ *   256, 512, 1024, 2048) the schedule that serves it among those that can:
+ *   threads per location (256, 512 or 1024), pool positions per lane and
+ *   factor entries kept in registers, and for each schedule that runs how the
+ *   chosen factor row reaches the lanes.  A change is kept if it is at least
+ *   1 % faster.  LAGP_PLAN_SCHEDULE(s) in plan_flags instead runs schedule s
+ *   (0 <= s < LAGP_PLAN_SCHEDULES) for every class it can serve, without
+ *   timing schedules (diagnostics; the results are the same bits on every
+ *   schedule).  The chosen launches are then captured into a graph.  Creation runs the
  *   path on `stream` (several times when tuning), synchronises it, and
  *   finally enqueues one graph launch, whose results the outputs hold once
  *   `stream` has been synchronised.  M >= 1.  Every buffer the structs point
@@ -396,6 +401,8 @@ lagp_status lagp_alc_uneven_from_pool(const double *X, const double *Y, int64_t 
  */
 typedef struct lagp_plan_s *lagp_plan;
 #define LAGP_PLAN_NO_TUNE 1
+#define LAGP_PLAN_SCHEDULES 6
+#define LAGP_PLAN_SCHEDULE(s) ((int32_t)((s) + 1) << 8)
 
 lagp_status lagp_plan_create(const lagp_problem *prob, const lagp_outputs *out, void *workspace,
                              size_t workspace_bytes, int32_t plan_flags, void *stream, lagp_plan *plan);

@@ -366,7 +366,7 @@ class Plan:
 
     def __init__(self, X, Y, XX, n0: int, n_max: int, Np_max: int, d: float, g: float, n_per=None,
                  Np_per=None, tune: bool = True, d_per=None, precision="fp64", normalize: bool = False,
-                 nn: str = "grid", d_sep=None):
+                 nn: str = "grid", d_sep=None, schedule: int | None = None):
         L = _lib.load()
         X, Y, XX = _check_xy(X, Y, XX)
         dev = X.device
@@ -375,8 +375,13 @@ class Plan:
         ws = _workspace(L, pr, o, dev)
         self._keep = (X, Y, XX, n_per, Np_per, d_per, d_sep)
         self.out, self._dev, self._h = o, dev, ctypes.c_void_p()
+        flags = 0 if tune else _lib.LAGP_PLAN_NO_TUNE
+        if schedule is not None:  # run this ALC schedule wherever it serves (LAGP_PLAN_SCHEDULE)
+            if not 0 <= int(schedule) < _lib.LAGP_PLAN_SCHEDULES:
+                raise ValueError(f"schedule must be in [0, {_lib.LAGP_PLAN_SCHEDULES})")
+            flags |= (int(schedule) + 1) << 8
         _lib.check(L.lagp_plan_create(ctypes.byref(pr), ctypes.byref(po), ws.data_ptr(), ws.numel(),
-                                      0 if tune else 1, _stream(dev), ctypes.byref(self._h)))
+                                      flags, _stream(dev), ctypes.byref(self._h)))
 
     def launch(self) -> dict:
         _lib.check(_lib.load().lagp_plan_launch(self._h, _stream(self._dev)))

@@ -20,6 +20,8 @@ LAGP_FP64_REFORM = 2
 LAGP_ABI_VERSION = 3
 LAGP_NORMALIZE_ALC = 1
 LAGP_NN_BRUTE = 2
+LAGP_PLAN_NO_TUNE = 1
+LAGP_PLAN_SCHEDULES = 6
 
 
 class Problem(ctypes.Structure):

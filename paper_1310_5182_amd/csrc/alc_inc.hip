@@ -47,7 +47,7 @@ namespace {
 
 constexpr int kIncNmax = 128;  // z_h and L^{-1} Y live in two lanes' worth of one wave
 constexpr int kIncPmax = 8;
-constexpr int kIncBcastDefault = 0x7;  // v_readlane broadcast on every schedule
+constexpr int kIncBcastDefault = 0x3f;  // DPP row broadcast of the chosen row on every schedule
 
 struct IncArgs {
     AlcArgs a;                // a.n / a.Np: uniform values, or the upper bounds
@@ -292,12 +292,14 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 double v = lane < NW ? red_s[par][lane] : -1.0;
                 int32_t vi = lane < NW ? red_i[par][lane] : INT32_MAX;
                 int vk = lane < NW ? red_k[par][lane] : -1;
-                // NW <= 8 proposals: three exchange stages within each group of
-                // eight lanes leave lane 0 with the argmax (ties: smaller index)
-                static_assert(NW <= 8, "one group of eight lanes");
+                // NW <= 16 proposals: three exchange stages within each group of
+                // eight lanes (a fourth across the two eights of a row) leave
+                // lane 0 with the argmax (ties: smaller index)
+                static_assert(NW <= 16, "one row of sixteen lanes");
                 argmax_stage<0>(v, vi, vk);
                 argmax_stage<1>(v, vi, vk);
                 argmax_stage<2>(v, vi, vk);
+                if constexpr (NW > 8) argmax_stage<3>(v, vi, vk);
                 vbest = readlane(v, 0);
                 wpos = __builtin_amdgcn_readlane(vk, 0);
                 wdi = __builtin_amdgcn_readlane(vi, 0);
@@ -512,11 +514,28 @@ struct Sched {
     }
 };
 
-// Schedule b serves pools of up to kSched[b].cap() positions.
-constexpr int kNumSched = 3;
-constexpr Sched kSched[kNumSched] = {{256, 2, 40}, {512, 2, 40}, {512, 4, 16}};
+// Schedule b: TB threads per location, S pool positions per lane (so pools of
+// up to TB S), ZR factor entries per position in registers.  0-2 are the
+// defaults of the pool-size classes; 3-5 are the alternatives a plan may time
+// against them: the same pools on twice the waves with half the positions per
+// lane (a SIMD then interleaves four waves, or two of eight for 512 threads,
+// over a step's dependent phases, at the price of fewer registers per lane and
+// a longer winner exchange).
+constexpr int kNumSched = 6;
+constexpr Sched kSched[kNumSched] = {{256, 2, 40},  {512, 2, 40},  {512, 4, 16},
+                                     {1024, 1, 40}, {1024, 2, 16}, {512, 1, 40}};
 
 static_assert(kNumSched == kIncSchedules, "schedule count");
+
+// Pool-size classes: class c holds pools of up to kClassCap[c] positions and
+// runs on one schedule, the default below unless a plan chose another.
+constexpr int kClassCap[kIncClasses] = {256, 512, 1024, 2048};
+constexpr int kDefaultMap[kIncClasses] = {0, 0, 1, 2};
+
+__host__ __device__ inline int class_of(int Np)
+{
+    return Np <= kClassCap[0] ? 0 : Np <= kClassCap[1] ? 1 : Np <= kClassCap[2] ? 2 : Np <= kClassCap[3] ? 3 : -1;
+}
 
 template <int B, bool RL>
 constexpr auto kernel_of()
@@ -531,8 +550,14 @@ const void *kernel_ptr(int b, bool rl)
         return rl ? (const void *)kernel_of<0, true>() : (const void *)kernel_of<0, false>();
     case 1:
         return rl ? (const void *)kernel_of<1, true>() : (const void *)kernel_of<1, false>();
-    default:
+    case 2:
         return rl ? (const void *)kernel_of<2, true>() : (const void *)kernel_of<2, false>();
+    case 3:
+        return rl ? (const void *)kernel_of<3, true>() : (const void *)kernel_of<3, false>();
+    case 4:
+        return rl ? (const void *)kernel_of<4, true>() : (const void *)kernel_of<4, false>();
+    default:
+        return rl ? (const void *)kernel_of<5, true>() : (const void *)kernel_of<5, false>();
     }
 }
 
@@ -543,7 +568,8 @@ bool rl_of(int bcast, int b)
 
 __host__ __device__ inline int sched_for(int Np)
 {
-    return Np <= kSched[0].cap() ? 0 : Np <= kSched[1].cap() ? 1 : Np <= kSched[2].cap() ? 2 : -1;
+    const int c = class_of(Np);
+    return c < 0 ? -1 : kDefaultMap[c];
 }
 
 // CUs of the current device; the schedules' LDS limit set once per device.
@@ -606,8 +632,17 @@ hipError_t launch_sched(int b, bool rl, const IncArgs &x, dim3 grid, size_t lds,
     case 1:
         launch_b<1>(rl, x, grid, lds, st);
         break;
-    default:
+    case 2:
         launch_b<2>(rl, x, grid, lds, st);
+        break;
+    case 3:
+        launch_b<3>(rl, x, grid, lds, st);
+        break;
+    case 4:
+        launch_b<4>(rl, x, grid, lds, st);
+        break;
+    default:
+        launch_b<5>(rl, x, grid, lds, st);
         break;
     }
     return hipGetLastError();
@@ -627,6 +662,7 @@ struct PlanWs {
     int32_t *queue;    // [M]
     int32_t *mlist[2]; // [M] each: locations for the mixed kernel, pools <= 512 / <= 1024
     int mixed;         // route the locations the mixed kernel covers to mlist
+    int smap[kIncClasses];  // schedule of each pool-size class
 };
 
 __global__ void plan_zero(PlanWs w)
@@ -641,8 +677,9 @@ __global__ void plan_zero(PlanWs w)
     if (t < 2) w.mcount[t] = 0;
 }
 
-// Classify every location: its schedule and a cost class (four per octave of
-// N' n^2, the order of its update work), or a shape error written in place.
+// Classify every location: its schedule (that of its pool-size class) and a
+// cost class (four per octave of N' n^2, the order of its update work), or a
+// shape error written in place.
 __global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -655,7 +692,8 @@ __global__ void plan_classify(IncArgs x, PlanWs w, int64_t M)
     const double dm = x.d_per ? x.d_per[m] : a.d;
     const bool ok = n >= a.n0 && n <= a.n && Np >= n && Np <= x.pool_stride && rowlen >= n && dm > 0.0 &&
                     isfinite(dm);
-    const int b = ok ? sched_for(Np) : -1;
+    const int c = ok ? class_of(Np) : -1;
+    const int b = c < 0 ? -1 : w.smap[c];
     if (b < 0) {
         w.key[m] = -1;
         if (a.mean) a.mean[m] = NAN;
@@ -731,6 +769,32 @@ int alc_inc_schedule(int Np)
     return sched_for(Np);
 }
 
+int alc_inc_class(int Np)
+{
+    return class_of(Np);
+}
+
+int alc_inc_default_sched(int c)
+{
+    return c >= 0 && c < kIncClasses ? kDefaultMap[c] : -1;
+}
+
+bool alc_inc_admissible(int s, int c, int p, int n_max, bool on_chip)
+{
+    if (s < 0 || s >= kNumSched || c < 0 || c >= kIncClasses) return false;
+    if (kSched[s].cap() < kClassCap[c]) return false;
+    const int gc = gcols_for(s, p, n_max);
+    return on_chip ? gc == 0 : gc >= 0;
+}
+
+void alc_inc_sched_name(int s, char *buf, size_t len)
+{
+    if (s < 0 || s >= kNumSched)
+        snprintf(buf, len, "none");
+    else
+        snprintf(buf, len, "%dx%d/%d", kSched[s].tb, kSched[s].s, kSched[s].zr);
+}
+
 bool alc_inc_supported(int p, int Np, int n)
 {
     if (p > kIncPmax || n > kIncNmax) return false;
@@ -738,14 +802,18 @@ bool alc_inc_supported(int p, int Np, int n)
     return b >= 0 && gcols_for(b, p, n) == 0;
 }
 
-hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast)
+hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast, const int *smap)
 {
     if (a.M == 0) return hipSuccess;
     if (!alc_inc_supported(a.p, a.Np, a.n)) return hipErrorNotSupported;
     DevInfo info;
     hipError_t e = dev_info(info);
     if (e != hipSuccess) return e;
-    const int b = sched_for(a.Np);
+    int b = sched_for(a.Np);
+    if (smap) {  // the plan's schedule for this pool size, if it keeps every column on chip
+        const int c = class_of(a.Np);
+        if (alc_inc_admissible(smap[c], c, a.p, a.n, true)) b = smap[c];
+    }
     IncArgs x{};
     x.a = a;
     x.pool_stride = a.Np;
@@ -757,11 +825,29 @@ hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast)
 bool alc_uneven_supported(int p, int Np_max, int n_max)
 {
     if (p > kIncPmax || n_max > kIncNmax) return false;
-    const int top = sched_for(Np_max);
+    const int top = class_of(Np_max);
     if (top < 0) return false;
-    for (int b = 0; b <= top; b++)
-        if (gcols_for(b, p, n_max) < 0) return false;
+    for (int c = 0; c <= top; c++)
+        if (!alc_inc_admissible(kDefaultMap[c], c, p, n_max, false)) return false;
     return true;
+}
+
+// The schedules a launch over classes 0 .. top may use: with a map, the
+// mapped ones (a bit per schedule); without, every schedule admissible for
+// one of those classes (the workspace holds the global columns of all of them,
+// so that a plan may choose among them after the workspace is sized).
+static unsigned sched_set(int top, int p, int n_max, const int *smap)
+{
+    unsigned set = 0;
+    for (int c = 0; c <= top; c++) {
+        if (smap) {
+            set |= 1u << smap[c];
+            continue;
+        }
+        for (int b = 0; b < kNumSched; b++)
+            if (alc_inc_admissible(b, c, p, n_max, false)) set |= 1u << b;
+    }
+    return set;
 }
 
 hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t *bytes)
@@ -769,10 +855,14 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
     DevInfo info;
     hipError_t e = dev_info(info);
     if (e != hipSuccess) return e;
-    // header, keys, queue, the two mixed-precision lists
+    // header, keys, queue, the two mixed-precision lists, then the global
+    // columns of every schedule a plan could map these classes to
     size_t total = kHdrBytes + 4 * align256((size_t)M * 4);
-    const int top = sched_for(Np_max);
-    for (int b = 0; b <= top; b++) {
+    const int top = class_of(Np_max);
+    if (top < 0) return hipErrorInvalidValue;
+    const unsigned set = sched_set(top, p, n_max, nullptr);
+    for (int b = 0; b < kNumSched; b++) {
+        if (!(set >> b & 1)) continue;
         const int gc = gcols_for(b, p, n_max);
         int64_t grid = 0;
         e = persistent_grid(b, kSched[b].lds(p, kSched[b].zl_fit(p, n_max), n_max), info.cus, &grid);
@@ -785,9 +875,16 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
 
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
                              const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
-                             hipStream_t st, int bcast, bool mixed)
+                             hipStream_t st, int bcast, bool mixed, const int *smap)
 {
     if (a.M == 0) return hipSuccess;
+    const int top = class_of(a.Np);
+    if (top < 0) return hipErrorInvalidValue;
+    int map[kIncClasses];
+    for (int c = 0; c < kIncClasses; c++) {
+        map[c] = smap ? smap[c] : kDefaultMap[c];
+        if (c <= top && !alc_inc_admissible(map[c], c, a.p, a.n, false)) return hipErrorInvalidValue;
+    }
     DevInfo info;
     hipError_t e = dev_info(info);
     if (e != hipSuccess) return e;
@@ -812,6 +909,7 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
         off += align256((size_t)a.M * 4);
     }
     w.mixed = mixed && a.p <= kIncPmax;
+    for (int c = 0; c < kIncClasses; c++) w.smap[c] = map[c];
 
     IncArgs x{};
     x.a = a;
@@ -844,8 +942,11 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
         }
     }
 
-    const int top = sched_for(a.Np);
-    for (int b = 0; b <= top; b++) {
+    // every admissible schedule owns a slice of the workspace (as sized by
+    // alc_uneven_workspace); the mapped ones run, each draining its queue
+    const unsigned all = sched_set(top, a.p, a.n, nullptr), used = sched_set(top, a.p, a.n, map);
+    for (int b = 0; b < kNumSched; b++) {
+        if (!(all >> b & 1)) continue;
         const int gc = gcols_for(b, a.p, a.n);
         x.zl_cols = kSched[b].zl_fit(a.p, a.n);
         x.zrow = Sched::zrow(a.n);
@@ -858,6 +959,7 @@ hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32
         x.gcols = gc;
         x.gz = gc > 0 ? (double *)(base + off) : nullptr;
         off += align256((size_t)grid64 * kSched[b].cap() * gc * 8);
+        if (!(used >> b & 1)) continue;
         e = launch_sched(b, rl_of(bcast, b), x, dim3(grid), lds, st);
         if (e != hipSuccess) return e;
     }

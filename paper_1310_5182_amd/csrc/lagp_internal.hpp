@@ -67,7 +67,7 @@ struct PathArgs {
 
 // Whole path (pools, designs, predictions) with the given NN variant (see
 // plan.cpp; -1: the default) and incremental-kernel broadcast mask / shape.
-hipError_t run_path(const PathArgs &P, int nn_variant, int bcast, hipStream_t st);
+hipError_t run_path(const PathArgs &P, int nn_variant, int bcast, hipStream_t st, const int *smap = nullptr);
 
 }  // namespace lagp
 
@@ -106,12 +106,21 @@ bool alc_supported(int precision, int p, int Np, int n);
 hipError_t launch_alc(const AlcArgs &a, int precision, hipStream_t st);
 
 // Float64 greedy ALC by incremental Cholesky columns.  `bcast` selects, per
-// pool-size schedule, how the chosen factor row reaches the lanes (bit b set:
-// v_readlane, clear: LDS reads); negative: the default.
-constexpr int kIncSchedules = 3;
-int alc_inc_schedule(int Np);  // schedule serving pools of Np (-1: none)
+// schedule, how the chosen factor row reaches the lanes (bit b set: DPP row
+// broadcasts from a per-lane copy, clear: uniform LDS reads); negative: the
+// default.  `smap` (kIncClasses entries, or NULL for the defaults) names the
+// schedule of each pool-size class.
+constexpr int kIncSchedules = 6, kIncClasses = 4;  // LAGP_PLAN_SCHEDULES of the public header
+int alc_inc_schedule(int Np);  // default schedule serving pools of Np (-1: none)
+int alc_inc_class(int Np);     // pool-size class of Np (-1: none)
+int alc_inc_default_sched(int c);  // the schedule of class c without a plan
+// Whether schedule s can serve class c at (p, n_max): the class's pools fit
+// it and its LDS holds the coordinates; `on_chip` also asks for every factor
+// column in registers or LDS (the uniform launch).
+bool alc_inc_admissible(int s, int c, int p, int n_max, bool on_chip);
+void alc_inc_sched_name(int s, char *buf, size_t len);
 bool alc_inc_supported(int p, int Np, int n);
-hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1);
+hipError_t launch_alc_inc(const AlcArgs &a, hipStream_t st, int bcast = -1, const int *smap = nullptr);
 // Per-location n, N' (a.n, a.Np are the upper bounds; pool rows of a.Np) and,
 // when d_per is not NULL, lengthscale d.
 bool alc_uneven_supported(int p, int Np_max, int n_max);
@@ -121,7 +130,7 @@ hipError_t alc_uneven_workspace(int p, int64_t M, int Np_max, int n_max, size_t 
 // in float64 with every step counted in guard.
 hipError_t launch_alc_uneven(const AlcArgs &a, const int32_t *n_per, const int32_t *Np_per,
                              const int64_t *sel_off, const double *d_per, void *ws, size_t ws_bytes,
-                             hipStream_t st, int bcast = -1, bool mixed = false);
+                             hipStream_t st, int bcast = -1, bool mixed = false, const int *smap = nullptr);
 // Mixed (float32 MFMA) kernel over the locations of a.list (per-location
 // sizes from a's per-location fields); `big` selects the 1024-slot schedule.
 hipError_t launch_alc_mixed_list(const AlcArgs &a, bool big, hipStream_t st);

@@ -3,16 +3,20 @@
 // A plan binds one problem of lagp_alc_predict to its buffers, picks the
 // fastest variant of each tunable launch by timing it on those very inputs (the
 // NN variant: locations per workgroup over the whole design, the stream of a
-// float32 copy of it, or the grid-pruned stream; for every pool-size schedule
-// of the float64 ALC kernel that runs, how the chosen factor row is
-// broadcast), and captures the chosen launches - NN pools, queue planning,
-// persistent ALC workgroups - into one HIP graph.  Replaying
-// the graph costs one launch call; every node is a kernel (no memset nodes).
+// float32 copy of it, or the grid-pruned stream; for every pool-size class of
+// the float64 ALC kernel that the problem's locations fall into, the schedule
+// that serves it - threads per location, positions per lane, factor entries in
+// registers, down to one wave per location - and, for every schedule that
+// runs, how the chosen factor row is broadcast), and captures the chosen
+// launches - NN pools, queue planning, persistent ALC workgroups - into one
+// HIP graph.  Replaying the graph costs one launch call; every node is a
+// kernel (no memset nodes).
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "lagp_alc.h"
 #include "lagp_internal.hpp"
@@ -21,10 +25,13 @@ struct lagp_plan_s {
     lagp::PathArgs P;
     int nnv = -1;       // NN variant: 2^nnv locations per workgroup, kNnF32 or kNnGrid
     int bcast = -1;     // ALC broadcast mask
+    int smap[lagp::kIncClasses] = {-1, -1, -1, -1};  // schedule of each pool-size class (-1: default)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string info;
 };
+
+static_assert(lagp::kIncSchedules == LAGP_PLAN_SCHEDULES, "the schedules of LAGP_PLAN_SCHEDULE");
 
 namespace lagp {
 
@@ -45,9 +52,10 @@ static const char *nn_name(int v, char *buf, size_t n)
 }
 
 // The whole path with the given NN variant (-1: the grid, or the default
-// location grouping under LAGP_NN_BRUTE) and broadcast mask of the float64
-// incremental kernel (-1: its default).
-hipError_t run_path(const PathArgs &P, int nnv, int bcast, hipStream_t st)
+// location grouping under LAGP_NN_BRUTE), broadcast mask of the float64
+// incremental kernel (-1: its default) and schedule per pool-size class (NULL:
+// the defaults).
+hipError_t run_path(const PathArgs &P, int nnv, int bcast, hipStream_t st, const int *smap)
 {
     const AlcArgs &a = P.a;
     if (nnv < 0 && !P.nn_brute) nnv = kNnGrid;
@@ -58,15 +66,16 @@ hipError_t run_path(const PathArgs &P, int nnv, int bcast, hipStream_t st)
     if (P.uniform) {
         // uniform n, N' and d with every factor column on chip: one workgroup per
         // location, no queue to classify and order
-        if (P.precision == 0 && alc_inc_supported(a.p, a.Np, a.n)) return launch_alc_inc(a, st, bcast);
+        if (P.precision == 0 && alc_inc_supported(a.p, a.Np, a.n)) return launch_alc_inc(a, st, bcast, smap);
         return launch_alc(a, P.precision, st);
     }
     return launch_alc_uneven(a, a.n_per, a.Np_per, a.sel_off, a.d_per, P.alc_ws, P.alc_ws_bytes, st, bcast,
-                             P.precision == 1);
+                             P.precision == 1, smap);
 }
 
 // Milliseconds of one run (the best of `reps`, after one untimed run).
-static hipError_t time_path(const PathArgs &P, int nnv, int bcast, hipStream_t st, int reps, float *ms)
+static hipError_t time_path(const PathArgs &P, int nnv, int bcast, const int *smap, hipStream_t st, int reps,
+                            float *ms)
 {
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -76,10 +85,10 @@ static hipError_t time_path(const PathArgs &P, int nnv, int bcast, hipStream_t s
         return e;
     }
     float best = 1e30f;
-    e = run_path(P, nnv, bcast, st);
+    e = run_path(P, nnv, bcast, st, smap);
     for (int r = 0; e == hipSuccess && r < reps; r++) {
         if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-        if ((e = run_path(P, nnv, bcast, st)) != hipSuccess) break;
+        if ((e = run_path(P, nnv, bcast, st, smap)) != hipSuccess) break;
         if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float t = 0.0f;
@@ -92,38 +101,67 @@ static hipError_t time_path(const PathArgs &P, int nnv, int bcast, hipStream_t s
     return e;
 }
 
-// Coordinate search: the NN variant first, then the broadcast bit of each
-// incremental-kernel schedule the problem runs.  The timing runs use at most
-// the first kTuneLocations locations (their outputs are overwritten later),
-// so that tuning stays short for large M.
+// Coordinate search: the NN variant first, then the schedule of each pool-size
+// class the locations fall into (among the schedules that can serve it), then
+// the broadcast bit of each schedule that runs.  A change is kept only if it
+// is at least 1 % faster.  The timing runs use at most the first
+// kTuneLocations locations (their outputs are overwritten later), so that
+// tuning stays short for large M.
 constexpr int64_t kTuneLocations = 65536;
 
-static hipError_t tune(lagp_plan_s &plan, hipStream_t st)
+// The pool-size classes that the locations of P use (a flag per class), and
+// the highest class of its bound N'; -1 if the incremental kernel does not run.
+static hipError_t classes_of(const PathArgs &P, bool (&present)[kIncClasses], int *top)
+{
+    for (int c = 0; c < kIncClasses; c++) present[c] = false;
+    *top = -1;
+    const bool inc = P.precision != 2 && (!P.uniform || (P.precision == 0 && alc_inc_supported(P.a.p, P.a.Np, P.a.n)));
+    const int t = alc_inc_class(P.a.Np);
+    if (!inc || t < 0) return hipSuccess;
+    if (P.a.Np_per) {
+        std::vector<int32_t> np((size_t)P.a.M);
+        hipError_t e = hipMemcpy(np.data(), P.a.Np_per, np.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+        for (int32_t v : np) {
+            const int c = alc_inc_class(v);
+            if (c >= 0 && c <= t) present[c] = true;
+        }
+    } else {
+        present[t] = true;
+    }
+    *top = t;
+    return hipSuccess;
+}
+
+static hipError_t tune(lagp_plan_s &plan, hipStream_t st, int forced)
 {
     PathArgs P = plan.P;
     if (P.a.M > kTuneLocations) P.a.M = kTuneLocations;
-    char line[160], nm[32];
+    char line[200], nm[32];
     std::string info;
     int variants[8], nv = 0;
     if (!P.nn_brute) variants[nv++] = kNnGrid;
     for (int g = 0; g < nn_pool_groupings(P.a.Np); g++) variants[nv++] = g;
     if (!P.nn_brute) variants[nv++] = kNnF32;
-    // the incremental kernel's schedules this problem launches, and their bits
-    int lo = 0, hi = -1;
-    if (P.precision != 2) {
-        hi = alc_inc_schedule(P.a.Np);
-        if (P.uniform) lo = hi = (P.precision == 0 && alc_inc_supported(P.a.p, P.a.Np, P.a.n)) ? hi : -1;
-        if (hi >= 0 && lo < 0) lo = 0;
-    }
-    int mask = 0x7, v_best = variants[0];
-    float best = 0.0f;
-    hipError_t e = time_path(P, v_best, mask, st, 2, &best);
+    // the incremental kernel's pool-size classes that this problem's locations use
+    bool present[kIncClasses];
+    int top = -1, map[kIncClasses];
+    hipError_t e = classes_of(P, present, &top);
     if (e != hipSuccess) return e;
-    snprintf(line, sizeof line, "nn %s alc mask=%x: %.3f ms", nn_name(v_best, nm, sizeof nm), mask, best);
+    for (int c = 0; c < kIncClasses; c++) {
+        map[c] = c <= top ? alc_inc_default_sched(c) : -1;
+        if (c <= top && forced >= 0 && alc_inc_admissible(forced, c, P.a.p, P.a.n, P.uniform)) map[c] = forced;
+    }
+    const int *mp = top >= 0 ? map : nullptr;
+    int mask = -1, v_best = variants[0];
+    float best = 0.0f;
+    e = time_path(P, v_best, mask, mp, st, 2, &best);
+    if (e != hipSuccess) return e;
+    snprintf(line, sizeof line, "nn %s: %.3f ms", nn_name(v_best, nm, sizeof nm), best);
     info += line;
     for (int q = 1; q < nv; q++) {
         float t = 0.0f;
-        if ((e = time_path(P, variants[q], mask, st, 2, &t)) != hipSuccess) return e;
+        if ((e = time_path(P, variants[q], mask, mp, st, 2, &t)) != hipSuccess) return e;
         snprintf(line, sizeof line, "; nn %s: %.3f ms", nn_name(variants[q], nm, sizeof nm), t);
         info += line;
         if (t < best) {
@@ -131,21 +169,55 @@ static hipError_t tune(lagp_plan_s &plan, hipStream_t st)
             v_best = variants[q];
         }
     }
-    for (int b = lo; b >= 0 && b <= hi; b++) {
-        const int m2 = mask ^ (1 << b);
-        float t = 0.0f;
-        if ((e = time_path(P, v_best, m2, st, 2, &t)) != hipSuccess) return e;
-        snprintf(line, sizeof line, "; alc mask=%x: %.3f ms", m2, t);
-        info += line;
-        if (t < best) {
-            best = t;
-            mask = m2;
+    mask = 0;
+    for (int b = 0; b < kIncSchedules; b++) mask |= 1 << b;  // DPP broadcast everywhere to start with
+    if (mp) {
+        for (int c = 0; c <= top && forced < 0; c++) {
+            if (!present[c]) continue;
+            for (int s = 0; s < kIncSchedules; s++) {
+                if (s == map[c] || !alc_inc_admissible(s, c, P.a.p, P.a.n, P.uniform)) continue;
+                int trial[kIncClasses];
+                for (int q = 0; q < kIncClasses; q++) trial[q] = map[q];
+                trial[c] = s;
+                float t = 0.0f;
+                if ((e = time_path(P, v_best, mask, trial, st, 2, &t)) != hipSuccess) return e;
+                alc_inc_sched_name(s, nm, sizeof nm);
+                snprintf(line, sizeof line, "; class %d on %s: %.3f ms", c, nm, t);
+                info += line;
+                if (t < 0.99f * best) {
+                    best = t;
+                    map[c] = s;
+                }
+            }
+        }
+        unsigned used = 0;
+        for (int c = 0; c <= top; c++)
+            if (present[c]) used |= 1u << map[c];
+        for (int b = 0; b < kIncSchedules; b++) {
+            if (!(used >> b & 1)) continue;
+            const int m2 = mask ^ (1 << b);
+            float t = 0.0f;
+            if ((e = time_path(P, v_best, m2, mp, st, 2, &t)) != hipSuccess) return e;
+            snprintf(line, sizeof line, "; alc mask=%x: %.3f ms", m2, t);
+            info += line;
+            if (t < 0.99f * best) {
+                best = t;
+                mask = m2;
+            }
         }
     }
     plan.nnv = v_best;
     plan.bcast = mask;
-    snprintf(line, sizeof line, "; chosen nn %s alc mask=%x (%.3f ms on %lld locations)",
-             nn_name(v_best, nm, sizeof nm), mask, best, (long long)P.a.M);
+    for (int c = 0; c < kIncClasses; c++) plan.smap[c] = map[c];
+    snprintf(line, sizeof line, "; chosen nn %s alc mask=%x", nn_name(v_best, nm, sizeof nm), mask);
+    info += line;
+    for (int c = 0; mp && c <= top; c++) {
+        if (!present[c]) continue;
+        alc_inc_sched_name(map[c], nm, sizeof nm);
+        snprintf(line, sizeof line, " class%d=%s", c, nm);
+        info += line;
+    }
+    snprintf(line, sizeof line, " (%.3f ms on %lld locations)", best, (long long)P.a.M);
     plan.info = info + line;
     return hipSuccess;
 }
@@ -167,7 +239,9 @@ lagp_status lagp_plan_create(const lagp_problem *prob, const lagp_outputs *out, 
 {
     if (!plan) return plan_fail(LAGP_EINVAL, "plan must be non-NULL");
     *plan = nullptr;
-    if (plan_flags & ~LAGP_PLAN_NO_TUNE) return plan_fail(LAGP_EINVAL, "unknown plan flags");
+    if (plan_flags & ~(LAGP_PLAN_NO_TUNE | (0xf << 8))) return plan_fail(LAGP_EINVAL, "unknown plan flags");
+    const int forced = ((plan_flags >> 8) & 0xf) - 1;  // LAGP_PLAN_SCHEDULE(s), or -1
+    if (forced >= lagp::kIncSchedules) return plan_fail(LAGP_EINVAL, "LAGP_PLAN_SCHEDULE(s) needs s < LAGP_PLAN_SCHEDULES");
     lagp::PathArgs path;
     lagp_status s = lagp::prepare_path(prob, out, workspace, workspace_bytes, &path);
     if (s != LAGP_OK) return s;  // its message stays in lagp_last_error()
@@ -179,7 +253,21 @@ lagp_status lagp_plan_create(const lagp_problem *prob, const lagp_outputs *out, 
     hipError_t e = hipSuccess;
     if (plan_flags & LAGP_PLAN_NO_TUNE) {
         P->info = path.nn_brute ? "defaults (not tuned: nn default)" : "defaults (not tuned: nn grid)";
-    } else if ((e = lagp::tune(*P, st)) != hipSuccess) {
+        bool present[lagp::kIncClasses];
+        int top = -1;
+        if (forced >= 0 && (e = lagp::classes_of(path, present, &top)) == hipSuccess) {
+            for (int c = 0; c <= top; c++)
+                P->smap[c] = lagp::alc_inc_admissible(forced, c, path.a.p, path.a.n, path.uniform)
+                                 ? forced : lagp::alc_inc_default_sched(c);
+            char nm[32];
+            lagp::alc_inc_sched_name(forced, nm, sizeof nm);
+            P->info += std::string("; schedule ") + nm + " where it serves";
+        }
+        if (e != hipSuccess) {
+            delete P;
+            return plan_fail(LAGP_EHIP, "pool sizes", e);
+        }
+    } else if ((e = lagp::tune(*P, st, forced)) != hipSuccess) {
         delete P;
         return plan_fail(LAGP_EHIP, "autotuning run", e);
     }
@@ -191,7 +279,7 @@ lagp_status lagp_plan_create(const lagp_problem *prob, const lagp_outputs *out, 
     }
     if ((e = hipStreamSynchronize(st)) == hipSuccess &&
         (e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
-        hipError_t run = lagp::run_path(P->P, P->nnv, P->bcast, cs);
+        hipError_t run = lagp::run_path(P->P, P->nnv, P->bcast, cs, P->smap[0] >= 0 ? P->smap : nullptr);
         e = hipStreamEndCapture(cs, &P->graph);
         if (run != hipSuccess) e = run;
     }

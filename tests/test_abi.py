@@ -253,6 +253,8 @@ def test_plan_validation(L):
     assert create(problem(n0=0)) == -1
     assert create(problem(struct_size=96)) == -1
     assert create(problem(), flags=4) == -1                           # unknown plan flag
+    assert create(problem(), flags=7 << 8) == -1                      # LAGP_PLAN_SCHEDULE(6): no such schedule
+    assert b"LAGP_PLAN_SCHEDULE" in L.lagp_last_error()
     assert h.value is None
     assert L.lagp_plan_destroy(None) == 0
     assert L.lagp_plan_launch(None, None) == -1

@@ -73,3 +73,50 @@ def test_plan_replays_match_eager(lagp, case, tune):
     info = plan.describe()
     assert ("chosen" in info) == tune
     plan.close()
+
+
+@pytest.mark.parametrize("case", ["config2", "config3"])
+def test_every_schedule_same_bits(lagp, case):
+    """Each ALC schedule a plan may choose (LAGP_PLAN_SCHEDULE forces one
+    wherever it can serve the pool sizes) gives the eager path's results bit
+    for bit: the schedules only move where factor entries live and how many
+    lanes share a step, not the order of any sum."""
+    import torch
+
+    if case == "config3":
+        W = workloads.make(3, N=50000, M=400)
+        n_max, Np_max, n_per, Np_per = 100, 2000, dev(W.n_per), dev(W.Np_per)
+    else:
+        W = workloads.make(2, N=50000, M=300)
+        n_max, Np_max, n_per, Np_per = 50, 1000, None, None
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    eager = lagp.alc_predict(X, Y, XX, W.n0, n_max, Np_max, W.d, W.g, "fp64", n_per=n_per, Np_per=Np_per)
+    torch.cuda.synchronize()
+    ref = snapshot(eager)
+    for s in range(6):
+        for tune in (False, True):
+            print(f"[plan] {case} schedule {s} tune={tune}", flush=True)
+            plan = lagp.Plan(X, Y, XX, W.n0, n_max, Np_max, W.d, W.g, n_per=n_per, Np_per=Np_per, tune=tune,
+                             schedule=s)
+            torch.cuda.synchronize()
+            print(f"[plan] {plan.describe()}", flush=True)
+            same(snapshot(plan.out), ref)
+            plan.launch()
+            torch.cuda.synchronize()
+            same(snapshot(plan.out), ref)
+            plan.close()
+
+
+def test_tuner_reports_schedule_choice(lagp):
+    """The tuned plan of a per-location workload names the schedule it chose
+    for each pool-size class present."""
+    W = workloads.make(3, N=50000, M=2000)
+    X, Y, XX = dev(W.X), dev(W.Y), dev(W.XX)
+    plan = lagp.Plan(X, Y, XX, W.n0, 100, 2000, W.d, W.g, n_per=dev(W.n_per), Np_per=dev(W.Np_per))
+    info = plan.describe()
+    print(f"[plan] {info}", flush=True)
+    chosen = info.split("chosen")[-1]
+    for c in range(1, 4):  # N' in [200, 2000]: classes 1..3 are present
+        assert f"class{c}=" in chosen, (c, chosen)
+    assert "class 3 on" in info  # an alternative was timed for the largest pools
+    plan.close()
