@@ -106,6 +106,20 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
                             void *stream);
 
 /*
+ * lagp_nn_pool_grouped -- lagp_nn_pool_ws with `group` (1, 2 or 4) locations
+ *   per workgroup, consecutive in the cell order, sharing one stream of the
+ *   cells: the cells are visited in order of their smallest box distance over
+ *   the group, and each row loaded serves every location whose own threshold
+ *   admits its cell.  The pools are identical to lagp_nn_pool's; the grouping
+ *   trades LDS (one key buffer per location) for fewer trips of each row from
+ *   L2 and the last-level cache.  group 2 is compiled for p <= 8, group 4 for
+ *   p <= 8 and Np <= 1024 (else LAGP_EUNSUPPORTED); workspace as for
+ *   lagp_nn_pool_ws.
+ */
+lagp_status lagp_nn_pool_grouped(const double *X, int64_t N, int32_t p, const double *XX, int64_t M, int32_t Np,
+                                 int32_t group, int32_t *pool, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * lagp_nn_pool_static -- lagp_nn_pool_ws without caller workspace, for
  *   callers that cannot allocate device memory (code under stream capture,
  *   serving loops that forbid allocation).  The grid-pruned pools are built

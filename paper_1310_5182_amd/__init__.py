@@ -45,13 +45,14 @@ def version() -> str:
 
 
 def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None = None,
-            grid: bool = False, workspace: torch.Tensor | None = None) -> torch.Tensor:
+            grid: bool = False, workspace: torch.Tensor | None = None, group: int = 1) -> torch.Tensor:
     """M x Np int32 pools: the Np nearest design rows of each location, sorted by (distance, index).
 
     grid: bucket the design into grid cells and stream, nearest cell first, only
     the cells that can hold a pool member (lagp_nn_pool_ws; the same pools),
     with the cells kept in `workspace` (a uint8 device tensor, allocated here if
-    None or too small)."""
+    None or too small); group: 2 or 4 locations per workgroup sharing the
+    stream of cells (lagp_nn_pool_grouped; the same pools)."""
     L = _lib.load()
     X, XX = _f64(X, "X"), _f64(XX, "XX")
     M, p = XX.shape
@@ -67,8 +68,13 @@ def nn_pool(X: torch.Tensor, XX: torch.Tensor, Np: int, out: torch.Tensor | None
     _lib.check(L.lagp_nn_pool_workspace(X.shape[0], p, M, ctypes.byref(nbytes)))
     if workspace is None or workspace.numel() < nbytes.value:
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=X.device)
-    _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
-                                 workspace.data_ptr(), workspace.numel(), _stream(X.device)))
+    if group == 1:
+        _lib.check(L.lagp_nn_pool_ws(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, out.data_ptr(),
+                                     workspace.data_ptr(), workspace.numel(), _stream(X.device)))
+    else:
+        _lib.check(L.lagp_nn_pool_grouped(X.data_ptr(), X.shape[0], p, XX.data_ptr(), M, Np, int(group),
+                                          out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                          _stream(X.device)))
     return out
 
 

@@ -52,6 +52,7 @@ EXPORTS = (
     "lagp_nn_pool_workspace",
     "lagp_nn_pool_ws",
     "lagp_nn_pool_static",
+    "lagp_nn_pool_grouped",
     "lagp_alc_scores",
     "lagp_mspe_workspace",
     "lagp_mspe_from_pool",
@@ -102,6 +103,8 @@ def load():
     L.lagp_nn_pool_ws.restype = i32
     L.lagp_nn_pool_static.argtypes = [P, i64, i32, P, i64, i32, P, P]
     L.lagp_nn_pool_static.restype = i32
+    L.lagp_nn_pool_grouped.argtypes = [P, i64, i32, P, i64, i32, i32, P, P, ctypes.c_size_t, P]
+    L.lagp_nn_pool_grouped.restype = i32
     L.lagp_mspe_workspace.argtypes = [i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.lagp_mspe_workspace.restype = i32
     L.lagp_mspe_from_pool.argtypes = [P, P, i64, i32, P, i64, P, i32, i32, i32, f64, f64, P, P, P, P, P, P, P,

@@ -115,6 +115,25 @@ lagp_status lagp_nn_pool_ws(const double *X, int64_t N, int32_t p, const double 
     return ok();
 }
 
+lagp_status lagp_nn_pool_grouped(const double *X, int64_t N, int32_t p, const double *XX, int64_t M, int32_t Np,
+                                 int32_t group, int32_t *pool, void *workspace, size_t workspace_bytes, void *stream)
+{
+    lagp_status s = check_common(X, N, p, XX, M, Np);
+    if (s != LAGP_OK) return s;
+    if (M > 0 && !pool) return fail(LAGP_EINVAL, "pool must be non-NULL");
+    if (group != 1 && group != 2 && group != 4) return fail(LAGP_EINVAL, "group = %d is not 1, 2 or 4", group);
+    if (lagp::nn_pool_cap(Np) == 0) return fail(LAGP_EUNSUPPORTED, "Np = %d too large for the pool kernel", Np);
+    if (group > 1 && (1 << (lagp::nn_grid_groups(p, Np) - 1)) < group)
+        return fail(LAGP_EUNSUPPORTED, "no grouping of %d locations for p = %d, Np = %d", group, p, Np);
+    if (M == 0) return ok();
+    if (!workspace || ((uintptr_t)workspace & 15) || workspace_bytes < lagp::nn_pool_workspace(N, p, M))
+        return fail(LAGP_EWORKSPACE, "workspace must be 16-byte aligned and hold %zu bytes",
+                    lagp::nn_pool_workspace(N, p, M));
+    hipError_t e = lagp::launch_nn_grid(X, N, p, XX, M, Np, pool, workspace, (hipStream_t)stream, group);
+    if (e != hipSuccess) return hip_fail(e, "nn_pool launch");
+    return ok();
+}
+
 lagp_status lagp_nn_pool_static(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
                                 int32_t Np, int32_t *pool, void *stream)
 {

@@ -95,8 +95,12 @@ size_t nn_pool_workspace(int64_t N, int p, int64_t M);
 // device address once per device).
 constexpr size_t kNnStaticScratch = (size_t)64 << 20;
 hipError_t nn_static_scratch(void **ptr);
+// group: locations per workgroup sharing the stream of cells (1, 2 or 4; see
+// nn_grid_groups for what a problem supports).
 hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
-                          void *ws, hipStream_t st);
+                          void *ws, hipStream_t st, int group = 1);
+// Number of grid groupings (1, 2, 4 locations per workgroup) compiled for (p, Np).
+int nn_grid_groups(int p, int Np);
 hipError_t launch_nn_pool(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
                           int32_t *pool, hipStream_t st, int grouping = -1, float *x32 = nullptr);
 

@@ -977,10 +977,312 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
     for (int r = tid; r < Np; r += kNnBlock) pool[m * Np + r] = idxs[r];
 }
 
+// G locations per workgroup, consecutive in cell order (so mostly of one
+// cell), sharing the stream: the cells are visited in order of their smallest
+// box distance over the G locations, a cell is streamed while any location can
+// still have a pool member in it, and each row loaded serves every location
+// whose own threshold admits the row's cell.  Per location the screen, the
+// exact key, the buffer and the selections are those of nn_grid_kernel, so the
+// pools are the same; G locations share each row's trip from L2 / MALL.
+template <int G, int CAP, int SORTN, int PF>
+__global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *__restrict__ X, int64_t N,
+                                                                 const double *__restrict__ XX, int64_t M, int Np,
+                                                                 int32_t *__restrict__ pool, NnGrid gr)
+{
+    static_assert(CAP >= SORTN + kNnChunk && CAP >= kGridCmax, "room for one chunk above the kept set");
+    static_assert(G * kNnItems <= 32, "pending bits of every location and item in one word");
+    constexpr int p = PF;
+    constexpr float kU = 5.9604645e-8f;  // 2^-24
+    constexpr double kMargin = 1.0 - 1.0 / (1 << 20);
+    __shared__ uint64_t keys[G][CAP];
+    __shared__ int32_t idxs[G][CAP];
+    __shared__ double xs[G][PF];
+    __shared__ NnGroup grp[G];
+    __shared__ NnShared S;
+    __shared__ int32_t pre[kGridCmax + 1];   // rows in the cells of rank < r
+    __shared__ int16_t cellr[kGridCmax];     // cell of rank r (smallest group distance first)
+    __shared__ float mindr[G][kGridCmax];    // <= squared distance from location g to the box of that cell
+
+    const int tid = threadIdx.x, C = gr.C;
+    // the XCD of this workgroup (blockIdx.x mod 8) takes the groups
+    // [x q, (x + 1) q) of G consecutive locations in cell order
+    const int64_t ngroups = (M + G - 1) / G, q = (ngroups + 7) / 8;
+    const int64_t gi = (int64_t)(blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    if (gi >= ngroups) return;  // the whole workgroup, before any barrier
+    const int64_t s0 = gi * G;
+    const int ng = (int)(M - s0 < G ? M - s0 : G);
+    int64_t mloc[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) mloc[g] = g < ng ? gr.lperm[s0 + g] : 0;
+    for (int t = tid; t < G * PF; t += kNnBlock) {
+        const int g = t / PF, k = t - g * PF;
+        xs[g][k] = g < ng ? XX[mloc[g] * p + k] : 0.0;
+    }
+    if (tid < G) {
+        grp[tid].count = 0;
+        grp[tid].thr_k = ~0ull;
+        grp[tid].thr_i = INT32_MAX;
+    }
+    __syncthreads();
+    constexpr float kSlope = 1.0f - 2.0f * PF * kU;
+    constexpr float kConst = 40.0f * PF * kU;
+    // the screen's bound B from the design's bounding box and each location
+    float bd = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PF; k++) {
+        const double lo = gr.part[((size_t)kGridParts * p + k) * 2], hi = gr.part[((size_t)kGridParts * p + k) * 2 + 1];
+        const double mk = fmax(fabs(lo), fabs(hi));
+        float f = (float)mk;
+        if ((double)f < mk) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u);
+        bd = fmaxf(bd, f);
+    }
+    float xf[G][PF], cB[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        float lmax = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PF; k++) {
+            xf[g][k] = (float)xs[g][k];
+            lmax = fmaxf(lmax, fabsf(xf[g][k]));
+        }
+        const float bB = fmaxf(bd, lmax);
+        cB[g] = kConst * bB * bB;
+    }
+
+    // ---- cells in order of their smallest squared box distance over the group
+    auto box_sd = [&](int c, int g) {
+        double sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < PF; k++) {
+            const double lo = gr.box[((size_t)c * p + k) * 2], hi = gr.box[((size_t)c * p + k) * 2 + 1];
+            const double gap = fmax(fmax(lo - xs[g][k], xs[g][k] - hi), 0.0);
+            sd = fma(gap, gap, sd);
+        }
+        return sd;
+    };
+    for (int c = tid; c < C; c += kNnBlock) {
+        double sdm = INFINITY;
+        bool nan = false;
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            if (g >= ng) break;
+            const double sd = box_sd(c, g);
+            nan |= !(sd >= 0.0);
+            sdm = fmin(sdm, sd);
+        }
+        keys[0][c] = __builtin_bit_cast(uint64_t, nan ? NAN : sdm);  // a NaN location's cells go last
+        idxs[0][c] = c;
+    }
+    __syncthreads();
+    bitonic_sort_n(keys[0], idxs[0], C);
+    int32_t csum[4], tot = 0;
+#pragma unroll
+    for (int qq = 0; qq < 4; qq++) {
+        const int r = 4 * tid + qq;
+        csum[qq] = 0;
+        if (r < C) {
+            const int c = idxs[0][r];
+            cellr[r] = (int16_t)c;
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const double md = g < ng ? box_sd(c, g) : INFINITY;
+                float f = (float)md;  // rounded down to a float below md
+                if (!(md >= 0.0)) f = INFINITY;
+                else if ((double)f > md) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) - 1u);
+                mindr[g][r] = f;
+            }
+            csum[qq] = gr.off[c + 1] - gr.off[c];
+        }
+        tot += csum[qq];
+    }
+    S.hist[tid] = (uint32_t)tot;
+    __syncthreads();
+    for (int o = 1; o < kNnBlock; o <<= 1) {
+        const uint32_t add = tid >= o ? S.hist[tid - o] : 0u;
+        __syncthreads();
+        S.hist[tid] += add;
+        __syncthreads();
+    }
+    int32_t run = (int32_t)S.hist[tid] - tot;
+#pragma unroll
+    for (int qq = 0; qq < 4; qq++) {
+        const int r = 4 * tid + qq;
+        if (r < C) pre[r] = run;
+        run += csum[qq];
+    }
+    if (tid == 0) pre[C] = (int32_t)N;
+    __syncthreads();
+
+    // ---- the rows, cell by cell
+    int rc = 0;  // rank of the cell that holds row vb
+    for (int64_t vb = 0; vb < N; vb += kNnChunk) {
+        uint64_t tk[G];
+        int32_t ti[G];
+        double td[G];
+        float tf[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            tk[g] = grp[g].thr_k;
+            ti[g] = grp[g].thr_i;
+            td[g] = (tk[g] == ~0ull || g >= ng) ? INFINITY : __builtin_bit_cast(double, tk[g]);
+            const float f = (float)td[g];
+            tf[g] = (double)f < td[g] ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
+        }
+        // every remaining cell is at least as far from each location as its
+        // distance to the cell holding row vb (the order is by the group's
+        // smallest distance, so this holds for the group minimum only): stop
+        // when no location can use that cell or, as the group minimum only
+        // grows, any later one
+        rc = rank_from(pre, rc, vb);
+        {
+            float gmin = INFINITY;
+            double tmax = 0.0;
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                if (g >= ng) break;
+                gmin = fminf(gmin, mindr[g][rc]);
+                tmax = fmax(tmax, td[g]);
+            }
+            if ((double)gmin * kMargin > tmax) break;
+        }
+        int r = rc;
+        uint32_t pend = 0;
+        constexpr int kB = PF <= kNnBatchPmax ? 4 : 1;
+#pragma unroll
+        for (int it0 = 0; it0 < kNnItems; it0 += kB) {
+            uint32_t usem[kB];  // bit g: location g reads this item's row
+            int64_t rowb[kB];
+#pragma unroll
+            for (int b = 0; b < kB; b++) {
+                const int64_t v = vb + (it0 + b) * kNnBlock + tid;
+                const int64_t vc = v < N ? v : N - 1;
+                r = rank_from(pre, r, vc);
+                usem[b] = 0;
+#pragma unroll
+                for (int g = 0; g < G; g++)
+                    if (g < ng && v < N && (double)mindr[g][r] * kMargin <= td[g]) usem[b] |= 1u << g;
+                rowb[b] = gr.off[cellr[r]] + (vc - pre[r]);
+            }
+            float xb[kB][PF];
+#pragma unroll
+            for (int b = 0; b < kB; b++) {
+                const int64_t row = usem[b] ? rowb[b] : 0;
+#pragma unroll
+                for (int k = 0; k < PF; k++) xb[b][k] = gr.x32[row * PF + k];
+            }
+#pragma unroll
+            for (int b = 0; b < kB; b++) {
+                if (!usem[b]) continue;
+                const int it = it0 + b;
+                const int64_t row = rowb[b];
+                int32_t i = -1;
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    if (!((usem[b] >> g) & 1u)) continue;
+                    float d32 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < PF; k++) {
+                        const float t = xb[b][k] - xf[g][k];
+                        d32 = fmaf(t, t, d32);
+                    }
+                    if (d32 * kSlope - cB[g] < tf[g]) {
+                        if (i < 0) i = gr.perm[row];
+                        const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs[g], 1, p);
+                        const uint64_t key = __builtin_bit_cast(uint64_t, sd);
+                        if (key_less(key, i, tk[g], ti[g])) {
+                            const int pos = atomicAdd(&grp[g].count, 1);
+                            if (pos < CAP) {
+                                keys[g][pos] = key;
+                                idxs[g][pos] = i;
+                            } else {
+                                pend |= 1u << (g * kNnItems + it);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // a full buffer: as in nn_pool_kernel, location by location
+#pragma unroll 1
+        for (int g = 0; g < G; g++) {
+            if (grp[g].count > CAP) {
+                select_keep(keys[g], idxs[g], S, grp[g], CAP, Np);
+                const uint64_t nk = grp[g].thr_k;
+                const int32_t ni = grp[g].thr_i;
+#pragma unroll
+                for (int it = 0; it < kNnItems; it++) {
+                    if ((pend >> (g * kNnItems + it)) & 1u) {
+                        const int64_t v = vb + it * kNnBlock + tid;
+                        const int rr = rank_from(pre, rc, v);
+                        const int32_t i = gr.perm[gr.off[cellr[rr]] + (v - pre[rr])];
+                        const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs[g], 1, p);
+                        const uint64_t key = __builtin_bit_cast(uint64_t, sd);
+                        if (key_less(key, i, nk, ni)) {
+                            const int pos = atomicAdd(&grp[g].count, 1);
+                            keys[g][pos] = key;
+                            idxs[g][pos] = i;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll 1
+    for (int g = 0; g < ng; g++) {
+        if (grp[g].count > Np) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
+        for (int i = Np + tid; i < SORTN; i += kNnBlock) {
+            keys[g][i] = ~0ull;
+            idxs[g][i] = INT32_MAX;
+        }
+        __syncthreads();
+        bitonic_sort<SORTN>(keys[g], idxs[g]);
+        for (int r = tid; r < Np; r += kNnBlock) pool[mloc[g] * Np + r] = idxs[g][r];
+        __syncthreads();
+    }
+}
+
+// Grouped grid pools for p <= kGridGroupPmax (G = 2 at every pool size, G = 4
+// where four buffers of CAP keys fit in LDS).
+constexpr int kGridGroupPmax = 8;
+
+template <int G, int CAP, int SORTN>
+static hipError_t launch_grid_group(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
+                                    int32_t *pool, const NnGrid &g, hipStream_t st)
+{
+    const int64_t groups = (M + G - 1) / G;
+    const dim3 grid((unsigned)(8 * ((groups + 7) / 8)));
+    switch (p) {
+#define LAGP_NGG_CASE(P)                                                                                      \
+    case P:                                                                                                   \
+        hipLaunchKernelGGL((nn_grid_group_kernel<G, CAP, SORTN, P>), grid, dim3(kNnBlock), 0, st, X, N, XX, M, \
+                           Np, pool, g);                                                                      \
+        break;
+        LAGP_NGG_CASE(1)
+        LAGP_NGG_CASE(2)
+        LAGP_NGG_CASE(3)
+        LAGP_NGG_CASE(4)
+        LAGP_NGG_CASE(5)
+        LAGP_NGG_CASE(6)
+        LAGP_NGG_CASE(7)
+        LAGP_NGG_CASE(8)
+#undef LAGP_NGG_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int CAP, int SORTN>
 static hipError_t launch_grid_cap(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np,
-                                  int32_t *pool, const NnGrid &g, hipStream_t st)
+                                  int32_t *pool, const NnGrid &g, hipStream_t st, int group)
 {
+    if (group == 2 && p <= kGridGroupPmax) return launch_grid_group<2, CAP, SORTN>(X, N, p, XX, M, Np, pool, g, st);
+    if constexpr (CAP <= 2048) {
+        if (group == 4 && p <= kGridGroupPmax)
+            return launch_grid_group<4, CAP, SORTN>(X, N, p, XX, M, Np, pool, g, st);
+    }
     switch (p) {
 #define LAGP_NG_CASE(P)                                                                                       \
     case P:                                                                                                   \
@@ -1010,8 +1312,14 @@ static hipError_t launch_grid_cap(const double *X, int64_t N, int p, const doubl
     return hipGetLastError();
 }
 
+int nn_grid_groups(int p, int Np)
+{
+    if (p > kGridGroupPmax) return 1;
+    return Np <= 1024 ? 3 : 2;  // G = 1, 2, 4 (four buffers of 3072 keys would not fit in LDS)
+}
+
 hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, int64_t M, int Np, int32_t *pool,
-                          void *ws, hipStream_t st)
+                          void *ws, hipStream_t st, int group)
 {
     if (M == 0) return hipSuccess;
     if (p < 1 || p > kMaxP || !ws) return hipErrorInvalidValue;
@@ -1030,9 +1338,10 @@ hipError_t launch_nn_grid(const double *X, int64_t N, int p, const double *XX, i
     hipLaunchKernelGGL(grid_box, dim3((unsigned)g.C), dim3(256), 0, st, X, p, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (Np <= 512) return launch_grid_cap<2048, 512>(X, N, p, XX, M, Np, pool, g, st);
-    if (Np <= 1024) return launch_grid_cap<2048, 1024>(X, N, p, XX, M, Np, pool, g, st);
-    if (Np <= kNnMaxNp) return launch_grid_cap<3072, 2048>(X, N, p, XX, M, Np, pool, g, st);
+    if (group != 1 && group != 2 && group != 4) return hipErrorInvalidValue;
+    if (Np <= 512) return launch_grid_cap<2048, 512>(X, N, p, XX, M, Np, pool, g, st, group);
+    if (Np <= 1024) return launch_grid_cap<2048, 1024>(X, N, p, XX, M, Np, pool, g, st, group);
+    if (Np <= kNnMaxNp) return launch_grid_cap<3072, 2048>(X, N, p, XX, M, Np, pool, g, st, group);
     return hipErrorInvalidValue;
 }
 

@@ -35,13 +35,17 @@ static_assert(lagp::kIncSchedules == LAGP_PLAN_SCHEDULES, "the schedules of LAGP
 
 namespace lagp {
 
-// NN variants beyond the location groupings 0 .. nn_pool_groupings(Np) - 1
-constexpr int kNnF32 = 100, kNnGrid = 101;
+// NN variants beyond the location groupings 0 .. nn_pool_groupings(Np) - 1:
+// the float32 stream, and the grid-pruned pools with 1, 2 or 4 locations per
+// workgroup
+constexpr int kNnF32 = 100, kNnGrid = 101, kNnGrid2 = 102, kNnGrid4 = 103;
 
 static const char *nn_name(int v, char *buf, size_t n)
 {
     if (v == kNnGrid)
         snprintf(buf, n, "grid");
+    else if (v == kNnGrid2 || v == kNnGrid4)
+        snprintf(buf, n, "grid g=%d", v == kNnGrid2 ? 2 : 4);
     else if (v == kNnF32)
         snprintf(buf, n, "g=1 x32");
     else if (v < 0)
@@ -59,7 +63,9 @@ hipError_t run_path(const PathArgs &P, int nnv, int bcast, hipStream_t st, const
 {
     const AlcArgs &a = P.a;
     if (nnv < 0 && !P.nn_brute) nnv = kNnGrid;
-    hipError_t e = nnv == kNnGrid ? launch_nn_grid(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, P.nn_ws, st)
+    hipError_t e = nnv == kNnGrid    ? launch_nn_grid(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, P.nn_ws, st)
+                   : nnv == kNnGrid2 ? launch_nn_grid(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, P.nn_ws, st, 2)
+                   : nnv == kNnGrid4 ? launch_nn_grid(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, P.nn_ws, st, 4)
                    : nnv == kNnF32 ? launch_nn_pool(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, st, 0, (float *)P.nn_ws)
                                    : launch_nn_pool(a.X, a.N, a.p, a.XX, a.M, a.Np, P.pool, st, nnv, nullptr);
     if (e != hipSuccess) return e;
@@ -140,7 +146,12 @@ static hipError_t tune(lagp_plan_s &plan, hipStream_t st, int forced)
     char line[200], nm[32];
     std::string info;
     int variants[8], nv = 0;
-    if (!P.nn_brute) variants[nv++] = kNnGrid;
+    if (!P.nn_brute) {
+        variants[nv++] = kNnGrid;
+        const int gg = nn_grid_groups(P.a.p, P.a.Np);
+        if (gg >= 2) variants[nv++] = kNnGrid2;
+        if (gg >= 3) variants[nv++] = kNnGrid4;
+    }
     for (int g = 0; g < nn_pool_groupings(P.a.Np); g++) variants[nv++] = g;
     if (!P.nn_brute) variants[nv++] = kNnF32;
     // the incremental kernel's pool-size classes that this problem's locations use

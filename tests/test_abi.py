@@ -320,3 +320,14 @@ def test_mspe_validation(L):
     assert L.lagp_mspe_workspace(0, 10, 5, ct.byref(nb)) == 0 and nb.value == 0
     assert L.lagp_mspe_workspace(10, 2000, 5, ct.byref(nb)) == -4
     assert L.lagp_mspe_workspace(10, 10, 5, None) == -1
+
+
+def test_nn_pool_grouped_validation(L):
+    def grouped(group, p=2, Np=10, M=3, ws=FAKE, nbytes=1 << 40):
+        return L.lagp_nn_pool_grouped(FAKE, 100, p, FAKE, M, Np, group, FAKE, ws, nbytes, None)
+
+    assert grouped(3) == -1
+    assert grouped(0) == -1
+    assert grouped(2, p=9) == -4                 # grouped pools are compiled for p <= 8
+    assert grouped(2, M=0) == 0
+    assert grouped(4, M=3, ws=None) == -2

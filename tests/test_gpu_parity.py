@@ -89,10 +89,15 @@ def test_nn_pool_bit_exact(lagp, orc, case):
 
         got = lagp.nn_pool(dev(W.X), dev(W.XX), npl)
         got32 = lagp.nn_pool(dev(W.X), dev(W.XX), npl, grid=True)  # grid-pruned stream
+        # grid-pruned, two and four locations per workgroup sharing the stream
+        groups = [g for g in (2, 4) if W.p <= 8 and (g == 2 or npl <= 1024)]
+        gotg = {g: lagp.nn_pool(dev(W.X), dev(W.XX), npl, grid=True, group=g) for g in groups}
         torch.cuda.synchronize()
         want = orc.nn_pool(W.X, W.XX, npl)
         assert np.array_equal(got.cpu().numpy(), want), (case, npl)
         assert np.array_equal(got32.cpu().numpy(), want), (case, npl, "grid")
+        for g, t in gotg.items():
+            assert np.array_equal(t.cpu().numpy(), want), (case, npl, "grid", g)
 
 
 # ---------------------------------------------------------------- ALC designs
@@ -254,9 +259,13 @@ def test_nn_pool_grid_nonuniform(lagp, orc, case):
     for npl in sizes:
         print(f"[parity] nn_pool grid {case} N={X.shape[0]} p={X.shape[1]} M={XX.shape[0]} Np={npl}", flush=True)
         got = lagp.nn_pool(dev(X), dev(XX), npl, grid=True)
+        groups = [g for g in (2, 4) if X.shape[1] <= 8 and (g == 2 or npl <= 1024)]
+        gotg = {g: lagp.nn_pool(dev(X), dev(XX), npl, grid=True, group=g) for g in groups}
         torch.cuda.synchronize()
         want = orc.nn_pool(X, XX, npl)
         assert np.array_equal(got.cpu().numpy(), want), (case, npl)
+        for g, t in gotg.items():
+            assert np.array_equal(t.cpu().numpy(), want), (case, npl, g)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "fp64_reform"])
