@@ -336,7 +336,30 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 xw[k] = k < p ? v : 0.0;
             }
             const double qw = uniform(cq[wpos]);
-            if (j + 1 < n) __syncthreads();
+            // K(c, x*) of every slot from centred coordinates, |c - x*|^2 =
+            // |c'|^2 + |x*'|^2 - 2 c'.x*', also before the barrier: the distances
+            // and exps need only x*, so they hide the winner's row write
+            double kcs[S];
+            if (j + 1 < n) {
+#pragma unroll
+                for (int s = 0; s < S; s++) {
+                    const int pos = tid + s * TB;
+                    double dt = 0.0;
+                    if (p > 4) {
+#pragma unroll
+                        for (int k = 0; k < 8; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                    } else if (p > 2) {
+#pragma unroll
+                        for (int k = 0; k < 4; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 2; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
+                    }
+                    const double r2 = fma(-2.0, dt, cq[pos] + qw);
+                    kcs[s] = exp(r2 * nid);
+                }
+                __syncthreads();
+            }
             // step scalars, wave-uniform (scalar registers)
             const double ilam = uniform(pub[par][vw][1]);
             const double *el = zbp;
@@ -399,7 +422,6 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
 #pragma unroll
                 for (int s = 0; s < S; s++) acc[s] = fma(col[s * TB], e, acc[s]);
             }
-            // K(c, x*) from centred coordinates: |c - x*|^2 = |c'|^2 + |x*'|^2 - 2 c'.x*'
             // the entry index, as a scalar: the write below is a scalar branch, not
             // a select over every register column
             const int jc = __builtin_amdgcn_readfirstlane(j >> 3), ju = __builtin_amdgcn_readfirstlane(j & 7);
@@ -407,20 +429,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
 #pragma unroll
             for (int s = 0; s < S; s++) {
                 const int pos = tid + s * TB;
-                double dt = 0.0;
-                if (p > 4) {
-#pragma unroll
-                    for (int k = 0; k < 8; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                } else if (p > 2) {
-#pragma unroll
-                    for (int k = 0; k < 4; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 2; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                }
-                const double r2 = fma(-2.0, dt, cq[pos] + qw);
-                const double kc = exp(r2 * nid);
-                const double wc = (kc - acc[s]) * ilam;
+                const double wc = (kcs[s] - acc[s]) * ilam;
                 wcs[s] = wc;
                 if (j >= ZR) {
                     if (j < G0)
