@@ -129,9 +129,11 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--M", type=int, default=None, help="predictive locations (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="locations the oracle runs on (default: about 15 s of work on 16 cores)")
     ap.add_argument("--only", choices=["mixed", "fp64", "fp64_reform", "both"], default="both")
     ap.add_argument("--no-scores", action="store_true", help="skip the batch-scores microbenchmark")
+    ap.add_argument("--no-mspe", action="store_true", help="skip the MSPE-designs timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -173,13 +175,15 @@ def main() -> int:
     # ---- the whole step per path
     paths = {}
     plan_info = None
-    if cfg == 5 and args.only == "both":
-        # 10^6 locations: the float64 path as one tuned, graph-captured plan
-        plan = lagp.Plan(X, Y, XX, n0, n, Np, d, g)
-        plan_info = plan.describe()
-        print(f"[bench] plan: {plan_info}", file=sys.stderr, flush=True)
-        paths["fp64"] = (plan.launch, plan.out)
-        precs = ["fp64"]
+    if cfg == 5 and args.only in ("both", "fp64", "mixed"):
+        # 10^6 locations: each precision as one tuned, graph-captured plan
+        precs = ["fp64", "mixed"] if args.only == "both" else [args.only]
+        plans5 = {}
+        for prec in precs:
+            plans5[prec] = lagp.Plan(X, Y, XX, n0, n, Np, d, g, precision=prec)
+            print(f"[bench] plan {prec}: {plans5[prec].describe()}", file=sys.stderr, flush=True)
+            paths[prec] = (plans5[prec].launch, plans5[prec].out)
+        plan_info = plans5[precs[0]].describe()
     elif cfg == 3:
         # one autotuned, graph-captured plan (built and tuned before the timed region)
         n_per, Np_per = torch.from_numpy(W.n_per).to(dev), torch.from_numpy(W.Np_per).to(dev)
@@ -251,14 +255,16 @@ def main() -> int:
     o = paths[precs[0]][1]
     pool = o["pool"]
     # the NN variant the step runs: plans may use the grid-pruned pools
-    nngrid = plan_info is not None and ("chosen" not in plan_info or "nn grid" in plan_info.split("chosen")[-1])
+    chosen = plan_info.split("chosen")[-1] if plan_info else ""
+    nngrid = plan_info is not None and ("chosen" not in plan_info or "nn grid" in chosen)
+    group = 4 if "nn grid g=4" in chosen else 2 if "nn grid g=2" in chosen else 1
     nnws = None
     if nngrid:
         nbytes = ctypes.c_size_t(0)
         lagp._lib.check(lagp._lib.load().lagp_nn_pool_workspace(W.N, W.p, M, ctypes.byref(nbytes)))
         nnws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
-    kms = {"nn_pool" + ("_grid" if nngrid else ""): timer.run(
-        lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, grid=nngrid, workspace=nnws), args.steps)}
+    kms = {"nn_pool" + ("_grid" if nngrid else "") + (f"_g{group}" if group > 1 else ""): timer.run(
+        lambda: lagp.nn_pool(X, XX, pool.shape[1], out=pool, grid=nngrid, workspace=nnws, group=group), args.steps)}
     if cfg == 3:
         kms["alc_fp64_uneven"] = timer.run(
             lambda: lagp.alc_uneven_from_pool(X, Y, XX, pool, n0, n, d, g, n_per=n_per, Np_per=Np_per,
@@ -321,24 +327,25 @@ def main() -> int:
     guard = oh["guard"].cpu().numpy() if "guard" in oh else np.zeros(M)
 
     cpu = None
+    ref = None  # the oracle's own results on the cpu_baseline sample
     if not args.no_cpu_baseline:
         import oracle
 
-        S = min(args.cpu_sample, M)
+        S = min(args.cpu_sample or {1: 100, 2: 8192, 3: 4096, 4: 8192, 5: 2048}[cfg], M)
         orc = oracle.default()
         threads = orc.max_threads()
         t0 = time.perf_counter()
         if cfg == 3:
             pool_h = orc.nn_pool(W.X, W.XX[:S], Np, threads=threads)
-            orc.alc(W.X, W.Y, W.XX[:S], pool_h, n0, n, d, g, n_per=W.n_per[:S], Np_per=W.Np_per[:S],
-                    threads=threads)
+            ref = orc.alc(W.X, W.Y, W.XX[:S], pool_h, n0, n, d, g, n_per=W.n_per[:S], Np_per=W.Np_per[:S],
+                          threads=threads)
             what = "NN pool + ALC design + prediction with per-location n, N'"
         elif cfg == 4:
-            r = orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
-            orc.local_mle(W.X, W.Y, r["sel"], d, g, 1e-3, 5.0, 100)
+            ref = orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
+            orc.local_mle(W.X, W.Y, ref["sel"], d, g, 1e-3, 5.0, 100)
             what = "NN pool + ALC design at d0 + MLE of d"
         else:
-            orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
+            ref = orc.lagp(W.X, W.Y, W.XX[:S], n0, n, Np, d, g, threads=threads)
             what = "NN pool + ALC design + prediction"
         dt = time.perf_counter() - t0
         cpu = dict(value=S / dt, unit="loc/s", cores=threads, kind="oracle",
@@ -346,24 +353,74 @@ def main() -> int:
                           f"locations ({dt:.1f} s wall)")
         print(f"[bench] cpu oracle: {S / dt:.1f} loc/s on {threads} threads", file=sys.stderr, flush=True)
 
+        def oracle_report(o):
+            """Every result of a timed path on this sample against the oracle's
+            own free run: the fraction of identical designs and, where they are
+            identical, the relative errors of mean, s2 and var.  Locations above
+            the 1e-10 float64 bar are re-run by the oracle forced along the same
+            design with its partitioned-inverse route as well, and measured
+            against max(1e-10, 10x the gap between its two routes), as the
+            parity tests do."""
+            if cfg == 4:
+                return None
+            Sr = ref["sel"].shape[0]
+            sel = o["sel"][:Sr].cpu().numpy()
+            same = np.array([np.array_equal(sel[i], ref["sel"][i]) for i in range(Sr)])
+            floor = 1e-6 * float(np.sqrt(np.mean(W.Y ** 2)))
+            out = {"sample": Sr, "same_design_frac": float(same.mean())}
+            rels = {}
+            for k in ("mean", "s2", "var"):
+                a, b = o[k][:Sr].cpu().numpy(), ref[k]
+                rels[k] = np.abs(a - b) / np.maximum(np.abs(b), floor if k == "mean" else 0.0)
+                out[f"{k}_max_rel"] = float(rels[k][same].max()) if same.any() else None
+            above = np.flatnonzero(same & np.any([rels[k] > 1e-10 for k in rels], axis=0))
+            out["above_1e-10"] = int(len(above))
+            worst = 0.0
+            if len(above):
+                kw = dict(n_per=W.n_per[above], Np_per=W.Np_per[above]) if cfg == 3 else {}
+                f = orc.alc(W.X, W.Y, W.XX[above], o["pool"][above].cpu().numpy(), n0, n, d, g,
+                            forced=sel[above], mode_b=True, threads=threads, **kw)
+                for k in rels:
+                    fl = floor if k == "mean" else 0.0
+                    gap = np.abs(f[k + "_b"] - f[k]) / np.maximum(np.abs(f[k]), fl)
+                    worst = max(worst, float(np.max(rels[k][above] / np.maximum(1e-10, 10 * gap))))
+            out["worst_over_route_tol"] = worst
+            return out
+
+        oracle_err = {k: oracle_report(paths[k][1]) for k in precs}
+    else:
+        oracle_err = None
+
     scores = scores_microbench(lagp, torch, timer) if cfg == 2 and not args.no_scores else None
 
-    # mixed-precision error report: every result of the mixed path against the float64 path
-    # (whose designs and outputs are parity-tested against the float64 oracle)
+    # mixed-precision report: the float32 score of each chosen point against its
+    # float64 re-score, the fraction of steps redone in float64, and the errors
+    # against the oracle
     mixed_report = None
-    if "mixed" in res and "fp64" in res:
-        om, of = paths["mixed"][1], paths["fp64"][1]
+    if "mixed" in res:
+        om = paths["mixed"][1]
         a32 = om["alc32"].cpu().numpy()[:, n0:]
         a64 = om["alc"].cpu().numpy()[:, n0:]
         fin = np.isfinite(a32) & (a64 > 0)
-        rel = lambda k: float(np.max((om[k] - of[k]).abs().cpu().numpy()  # noqa: E731
-                                     / np.maximum(of[k].abs().cpu().numpy(), 1e-300)))
         mixed_report = {
-            "same_designs_frac": float((om["sel"] == of["sel"]).all(dim=1).float().mean().item()),
-            "mean_max_rel": rel("mean"), "s2_max_rel": rel("s2"), "var_max_rel": rel("var"),
+            "vs_oracle": oracle_err.get("mixed") if oracle_err else None,
             "alc32_vs_alc64_max_rel": float(np.max(np.abs(a32[fin] - a64[fin]) / a64[fin])) if fin.any() else None,
             "fallback_steps_frac": float(om["guard"].sum().item()) / (M * (n - n0)),
         }
+        if "fp64" in res:
+            of = paths["fp64"][1]
+            mixed_report["same_designs_as_fp64_frac"] = float((om["sel"] == of["sel"]).all(dim=1).float().mean().item())
+
+    # MSPE designs (eq. mspe) on the same workload: the alternative criterion's throughput
+    mspe = None
+    if cfg in (2, 4) and not args.no_mspe and n <= 64 and Np <= 1024:
+        om = {}
+        fn = lambda: lagp.mspe_from_pool(X, Y, XX, pool, n0, n, d, g, out=om)  # noqa: E731
+        fn()
+        ms = timer.run(fn, max(1, min(args.steps, 3)))
+        mspe = {"kernel_ms": ms, "loc_per_s_designs": M / (ms * 1e-3),
+                "status_nonzero": int(np.count_nonzero(om["status"].cpu().numpy()))}
+        print(f"[bench] mspe designs: {ms:.2f} ms ({M / (ms * 1e-3):.1f} loc/s)", file=sys.stderr, flush=True)
 
     metric = "predictive locations/sec (n=50 ALC, N'=1000) mixed vs FP64; ALC evals/sec"
     line = {
@@ -397,6 +454,8 @@ def main() -> int:
         "kernel_ms": kms,
         "guard_steps_frac": float(guard.sum()) / max(1, M * (n - n0)),
         "mixed_error_report": mixed_report,
+        "oracle_error_report": oracle_err,
+        "mspe": mspe,
         "plan": plan_info,
         "status_nonzero": int(np.count_nonzero(st)),
         "roofline": {"kernel": kname, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
