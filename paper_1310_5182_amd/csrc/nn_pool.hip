@@ -13,7 +13,8 @@
 // are appended to the location's LDS buffer.  When a buffer could overflow,
 // an exact radix select on the composite key finds the Np-th smallest key,
 // the buffer is cut to exactly the Np smallest and the threshold becomes that
-// key.  A final bitonic sort of the Np survivors gives the pool in ascending
+// key.  A final bitonic sort of the Np survivors (in registers, lane
+// exchanges within a wave, LDS between waves) gives the pool in ascending
 // (distance, index) order: exact, and independent of scheduling.
 //
 // Float32 error bound.  With u = 2^-24, coordinates bounded by B in
@@ -40,7 +41,11 @@
 // either side) holds no row below it, and since the cells come in order of
 // that distance, the first such chunk ends the stream.  Every row that is
 // streamed goes through the same screen and exact key as above, so the pools
-// are identical to the unpruned ones.  The locations are bucketed into the
+// are identical to the unpruned ones.  In the grid kernel the rows that pass
+// the float32 screen are first gathered into a per-wave list and their exact
+// keys are then computed 64 at a time, so that the float64 arithmetic and the
+// gathers of float64 rows run on full waves rather than on the few lanes of a
+// block that passed.  The locations are bucketed into the
 // same cells, and the workgroups of each XCD (the dispatcher hands out
 // consecutive workgroups to the XCDs in turn) take a contiguous run of them in
 // cell order, so that the workgroups resident on one XCD read mostly the same
@@ -69,7 +74,12 @@ __device__ __forceinline__ bool key_less(uint64_t k1, int32_t i1, uint64_t k2, i
 // Selection scratch, shared by the locations of a workgroup (one select at a time).
 struct NnShared {
     uint32_t hist[256];
-    int16_t holes[kNnMaxNp];
+    // holes of a selection; between selections, the grid kernel's per-wave
+    // lists of the rows that passed the float32 screen in the current chunk
+    union {
+        int16_t holes[kNnMaxNp];
+        int32_t surv[kNnMaxNp / 2];
+    };
     uint64_t wmin[kNnWaves], wmax[kNnWaves];
     int nholes, nmove;
     // radix-select state
@@ -78,9 +88,16 @@ struct NnShared {
     int rank, bin, bin_count;
 };
 
-// Buffer fill and threshold of one location.
+// Buffer fill and threshold of one location.  full[c & 1] is set when an
+// append of chunk c finds the buffer full.  Every thread reads it after the
+// chunk's barrier, and nothing writes it again before the end of chunk c + 1
+// (the flag of chunk c + 1 is the other one, and a selection clears it before
+// its last barrier), so all threads take the same decision even when some of
+// them are already appending rows of chunk c + 1, which moves the count.
 struct NnGroup {
     int count;
+    int full[2];
+    int cut;  // grid kernel: first stream position out of the threshold's reach
     uint64_t thr_k;
     int32_t thr_i;
 };
@@ -223,35 +240,93 @@ __device__ void select_keep(uint64_t *keys, int32_t *idxs, NnShared &S, NnGroup 
     }
     if (tid == 0) {
         grp.count = Np;
+        grp.full[0] = grp.full[1] = 0;
         grp.thr_k = ks;
         grp.thr_i = is;
     }
     __syncthreads();
 }
 
-template <int SORTN>
-__device__ void bitonic_sort(uint64_t *keys, int32_t *idx)
+// Ascending sort of SORTN composite keys, E = SORTN / kNnBlock per thread in
+// registers (thread t holds elements t E .. t E + E - 1), by the bitonic
+// network: steps between elements of one thread in registers, between threads
+// of one wave by lane exchanges (every lane keeps the smaller or the larger of
+// its element and its partner's), between waves through LDS (kv, iv; the first
+// such step waits for every thread to have read what it needs from them).
+// Step (KK, J) compares elements i and i ^ J in blocks of KK; the steps are
+// instantiated one by one so that every register index is a constant.
+template <int SORTN, int KK, int J>
+__device__ __forceinline__ void bitonic_step(uint64_t (&k)[SORTN / kNnBlock], int32_t (&ix)[SORTN / kNnBlock],
+                                             uint64_t *kv, int32_t *iv)
 {
-    for (int k = 2; k <= SORTN; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < SORTN; i += kNnBlock) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const uint64_t ka = keys[i], kb = keys[ixj];
-                    const int32_t ia = idx[i], ib = idx[ixj];
-                    const bool up = (i & k) == 0;
-                    const bool swap = up ? key_less(kb, ib, ka, ia) : key_less(ka, ia, kb, ib);
-                    if (swap) {
-                        keys[i] = kb;
-                        keys[ixj] = ka;
-                        idx[i] = ib;
-                        idx[ixj] = ia;
-                    }
+    constexpr int E = SORTN / kNnBlock;
+    const int tid = threadIdx.x;
+    if constexpr (J < E) {
+#pragma unroll
+        for (int q = 0; q < E; q++) {
+            const int l = q ^ J;
+            if (l > q) {
+                const bool up = ((tid * E + q) & KK) == 0;
+                const bool sw = up ? key_less(k[l], ix[l], k[q], ix[q]) : key_less(k[q], ix[q], k[l], ix[l]);
+                if (sw) {
+                    const uint64_t tk = k[q];
+                    const int32_t tix = ix[q];
+                    k[q] = k[l];
+                    ix[q] = ix[l];
+                    k[l] = tk;
+                    ix[l] = tix;
                 }
             }
+        }
+    } else {
+        uint64_t pk[E];
+        int32_t pi[E];
+        if constexpr (J < kWave * E) {
+            constexpr int lm = J / E;
+#pragma unroll
+            for (int q = 0; q < E; q++) {
+                const uint32_t lo = __shfl_xor((uint32_t)k[q], lm, kWave);
+                const uint32_t hi = __shfl_xor((uint32_t)(k[q] >> 32), lm, kWave);
+                pk[q] = ((uint64_t)hi << 32) | lo;
+                pi[q] = __shfl_xor(ix[q], lm, kWave);
+            }
+        } else {
             __syncthreads();
+#pragma unroll
+            for (int q = 0; q < E; q++) {
+                kv[tid * E + q] = k[q];
+                iv[tid * E + q] = ix[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < E; q++) {
+                pk[q] = kv[(tid * E + q) ^ J];
+                pi[q] = iv[(tid * E + q) ^ J];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < E; q++) {
+            const int i = tid * E + q;
+            const bool keep_min = ((i & J) == 0) == ((i & KK) == 0);
+            const bool pless = key_less(pk[q], pi[q], k[q], ix[q]);
+            if (keep_min == pless) {
+                k[q] = pk[q];
+                ix[q] = pi[q];
+            }
         }
     }
+    if constexpr (J > 1)
+        bitonic_step<SORTN, KK, J / 2>(k, ix, kv, iv);
+    else if constexpr (KK < SORTN)
+        bitonic_step<SORTN, 2 * KK, KK>(k, ix, kv, iv);
+}
+
+template <int SORTN>
+__device__ __forceinline__ void bitonic_sort_regs(uint64_t (&k)[SORTN / kNnBlock], int32_t (&ix)[SORTN / kNnBlock],
+                                                  uint64_t *kv, int32_t *iv)
+{
+    static_assert(SORTN % kNnBlock == 0 && (SORTN & (SORTN - 1)) == 0, "whole elements per thread");
+    bitonic_step<SORTN, 2, 1>(k, ix, kv, iv);
 }
 
 // Ascending sort of n (a power of two <= the buffers) composite keys.
@@ -314,6 +389,7 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
     }
     if (threadIdx.x < G) {
         grp[threadIdx.x].count = 0;
+        grp[threadIdx.x].full[0] = grp[threadIdx.x].full[1] = 0;
         grp[threadIdx.x].thr_k = ~0ull;
         grp[threadIdx.x].thr_i = INT32_MAX;
     }
@@ -334,6 +410,7 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
     constexpr float kConst = 40.0f * PF * kU;
 
     for (int64_t base = 0; base < N; base += kNnChunk) {
+        const int par = (int)((base / kNnChunk) & 1);
         uint64_t tk[G];
         int32_t ti[G];
         float tf[G];
@@ -413,6 +490,7 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
                                 idxs[g][pos] = (int32_t)i;
                             } else {
                                 pend |= 1u << (g * kNnItems + it);
+                                grp[g].full[par] = 1;
                             }
                         }
                     }
@@ -423,11 +501,11 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
         __syncthreads();
         // A full buffer: keep the Np smallest of its CAP keys, then insert the
         // rows that did not fit and still beat the new threshold (at most one
-        // chunk, and CAP >= Np + chunk).  Every thread reads the same count:
-        // it changes only at the end of select_keep, after a barrier.
+        // chunk, and CAP >= Np + chunk).  The decision reads this chunk's flag,
+        // the same for every thread (the count may already be moving).
 #pragma unroll 1
         for (int g = 0; g < G; g++) {
-            if (grp[g].count > CAP) {
+            if (grp[g].full[par]) {
                 select_keep(keys[g], idxs[g], S, grp[g], CAP, Np);
                 const uint64_t nk = grp[g].thr_k;
                 const int32_t ni = grp[g].thr_i;
@@ -451,13 +529,21 @@ __global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(nn_wav
 #pragma unroll 1
     for (int g = 0; g < ng; g++) {
         if (grp[g].count > Np) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
-        for (int i = Np + threadIdx.x; i < SORTN; i += kNnBlock) {
-            keys[g][i] = ~0ull;
-            idxs[g][i] = INT32_MAX;
+        constexpr int E = SORTN / kNnBlock;
+        uint64_t kr[E];
+        int32_t ir[E];
+#pragma unroll
+        for (int qq = 0; qq < E; qq++) {
+            const int e = threadIdx.x * E + qq;
+            kr[qq] = e < Np ? keys[g][e] : ~0ull;
+            ir[qq] = e < Np ? idxs[g][e] : INT32_MAX;
         }
-        __syncthreads();
-        bitonic_sort<SORTN>(keys[g], idxs[g]);
-        for (int r = threadIdx.x; r < Np; r += kNnBlock) pool[(m0 + g) * Np + r] = idxs[g][r];
+        bitonic_sort_regs<SORTN>(kr, ir, keys[g], idxs[g]);
+#pragma unroll
+        for (int qq = 0; qq < E; qq++) {
+            const int e = threadIdx.x * E + qq;
+            if (e < Np) pool[(m0 + g) * Np + e] = ir[qq];
+        }
         __syncthreads();
     }
 }
@@ -765,34 +851,161 @@ __device__ __forceinline__ int rank_from(const int32_t *pre, int r0, int64_t v)
     return r0;
 }
 
+// A non-negative float kept in 16 bits, its top half (truncation toward zero):
+// a lower bound of the value, +inf for +inf.
+__device__ __forceinline__ uint16_t f16_down(float f)
+{
+    return (uint16_t)(__builtin_bit_cast(uint32_t, f) >> 16);
+}
+__device__ __forceinline__ float f16_value(uint16_t h)
+{
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+constexpr double kGridMargin = 1.0 - 1.0 / (1 << 20);
+
+// The first stream position that lies in a cell out of the reach of the
+// threshold distance td: pre[R] for the smallest rank R whose lower bound on
+// the box distance, less the margin, exceeds td (the bounds ascend with the
+// rank), or N = pre[C] if there is none.
+__device__ int grid_cut(const uint16_t *mind, const int32_t *pre, int C, double td)
+{
+    int lo = 0, hi = C;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)f16_value(mind[mid]) * kGridMargin > td)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return pre[lo];
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// The cells of the grid in order of the squared distance from x to their boxes
+// (ties by cell index) for the grid kernel: E ranks per thread (thread t gets
+// ranks t E .. t E + E - 1, C <= E kNnBlock), sorted in registers with the
+// entries past C padded by the largest key; then the lower bound of each
+// cell's distance (mindr), the rows before it in rank order (pre, with
+// pre[C] = N) and its row offset (rbase).  kv, iv: LDS scratch of E kNnBlock
+// entries for the sort; hist: kNnBlock words for the scan; box, off: the
+// grid's cell bounds and row offsets.
+template <int E, int PF>
+__device__ __forceinline__ void grid_rank_cells(const double *box, const int32_t *off, const double *xs, int C,
+                                                int64_t N, uint64_t *kv, int32_t *iv, uint32_t *hist, int32_t *pre,
+                                                int32_t *rbase, uint16_t *mindr)
+{
+    static_assert((E == 1 || E == 2 || E == 4) && 4 * kNnBlock >= kGridCmax, "up to four ranks per thread");
+    const int tid = threadIdx.x;
+    uint64_t kr[E];
+    int32_t cr[E];
+#pragma unroll
+    for (int qq = 0; qq < E; qq++) {
+        const int c = tid * E + qq;
+        kr[qq] = ~0ull;
+        cr[qq] = c;
+        if (c < C) {
+            double sd = 0.0;
+#pragma unroll
+            for (int k = 0; k < PF; k++) {
+                const double lo = box[((size_t)c * PF + k) * 2], hi = box[((size_t)c * PF + k) * 2 + 1];
+                const double gap = fmax(fmax(lo - xs[k], xs[k] - hi), 0.0);
+                sd = fma(gap, gap, sd);
+            }
+            kr[qq] = __builtin_bit_cast(uint64_t, sd);  // >= 0 (or NaN for a NaN location: after the others)
+        }
+    }
+    bitonic_sort_regs<E * kNnBlock>(kr, cr, kv, iv);
+    int32_t csum[E], coff[E], tot = 0;
+#pragma unroll
+    for (int qq = 0; qq < E; qq++) {
+        const int r = tid * E + qq;
+        csum[qq] = 0;
+        coff[qq] = 0;
+        if (r < C) {
+            const int c = cr[qq];
+            const double md = __builtin_bit_cast(double, kr[qq]);
+            float f = (float)md;  // rounded down to a float below md
+            if (!(md >= 0.0)) f = INFINITY;
+            else if ((double)f > md) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) - 1u);
+            mindr[r] = f16_down(f);
+            coff[qq] = off[c];
+            csum[qq] = off[c + 1] - coff[qq];
+        }
+        tot += csum[qq];
+    }
+    // exclusive scan of the cell sizes in rank order: pre[r]
+    hist[tid] = (uint32_t)tot;
+    __syncthreads();
+    for (int o = 1; o < kNnBlock; o <<= 1) {
+        const uint32_t add = tid >= o ? hist[tid - o] : 0u;
+        __syncthreads();
+        hist[tid] += add;
+        __syncthreads();
+    }
+    int32_t run = (int32_t)hist[tid] - tot;
+#pragma unroll
+    for (int qq = 0; qq < E; qq++) {
+        const int r = tid * E + qq;
+        if (r < C) {
+            pre[r] = run;
+            rbase[r] = coff[qq] - run;
+        }
+        run += csum[qq];
+    }
+    if (tid == 0) pre[C] = (int32_t)N;
+    __syncthreads();
+}
+
 // One location per workgroup, rows streamed cell by cell (nearest first).
+//
+// Stream position v (0 <= v < N) is row v + rbase[r] of the bucketed design,
+// where r is the rank of the cell with pre[r] <= v < pre[r + 1].  A chunk is
+// kNnChunk positions; wave w takes kNnItems blocks of 64 consecutive positions
+// from it.  Each wave keeps a cursor on the cell of its current block (its
+// positions only grow), so a block inside one cell costs one add per lane;
+// lanes of a block that crosses into later cells walk pre[] on their own.
+// Since the box bounds ascend with the rank, every position below `cut` is in
+// a cell within reach of the threshold and every position from `cut` on is
+// not: the stream ends at the first chunk that starts at or past it.  Rows
+// that pass the float32 screen go to a per-wave list, and the exact keys are
+// then computed for the list, 64 rows at a time, so that the float64 work and
+// its gathers run on full waves; a wave appends its new keys with one atomic.
 template <int CAP, int SORTN, int PF>
 __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restrict__ X, int64_t N,
                                                            const double *__restrict__ XX, int64_t M, int Np,
                                                            int32_t *__restrict__ pool, NnGrid gr)
 {
     static_assert(CAP >= SORTN + kNnChunk && CAP >= kGridCmax, "room for one chunk above the kept set");
+    static_assert(kNnWaves * kNnItems * kWave <= kNnMaxNp / 2, "the survivor lists fit in the holes' space");
+    static_assert(kNnItems <= 32, "pending bits in one word");
     constexpr int p = PF;
     constexpr float kU = 5.9604645e-8f;  // 2^-24
-    constexpr double kMargin = 1.0 - 1.0 / (1 << 20);
     __shared__ uint64_t keys[CAP];
     __shared__ int32_t idxs[CAP];
     __shared__ double xs[PF];
     __shared__ NnGroup grp;
     __shared__ NnShared S;
     __shared__ int32_t pre[kGridCmax + 1];  // rows in the cells of rank < r
-    __shared__ int16_t cellr[kGridCmax];    // cell of rank r (nearest first)
-    __shared__ float mindr[kGridCmax];      // <= squared distance from x to the box of that cell
+    __shared__ int32_t rbase[kGridCmax];    // first row of the cell of rank r (nearest first), less pre[r]
+    __shared__ uint16_t mindr[kGridCmax];   // <= squared distance from x to the box of that cell
 
     const int tid = threadIdx.x, C = gr.C;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & (kWave - 1);
     // the XCD of this workgroup (blockIdx.x mod 8) takes the slots
     // [x q, (x + 1) q) of the locations in cell order; the grid is 8 q wide
-    const int64_t q = (M + 7) / 8, slot = (int64_t)(blockIdx.x & 7) * q + (blockIdx.x >> 3);
+    const int64_t q8 = (M + 7) / 8, slot = (int64_t)(blockIdx.x & 7) * q8 + (blockIdx.x >> 3);
     if (slot >= M) return;  // the whole workgroup, before any barrier
     const int64_t m = gr.lperm[slot];
     if (tid < PF) xs[tid] = XX[m * p + tid];
     if (tid == 0) {
         grp.count = 0;
+        grp.full[0] = grp.full[1] = 0;
+        grp.cut = (int)N;  // no threshold yet: every cell is in reach
         grp.thr_k = ~0ull;
         grp.thr_i = INT32_MAX;
     }
@@ -822,139 +1035,135 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
     const float cB = kConst * bB * bB;
 
     // ---- cells in order of the squared distance from x to their boxes
-    for (int c = tid; c < C; c += kNnBlock) {
-        double sd = 0.0;
-#pragma unroll
-        for (int k = 0; k < PF; k++) {
-            const double lo = gr.box[((size_t)c * p + k) * 2], hi = gr.box[((size_t)c * p + k) * 2 + 1];
-            const double gap = fmax(fmax(lo - xs[k], xs[k] - hi), 0.0);
-            sd = fma(gap, gap, sd);
-        }
-        keys[c] = __builtin_bit_cast(uint64_t, sd);  // >= 0 (or NaN for a NaN location: last)
-        idxs[c] = c;
-    }
-    __syncthreads();
-    bitonic_sort_n(keys, idxs, C);
-    int32_t csum[4], tot = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int r = 4 * tid + q;
-        csum[q] = 0;
-        if (r < C) {
-            const int c = idxs[r];
-            cellr[r] = (int16_t)c;
-            const double md = __builtin_bit_cast(double, keys[r]);
-            float f = (float)md;  // rounded down to a float below md
-            if (!(md >= 0.0)) f = INFINITY;
-            else if ((double)f > md) f = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) - 1u);
-            mindr[r] = f;
-            csum[q] = gr.off[c + 1] - gr.off[c];
-        }
-        tot += csum[q];
-    }
-    // exclusive scan of the cell sizes in rank order: pre[r]
-    S.hist[tid] = (uint32_t)tot;
-    __syncthreads();
-    for (int o = 1; o < kNnBlock; o <<= 1) {
-        const uint32_t add = tid >= o ? S.hist[tid - o] : 0u;
-        __syncthreads();
-        S.hist[tid] += add;
-        __syncthreads();
-    }
-    int32_t run = (int32_t)S.hist[tid] - tot;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int r = 4 * tid + q;
-        if (r < C) pre[r] = run;
-        run += csum[q];
-    }
-    if (tid == 0) pre[C] = (int32_t)N;
-    __syncthreads();
+    if (C <= kNnBlock)
+        grid_rank_cells<1, PF>(gr.box, gr.off, xs, C, N, keys, idxs, S.hist, pre, rbase, mindr);
+    else if (C <= 2 * kNnBlock)
+        grid_rank_cells<2, PF>(gr.box, gr.off, xs, C, N, keys, idxs, S.hist, pre, rbase, mindr);
+    else
+        grid_rank_cells<4, PF>(gr.box, gr.off, xs, C, N, keys, idxs, S.hist, pre, rbase, mindr);
 
     // ---- the rows, nearest cell first
-    int rc = 0;  // rank of the cell that holds row vb
+    int32_t *surv = S.surv + w * (kNnItems * kWave);  // this wave's list
+    int cr = 0;                                        // this wave's cursor: a cell rank,
+    int cend = __builtin_amdgcn_readfirstlane(pre[1]);  // the position where that cell ends,
+    int cbase = __builtin_amdgcn_readfirstlane(rbase[0]);  // and its row offset
     for (int64_t vb = 0; vb < N; vb += kNnChunk) {
+        const int par = (int)((vb / kNnChunk) & 1);
         const uint64_t tk = grp.thr_k;
         const int32_t ti = grp.thr_i;
+        const int cut = __builtin_amdgcn_readfirstlane(grp.cut);
+        if (vb >= cut) break;
         const double td = tk == ~0ull ? INFINITY : __builtin_bit_cast(double, tk);
         float tf;
         {
             const float f = (float)td;
             tf = (double)f < td ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
         }
-        // every remaining cell is at least as far as the one holding row vb
-        rc = rank_from(pre, rc, vb);
-        if ((double)mindr[rc] * kMargin > td) break;
-        int r = rc;  // the items' rows come in increasing order
-        uint32_t pend = 0;
-        // two items at a time: both cell offsets, then both rows, in flight
-        // together (an item past the design or in a pruned cell reads row 0
-        // and is not used)
+        // screen: bit it of okm is set if the lane's row of block it passed
+        uint32_t okm = 0;
+        int32_t rowi[kNnItems];
         constexpr int kB = PF <= kNnBatchPmax ? 4 : 1;
 #pragma unroll
         for (int it0 = 0; it0 < kNnItems; it0 += kB) {
-        bool use[kB];
-        int64_t rowb[kB];
+            int nval[kB];
 #pragma unroll
-        for (int b = 0; b < kB; b++) {
-            const int64_t v = vb + (it0 + b) * kNnBlock + tid;
-            const int64_t vc = v < N ? v : N - 1;
-            r = rank_from(pre, r, vc);
-            use[b] = v < N && (double)mindr[r] * kMargin <= td;
-            rowb[b] = gr.off[cellr[r]] + (vc - pre[r]);
-        }
-        float xb[kB][PF];
-#pragma unroll
-        for (int b = 0; b < kB; b++) {
-            const int64_t row = use[b] ? rowb[b] : 0;
-#pragma unroll
-            for (int k = 0; k < PF; k++) xb[b][k] = gr.x32[row * PF + k];
-        }
-#pragma unroll
-        for (int b = 0; b < kB; b++) {
-            const int it = it0 + b;
-            {
-                if (use[b]) {
-                    const int64_t row = rowb[b];
-                    float xrf[PF];
-#pragma unroll
-                    for (int k = 0; k < PF; k++) xrf[k] = xb[b][k];
-                    float d32 = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < PF; k++) {
-                        const float t = xrf[k] - xf[k];
-                        d32 = fmaf(t, t, d32);
+            for (int b = 0; b < kB; b++) {
+                const int64_t vi = vb + (int64_t)(w * kNnItems + it0 + b) * kWave;  // the block's first position
+                const int64_t nv = (int64_t)cut - vi;
+                nval[b] = (int)(nv < 0 ? 0 : nv > kWave ? kWave : nv);  // its positions in reach (and < N)
+                int row = 0;
+                if (nval[b] > 0) {
+                    while (vi >= cend) {  // wave-uniform: move the cursor to the block's first cell
+                        cr++;
+                        cend = __builtin_amdgcn_readfirstlane(pre[cr + 1]);
+                        cbase = __builtin_amdgcn_readfirstlane(rbase[cr]);
                     }
-                    if (d32 * kSlope - cB < tf) {
-                        const int32_t i = gr.perm[row];
-                        const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
-                        const uint64_t key = __builtin_bit_cast(uint64_t, sd);
-                        if (key_less(key, i, tk, ti)) {
-                            const int pos = atomicAdd(&grp.count, 1);
-                            if (pos < CAP) {
-                                keys[pos] = key;
-                                idxs[pos] = i;
-                            } else {
-                                pend |= 1u << it;
-                            }
+                    if (lane < nval[b]) {
+                        const int v = (int)vi + lane;
+                        int rb = cbase;
+                        if (v >= cend) {  // past the cursor's cell: this lane's own walk
+                            int r = cr + 1;
+                            while (v >= pre[r + 1]) r++;
+                            rb = rbase[r];
                         }
+                        row = v + rb;
+                    }
+                }
+                rowi[it0 + b] = row;
+            }
+            float xb[kB][PF];
+#pragma unroll
+            for (int b = 0; b < kB; b++) {
+#pragma unroll
+                for (int k = 0; k < PF; k++) xb[b][k] = gr.x32[(int64_t)rowi[it0 + b] * PF + k];
+            }
+#pragma unroll
+            for (int b = 0; b < kB; b++) {
+                float d32 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < PF; k++) {
+                    const float t = xb[b][k] - xf[k];
+                    d32 = fmaf(t, t, d32);
+                }
+                if (lane < nval[b] && d32 * kSlope - cB < tf) okm |= 1u << (it0 + b);
+            }
+        }
+        // this wave's list of the rows that passed
+        int ns = 0;
+#pragma unroll
+        for (int it = 0; it < kNnItems; it++) {
+            const bool ok = (okm >> it) & 1u;
+            const uint64_t bal = __ballot(ok);
+            if (ok) surv[ns + lanes_below(bal)] = rowi[it];
+            ns += __popcll(bal);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // exact keys of the list, 64 at a time; keys below the threshold are appended
+        uint32_t pend = 0;
+        int32_t iq[kNnItems];
+#pragma unroll
+        for (int qq = 0; qq < kNnItems; qq++) {
+            iq[qq] = 0;
+            if (qq * kWave >= ns) continue;
+            const int j = qq * kWave + lane;
+            bool app = false;
+            uint64_t key = 0;
+            if (j < ns) {
+                const int32_t i = gr.perm[surv[j]];
+                iq[qq] = i;
+                const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
+                key = __builtin_bit_cast(uint64_t, sd);
+                app = key_less(key, i, tk, ti);
+            }
+            const uint64_t am = __ballot(app);
+            if (am) {
+                const int lead = (int)__builtin_ctzll(am);
+                int base = 0;
+                if (lane == lead) base = atomicAdd(&grp.count, __popcll(am));
+                base = __shfl(base, lead, kWave);
+                if (app) {
+                    const int pos = base + lanes_below(am);
+                    if (pos < CAP) {
+                        keys[pos] = key;
+                        idxs[pos] = iq[qq];
+                    } else {
+                        pend |= 1u << qq;
+                        grp.full[par] = 1;
                     }
                 }
             }
         }
-        }
         __syncthreads();
-        // a full buffer: as in nn_pool_kernel (the count changes only after a barrier)
-        if (grp.count > CAP) {
+        // a full buffer: as in nn_pool_kernel (the decision reads the chunk's flag)
+        if (grp.full[par]) {
             select_keep(keys, idxs, S, grp, CAP, Np);
             const uint64_t nk = grp.thr_k;
             const int32_t ni = grp.thr_i;
+            if (tid == 0) grp.cut = grid_cut(mindr, pre, C, __builtin_bit_cast(double, nk));
 #pragma unroll
-            for (int it = 0; it < kNnItems; it++) {
-                if ((pend >> it) & 1u) {
-                    const int64_t v = vb + it * kNnBlock + tid;
-                    const int rr = rank_from(pre, rc, v);
-                    const int32_t i = gr.perm[gr.off[cellr[rr]] + (v - pre[rr])];
+            for (int qq = 0; qq < kNnItems; qq++) {
+                if ((pend >> qq) & 1u) {
+                    const int32_t i = iq[qq];
                     const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
                     const uint64_t key = __builtin_bit_cast(uint64_t, sd);
                     if (key_less(key, i, nk, ni)) {
@@ -968,13 +1177,21 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
         }
     }
     if (grp.count > Np) select_keep(keys, idxs, S, grp, grp.count, Np);
-    for (int i = Np + tid; i < SORTN; i += kNnBlock) {
-        keys[i] = ~0ull;
-        idxs[i] = INT32_MAX;
+    constexpr int E = SORTN / kNnBlock;
+    uint64_t kr[E];
+    int32_t ir[E];
+#pragma unroll
+    for (int qq = 0; qq < E; qq++) {
+        const int e = tid * E + qq;
+        kr[qq] = e < Np ? keys[e] : ~0ull;
+        ir[qq] = e < Np ? idxs[e] : INT32_MAX;
     }
-    __syncthreads();
-    bitonic_sort<SORTN>(keys, idxs);
-    for (int r = tid; r < Np; r += kNnBlock) pool[m * Np + r] = idxs[r];
+    bitonic_sort_regs<SORTN>(kr, ir, keys, idxs);
+#pragma unroll
+    for (int qq = 0; qq < E; qq++) {
+        const int e = tid * E + qq;
+        if (e < Np) pool[m * Np + e] = ir[qq];
+    }
 }
 
 // G locations per workgroup, consecutive in cell order (so mostly of one
@@ -1020,6 +1237,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *_
     }
     if (tid < G) {
         grp[tid].count = 0;
+        grp[tid].full[0] = grp[tid].full[1] = 0;
         grp[tid].thr_k = ~0ull;
         grp[tid].thr_i = INT32_MAX;
     }
@@ -1116,6 +1334,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *_
     // ---- the rows, cell by cell
     int rc = 0;  // rank of the cell that holds row vb
     for (int64_t vb = 0; vb < N; vb += kNnChunk) {
+        const int par = (int)((vb / kNnChunk) & 1);
         uint64_t tk[G];
         int32_t ti[G];
         double td[G];
@@ -1196,6 +1415,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *_
                                 idxs[g][pos] = i;
                             } else {
                                 pend |= 1u << (g * kNnItems + it);
+                                grp[g].full[par] = 1;
                             }
                         }
                     }
@@ -1206,7 +1426,7 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *_
         // a full buffer: as in nn_pool_kernel, location by location
 #pragma unroll 1
         for (int g = 0; g < G; g++) {
-            if (grp[g].count > CAP) {
+            if (grp[g].full[par]) {
                 select_keep(keys[g], idxs[g], S, grp[g], CAP, Np);
                 const uint64_t nk = grp[g].thr_k;
                 const int32_t ni = grp[g].thr_i;
@@ -1232,13 +1452,21 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_group_kernel(const double *_
 #pragma unroll 1
     for (int g = 0; g < ng; g++) {
         if (grp[g].count > Np) select_keep(keys[g], idxs[g], S, grp[g], grp[g].count, Np);
-        for (int i = Np + tid; i < SORTN; i += kNnBlock) {
-            keys[g][i] = ~0ull;
-            idxs[g][i] = INT32_MAX;
+        constexpr int E = SORTN / kNnBlock;
+        uint64_t kr[E];
+        int32_t ir[E];
+#pragma unroll
+        for (int qq = 0; qq < E; qq++) {
+            const int e = tid * E + qq;
+            kr[qq] = e < Np ? keys[g][e] : ~0ull;
+            ir[qq] = e < Np ? idxs[g][e] : INT32_MAX;
         }
-        __syncthreads();
-        bitonic_sort<SORTN>(keys[g], idxs[g]);
-        for (int r = tid; r < Np; r += kNnBlock) pool[mloc[g] * Np + r] = idxs[g][r];
+        bitonic_sort_regs<SORTN>(kr, ir, keys[g], idxs[g]);
+#pragma unroll
+        for (int qq = 0; qq < E; qq++) {
+            const int e = tid * E + qq;
+            if (e < Np) pool[mloc[g] * Np + e] = ir[qq];
+        }
         __syncthreads();
     }
 }
