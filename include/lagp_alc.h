@@ -123,16 +123,16 @@ lagp_status lagp_nn_pool_grouped(const double *X, int64_t N, int32_t p, const do
  * lagp_nn_pool_static -- lagp_nn_pool_ws without caller workspace, for
  *   callers that cannot allocate device memory (code under stream capture,
  *   serving loops that forbid allocation).  The grid-pruned pools are built
- *   in a static device array of LAGP_NN_STATIC_SCRATCH_BYTES (64 MiB) that
+ *   in a static device array of LAGP_NN_STATIC_SCRATCH_BYTES (128 MiB) that
  *   the library holds on each GPU it runs on until the process ends; the call
  *   itself allocates nothing.  Same arguments and pools as lagp_nn_pool_ws;
  *   LAGP_EWORKSPACE if lagp_nn_pool_workspace(N, p, M) exceeds the static
- *   size (at p = 8: about N (4 p + 8) + 8 M bytes, e.g. N = M = 10^6).
+ *   size (about N (12 p + 8) + 8 M bytes: at p = 8, e.g. N = M = 10^6).
  *   Every call on one GPU shares that GPU's array: calls that overlap on one
  *   GPU (different streams, threads) race and must be serialised by the
  *   caller.  The stream must belong to the current device.
  */
-#define LAGP_NN_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define LAGP_NN_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 lagp_status lagp_nn_pool_static(const double *X, int64_t N, int32_t p, const double *XX, int64_t M,
                                 int32_t Np, int32_t *pool, void *stream);
 

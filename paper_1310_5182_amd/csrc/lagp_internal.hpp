@@ -93,7 +93,7 @@ size_t nn_pool_workspace(int64_t N, int p, int64_t M);
 // Allocation-free grid-pruned pools: the same kernels on a file-scope
 // device array of kNnStaticScratch bytes (one copy per GPU, resolved to its
 // device address once per device).
-constexpr size_t kNnStaticScratch = (size_t)64 << 20;
+constexpr size_t kNnStaticScratch = (size_t)128 << 20;
 hipError_t nn_static_scratch(void **ptr);
 // group: locations per workgroup sharing the stream of cells (1, 2 or 4; see
 // nn_grid_groups for what a problem supports).

@@ -33,7 +33,7 @@
 // Grid-pruned pools (with caller workspace).  The design is bucketed once per
 // call into C <= 1024 cells of a regular grid over its bounding box (the bits
 // of the cell index spread over the first dimensions) by a counting sort,
-// which leaves a float32 copy of the rows cell by cell, their design indices,
+// which leaves float32 and float64 copies of the rows cell by cell, their design indices,
 // and the exact float64 bounding box of each cell's rows.  Each location
 // sorts the cells by the squared distance from x to their boxes and streams
 // the rows nearest cell first; a cell whose box is farther than the running
@@ -45,7 +45,8 @@
 // the float32 screen are first gathered into a per-wave list and their exact
 // keys are then computed 64 at a time, so that the float64 arithmetic and the
 // gathers of float64 rows run on full waves rather than on the few lanes of a
-// block that passed.  The locations are bucketed into the
+// block that passed; the float64 row comes from the bucketed copy, loaded
+// beside its design index rather than through it.  The locations are bucketed into the
 // same cells, and the workgroups of each XCD (the dispatcher hands out
 // consecutive workgroups to the XCDs in turn) take a contiguous run of them in
 // cell order, so that the workgroups resident on one XCD read mostly the same
@@ -594,6 +595,7 @@ constexpr int kGridParts = 256;  // workgroups of the bounding-box pass
 
 struct NnGrid {
     float *x32;      // [N x p] float32 rows, cell by cell
+    double *x64;     // [N x p] the same rows in float64
     int32_t *perm;   // [N] design index of each of those rows
     int32_t *cid;    // [N] cell of each design row
     int32_t *cnt;    // [C] rows per cell
@@ -623,7 +625,8 @@ static size_t align256(size_t v)
 
 size_t nn_pool_workspace(int64_t N, int p, int64_t M)
 {
-    return align256((size_t)N * p * 4) + 2 * align256((size_t)N * 4) + 3 * align256((kGridCmax + 1) * 4) +
+    return align256((size_t)N * p * 4) + align256((size_t)N * p * 8) + 2 * align256((size_t)N * 4) +
+           3 * align256((kGridCmax + 1) * 4) +
            align256((size_t)kGridCmax * p * 16) + align256((size_t)(kGridParts + 1) * p * 16) +
            2 * align256((size_t)M * 4) + 3 * align256((kGridCmax + 1) * 4);
 }
@@ -634,6 +637,8 @@ static NnGrid grid_layout(void *ws, int64_t N, int p, int64_t M)
     char *b = (char *)ws;
     g.x32 = (float *)b;
     b += align256((size_t)N * p * 4);
+    g.x64 = (double *)b;
+    b += align256((size_t)N * p * 8);
     g.perm = (int32_t *)b;
     b += align256((size_t)N * 4);
     g.cid = (int32_t *)b;
@@ -807,7 +812,11 @@ __global__ __launch_bounds__(256) void grid_scatter(const double *__restrict__ X
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
         const int pos = atomicAdd(&g.cur[g.cid[i]], 1);
         g.perm[pos] = (int32_t)i;
-        for (int k = 0; k < p; k++) g.x32[(size_t)pos * p + k] = (float)X[i * p + k];
+        for (int k = 0; k < p; k++) {
+            const double v = X[i * p + k];
+            g.x64[(size_t)pos * p + k] = v;
+            g.x32[(size_t)pos * p + k] = (float)v;
+        }
     }
 }
 
@@ -1129,9 +1138,10 @@ __global__ __launch_bounds__(kNnBlock) void nn_grid_kernel(const double *__restr
             bool app = false;
             uint64_t key = 0;
             if (j < ns) {
-                const int32_t i = gr.perm[surv[j]];
+                const int row = surv[j];
+                const int32_t i = gr.perm[row];  // loaded beside the row's float64 copy
                 iq[qq] = i;
-                const double sd = sqdist_strict(X + (int64_t)i * PF, 1, xs, 1, p);
+                const double sd = sqdist_strict(gr.x64 + (int64_t)row * PF, 1, xs, 1, p);
                 key = __builtin_bit_cast(uint64_t, sd);
                 app = key_less(key, i, tk, ti);
             }

@@ -19,7 +19,7 @@ def test_static_size_limit_rejected_before_any_launch():
     N, p, M = (1 << 31) - 1, 8, 1000
     need = ctypes.c_size_t(0)
     assert L.lagp_nn_pool_workspace(N, p, M, ctypes.byref(need)) == 0
-    assert need.value > (64 << 20)
+    assert need.value > (128 << 20)
     rc = L.lagp_nn_pool_static(fake, N, p, fake, M, 100, fake, None)
     assert rc == _lib.LAGP_EWORKSPACE
     assert b"static scratch" in L.lagp_last_error()
