@@ -524,12 +524,12 @@ struct Sched {
 };
 
 // Schedule b: TB threads per location, S pool positions per lane (so pools of
-// up to TB S), ZR factor entries per position in registers.  0-2 are the
-// defaults of the pool-size classes; 3-5 are the alternatives a plan may time
-// against them: the same pools on twice the waves with half the positions per
-// lane (a SIMD then interleaves four waves, or two of eight for 512 threads,
-// over a step's dependent phases, at the price of fewer registers per lane and
-// a longer winner exchange).
+// up to TB S), ZR factor entries per position in registers.  3-5 put the pools
+// of 0-2 on twice the waves with half the positions per lane (a SIMD then
+// interleaves four waves, or two of eight for 512 threads, over a step's
+// dependent phases, at the price of fewer registers per lane and a longer
+// winner exchange).  Each pool-size class has a default (below) and a plan may
+// time the others that hold its pools.
 constexpr int kNumSched = 6;
 constexpr Sched kSched[kNumSched] = {{256, 2, 40},  {512, 2, 40},  {512, 4, 16},
                                      {1024, 1, 40}, {1024, 2, 16}, {512, 1, 40}};
@@ -537,9 +537,11 @@ constexpr Sched kSched[kNumSched] = {{256, 2, 40},  {512, 2, 40},  {512, 4, 16},
 static_assert(kNumSched == kIncSchedules, "schedule count");
 
 // Pool-size classes: class c holds pools of up to kClassCap[c] positions and
-// runs on one schedule, the default below unless a plan chose another.
+// runs on one schedule, the default below unless a plan chose another (the
+// defaults are the plans' choices at the configurations measured: for pools of
+// 1025 to 2048, 1024 x 2 / 16 over 512 x 4 / 16).
 constexpr int kClassCap[kIncClasses] = {256, 512, 1024, 2048};
-constexpr int kDefaultMap[kIncClasses] = {0, 0, 1, 2};
+constexpr int kDefaultMap[kIncClasses] = {0, 0, 1, 4};
 
 __host__ __device__ inline int class_of(int Np)
 {
