@@ -327,15 +327,19 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                     }
             }
             // the chosen point's centred coordinates and squared norm, read while
-            // the winning lane writes its row (rows k >= p read row 0 and weigh
-            // it by zero, so that every load is unconditional)
+            // the winning lane writes its row: lane k < p loads coordinate k and
+            // lane kIncPmax the squared norm, all in one LDS access, and the values
+            // go to scalar registers lane by lane (rather than one round trip per
+            // value); coordinates k >= p are zero
             double xw[kIncPmax];  // wave-uniform: held in scalar registers
+            double qw;
+            {
+                const double *src = lane < p ? cx + lane * CAP + wpos : cq + wpos;
+                const double v = *src;
 #pragma unroll
-            for (int k = 0; k < kIncPmax; k++) {
-                const double v = uniform(cx[(k < p ? k : 0) * CAP + wpos]);
-                xw[k] = k < p ? v : 0.0;
+                for (int k = 0; k < kIncPmax; k++) xw[k] = k < p ? readlane(v, k) : 0.0;
+                qw = readlane(v, kIncPmax);
             }
-            const double qw = uniform(cq[wpos]);
             // K(c, x*) of every slot from centred coordinates, |c - x*|^2 =
             // |c'|^2 + |x*'|^2 - 2 c'.x*', also before the barrier: the distances
             // and exps need only x*, so they hide the winner's row write
@@ -360,13 +364,18 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                 }
                 __syncthreads();
             }
-            // step scalars, wave-uniform (scalar registers)
-            const double ilam = uniform(pub[par][vw][1]);
+            // step scalars, wave-uniform (scalar registers): lanes 1, 2, 3 load
+            // 1 / lambda, w_h and t_j in one LDS access
+            double ilam, wh, tn;
+            {
+                const double v = pub[par][vw][lane < 4 ? lane : 0];
+                ilam = readlane(v, 1);
+                wh = readlane(v, 2);
+                tn = readlane(v, 3);
+            }
             const double *el = zbp;
 
             // ===== (3) z_h and t = L^{-1} Y gain their entry j
-            const double wh = uniform(pub[par][vw][2]);
-            const double tn = uniform(pub[par][vw][3]);
             if (tid == 0) {
                 seldi[j] = j >= n0 ? wdi : red_i[par][vw];
                 // ap1 still holds psi_j = t.t over the first j entries (wave 0):
