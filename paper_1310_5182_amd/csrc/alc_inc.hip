@@ -108,6 +108,28 @@ __device__ __forceinline__ void dot_rowbcast(double (&acc)[S], const double (&lr
     }
 }
 
+// |c - x*|^2 = |c|^2 + |x*|^2 - 2 c . x* for the S pool positions tid + s TB
+// of a lane, from centred coordinates in LDS ([k][pos], K >= p of them read,
+// rows k >= p weighed by x*_k = 0): a slot's loads are all issued before its
+// first product uses one, so that their LDS round trips overlap.
+template <int TB, int S, int CAP, int K>
+__device__ __forceinline__ void sqdist_slots(const double *cx, const double *cq, int tid, int p,
+                                             const double (&xw)[kIncPmax], double qw, double (&r2)[S])
+{
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        double c[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) c[k] = cx[(k < p ? k : 0) * CAP + tid + s * TB];
+        const double q = cq[tid + s * TB];
+        __builtin_amdgcn_sched_barrier(0);
+        double dt = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; k++) dt = fma(c[k], xw[k], dt);
+        r2[s] = fma(-2.0, dt, q + qw);
+    }
+}
+
 // RL: the chosen row l reaches the lanes through DPP row broadcasts from a
 // per-lane copy (no instruction of its own) instead of uniform-address LDS
 // reads (LDS return bandwidth).
@@ -310,7 +332,14 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
             }
             const int wt = wpos % TB, ws = wpos / TB;
             const int vw = wt >> 6;  // the winner's wave
-            const double sstar = uniform(pub[par][vw][0]);
+            // the chosen point's centred coordinates, squared norm and Schur
+            // complement in one LDS access: lane k < p loads coordinate k, lane
+            // kIncPmax the squared norm and lane kIncPmax + 1 the complement s*;
+            // the values go to scalar registers lane by lane (rather than one
+            // round trip per value)
+            const double vch = *(lane < p ? cx + lane * CAP + wpos
+                                          : lane == kIncPmax + 1 ? &pub[par][vw][0] : cq + wpos);
+            const double sstar = readlane(vch, kIncPmax + 1);
             if (!(sstar > 0.0) || !isfinite(sstar)) {
                 status = j < n0 ? kLocInitNotPd : kLocStepFail;
                 break;
@@ -326,42 +355,26 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(2))) void al
                         sv[s] = -1.0;  // retire the chosen slot
                     }
             }
-            // the chosen point's centred coordinates and squared norm, read while
-            // the winning lane writes its row: lane k < p loads coordinate k and
-            // lane kIncPmax the squared norm, all in one LDS access, and the values
-            // go to scalar registers lane by lane (rather than one round trip per
-            // value); coordinates k >= p are zero
-            double xw[kIncPmax];  // wave-uniform: held in scalar registers
-            double qw;
-            {
-                const double *src = lane < p ? cx + lane * CAP + wpos : cq + wpos;
-                const double v = *src;
+            // the chosen point's coordinates (zero from p on) and squared norm,
+            // wave-uniform, from the access above
+            double xw[kIncPmax];
 #pragma unroll
-                for (int k = 0; k < kIncPmax; k++) xw[k] = k < p ? readlane(v, k) : 0.0;
-                qw = readlane(v, kIncPmax);
-            }
+            for (int k = 0; k < kIncPmax; k++) xw[k] = k < p ? readlane(vch, k) : 0.0;
+            const double qw = readlane(vch, kIncPmax);
             // K(c, x*) of every slot from centred coordinates, |c - x*|^2 =
             // |c'|^2 + |x*'|^2 - 2 c'.x*', also before the barrier: the distances
             // and exps need only x*, so they hide the winner's row write
             double kcs[S];
             if (j + 1 < n) {
+                double r2[S];
+                if (p > 4)
+                    sqdist_slots<TB, S, CAP, 8>(cx, cq, tid, p, xw, qw, r2);
+                else if (p > 2)
+                    sqdist_slots<TB, S, CAP, 4>(cx, cq, tid, p, xw, qw, r2);
+                else
+                    sqdist_slots<TB, S, CAP, 2>(cx, cq, tid, p, xw, qw, r2);
 #pragma unroll
-                for (int s = 0; s < S; s++) {
-                    const int pos = tid + s * TB;
-                    double dt = 0.0;
-                    if (p > 4) {
-#pragma unroll
-                        for (int k = 0; k < 8; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                    } else if (p > 2) {
-#pragma unroll
-                        for (int k = 0; k < 4; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 2; k++) dt = fma(cx[(k < p ? k : 0) * CAP + pos], xw[k], dt);
-                    }
-                    const double r2 = fma(-2.0, dt, cq[pos] + qw);
-                    kcs[s] = exp(r2 * nid);
-                }
+                for (int s = 0; s < S; s++) kcs[s] = exp(r2[s] * nid);
                 __syncthreads();
             }
             // step scalars, wave-uniform (scalar registers): lanes 1, 2, 3 load
